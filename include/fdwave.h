@@ -1,0 +1,203 @@
+/*
+ * fdwave.h - C ABI of the MI355X (gfx950) shaped-stencil acoustic wave library.
+ *
+ * The library advances the constant-density acoustic wave equation
+ *     u_tt - c(x)^2 lap(u) = f                        (Peixoto & Silva, Sec. 3.1, eq. wave_eq)
+ * with the explicit leapfrog scheme (Sec. 3.2, eq. time_derivative1) and a
+ * symmetric shaped Laplacian stencil (Sec. 3.2, eq. spacexz_derivative2_sym;
+ * shapes of Sec. 4.1), an absorbing damping band (Sec. 3.1: eta(x) u_t), a
+ * point source and receiver traces (Sec. 5.2).  Per time step n = 0..nt-1:
+ *
+ *     u^{n+1} = b [ 2 u^n - a u^{n-1} + v (W * u^n) + q s^n delta_{x,xs} ]
+ *     trace[n][r] = u^{n+1}(x_r)
+ *
+ * v = (c dt / h)^2 (squared Courant number, Sec. 3.4.1, eq. courant) is formed
+ * once per call in FP64 and rounded to FP32; W * u = sum_d w_d u(x + d) with
+ * u = 0 beyond the shot window; q = dt^2 / h^ndim; a = 1 - eta dt / 2,
+ * b = 1 / (1 + eta dt / 2), eta = eta_max * sum_axes (depth_into_band / nb)^2.
+ * The stencil is evaluated in the centre-free difference form
+ * sum_{d != 0} w_d (u(x + d) - u(x)), which equals W * u whenever the weights
+ * satisfy the zero-sum (r = 0) condition of Sec. 3.3.1, eq. taylor_system_r0;
+ * fd_weights_set enforces that condition.
+ *
+ * Conventions for every entry point:
+ *  - Arrays are row-major with x fastest: 2D [nz][nx], 3D [nz][ny][nx].
+ *    Coordinates are given x first: (x, z) in 2D, (x, y, z) in 3D.
+ *  - [dev] marks a pointer to device memory on the current HIP device.  All
+ *    such memory is allocated and owned by the caller; the library never frees
+ *    it.  [host] marks host memory, read during the call only.
+ *  - Every function returns an fd_status.  Arguments are validated before any
+ *    work is queued; on error nothing is queued and fd_last_error() returns a
+ *    message.  No C++ exception crosses this interface and nothing is printed.
+ *  - Device work is queued asynchronously on `hip_stream` (a hipStream_t, or
+ *    NULL for the null stream) unless a flag below asks for a synchronising
+ *    check.  Caller buffers must stay valid until that work has finished.
+ *  - The library keeps only host-side state: the registered stencils and a
+ *    cache of instantiated HIP graphs.  Scratch memory is the caller's
+ *    `workspace` (size from fd_workspace_bytes, 256-byte aligned).
+ */
+#ifndef FDWAVE_H
+#define FDWAVE_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    FD_OK = 0,
+    FD_EINVAL = 1,        /* invalid argument (sizes, indices, pointers) */
+    FD_EUNSTABLE = 2,     /* weights or time step violate the stability limit */
+    FD_ENOMEM = 3,        /* workspace too small */
+    FD_EDEVICE = 4,       /* a HIP runtime call failed */
+    FD_ENONFINITE = 5,    /* non-finite values found (check_finite) */
+    FD_EUNSUPPORTED = 6   /* valid request this build does not implement */
+} fd_status;
+
+typedef enum {
+    FD_CROSS = 0,    /* |d_i| <= M on one axis only (Sec. 4.1, P = Q = 0) */
+    FD_RHOMBUS = 1,  /* sum |d_i| <= M (Sec. 4.1: Q = floor(M/2), P0(q) = q,
+                        P(q) = M - q); in 3D the L1 ball */
+    FD_SQUARE = 2    /* max |d_i| <= M (Sec. 4.1: Q = M, P0(q) = q, P(q) = M) */
+} fd_shape;
+
+#define FD_MAX_RADIUS 8      /* largest M with compiled kernels */
+#define FD_MAX_ORBITS 64     /* largest number of unique weights per stencil */
+#define FD_MAX_STENCILS 256  /* registered stencils per process */
+
+/*
+ * Unique-weight structure of a stencil (Sec. 4.1, Fig. stencils: one weight
+ * per orbit of the axis-permutation / sign-flip symmetry, Sec. 3.2).
+ * An orbit is named by its representative, the absolute offsets sorted in
+ * descending order; orbits are listed in ascending lexicographic order of
+ * the representative, so orbit 0 is the centre.
+ *   ndim     2 or 3;  shape an fd_shape;  M the radius, 1..FD_MAX_RADIUS
+ *   reps     [host, out, may be NULL] nw*ndim representatives
+ *   counts   [host, out, may be NULL] nw point counts per orbit
+ *   nw       [host, out] number of orbits
+ * Errors: FD_EINVAL for bad ndim/shape/M or nw == NULL.
+ */
+int fd_orbits(int ndim, int shape, int M, int* reps, int* counts, int* nw);
+
+/*
+ * Register a stencil: one FP64 weight per orbit, in fd_orbits order, scaled
+ * so that h^2 lap(u)(x) ~ sum_d w_d u(x + d) (Sec. 3.2).  Checks
+ *   - nw matches fd_orbits (else FD_EINVAL);
+ *   - the zero-sum condition |sum_o count_o w_o| <= 1e-9 sum_o count_o |w_o|
+ *     (Sec. 3.3.1, eq. taylor_system_r0; else FD_EINVAL);
+ *   - the symbol S(k) = sum_d w_d cos(k.d) is <= 0 on a dense sample of the
+ *     Brillouin zone [0, pi]^ndim (else FD_EUNSTABLE: the scheme is unstable
+ *     for every time step, Sec. 3.4.1, eq. full_disp).
+ * Stores the FP32-rounded weights and the FP64 stability limit
+ * C_lim = 2 / sqrt(max_k -S(k)) (largest Courant number with |cos(w dt)| <= 1).
+ *   w           [host] nw weights
+ *   stencil_id  [host, out] handle for fd_shot.stencil_id
+ * Thread-safe.  Registering identical weights again returns the same id.
+ */
+int fd_weights_set(int ndim, int shape, int M, const double* w, int nw, int* stencil_id);
+
+/* FP64 stability limit of a registered stencil ([host, out] c_lim). */
+int fd_cfl_limit(int stencil_id, double* c_lim);
+
+/* The grid, time axis and damping band shared by all shots of a call. */
+typedef struct {
+    int ndim;              /* 2 or 3 */
+    int nt;                /* time steps, >= 1 */
+    long long n[3];        /* model extent along x, y, z; n[1] = 1 in 2D */
+    double h;              /* grid spacing (m), > 0 */
+    double dt;             /* time step (s), > 0 */
+    int nb;                /* damping band width in cells (0: no damping) */
+    double eta_max;        /* peak damping (1/s) at the outer edge of the band, >= 0 */
+    double vmax;           /* maximum velocity used for the stability check */
+    int check_finite;      /* 1: synchronise at the end and return FD_ENONFINITE
+                              if traces hold NaN/Inf, FD_EINVAL if a receiver
+                              coordinate lay outside its window or a velocity
+                              was not positive and finite */
+    int flags;             /* FD_NO_GRAPH | FD_NO_BATCH, 0 for the default path */
+} fd_grid;
+
+/* fd_grid.flags: the plain execution forms, kept as baselines.
+ * FD_NO_GRAPH: queue every kernel launch directly instead of replaying a
+ *              cached HIP graph of the whole call.
+ * FD_NO_BATCH: run the shots of a multi-shot call one after the other with
+ *              the single-shot kernels instead of one batched launch per step. */
+#define FD_NO_GRAPH 1
+#define FD_NO_BATCH 2
+
+/* One shot: a window into the model, its stencil, source and receivers. */
+typedef struct {
+    long long origin[3];     /* window origin in the model (x, y, z) */
+    long long extent[3];     /* window extent (x, y, z); y = 1 in 2D */
+    int stencil_id;          /* from fd_weights_set, same ndim as the grid */
+    int src[3];              /* source node, window coordinates (x, y, z) */
+    const float* wavelet;    /* [dev] nt samples s(n dt) of the source (unscaled) */
+    int nrec;                /* number of receivers, >= 0 */
+    const int* rec;          /* [dev] nrec*ndim window coordinates, x first.
+                                Coordinates outside the window are skipped
+                                (their traces are 0) and flagged (check_finite) */
+    float* traces;           /* [dev, out] nt*nrec: traces[n*nrec + r] = u^{n+1}(rec r) */
+    const float* trace_adj;  /* [dev] fd_adjoint_gradient only: dJ/dtraces, nt*nrec */
+    const float* init_prev;  /* [dev, optional] u^{-1} over the window (NULL: zeros) */
+    const float* init_cur;   /* [dev, optional] u^0 over the window (NULL: zeros) */
+    float* final_prev;       /* [dev, optional out] u^{nt-1} over the window */
+    float* final_cur;        /* [dev, optional out] u^{nt} over the window */
+} fd_shot;
+
+/*
+ * Forward modelling of nshots shots over one velocity model.
+ *   vel        [dev] model-sized velocity c (m/s), all > 0
+ *   shots      [host] nshots descriptors; windows must lie inside the model
+ *   nshots     >= 1.  nshots == 1 runs one per-step kernel launch per step;
+ *              nshots > 1 runs every shot's tiles in one launch per step
+ *              (ragged windows and mixed stencils allowed)
+ *   workspace  [dev] >= fd_workspace_bytes(g, shots, nshots, 0, 0) bytes
+ *   hip_stream hipStream_t to queue on
+ * Stability: vmax * dt / h must not exceed the stencil's C_lim (FD_EUNSTABLE).
+ * The time loop is replayed from a cached HIP graph when the same arguments
+ * are seen again.
+ */
+int fd_forward(const fd_grid* g, const float* vel, const fd_shot* shots, int nshots,
+               void* workspace, size_t ws_bytes, void* hip_stream);
+
+/*
+ * Exact discrete adjoint of fd_forward and the gradient dJ/dc of a scalar
+ * misfit J(traces), given trace_adj = dJ/dtraces for each shot.  The adjoint
+ * field psi runs backwards in time with the forward operator (W is symmetric),
+ *     psi^k = b [ 2 psi^{k+1} - a psi^{k+2} + v (W * psi^{k+1}) + v rho^{k-1} @ x_r ],
+ * k = nt..1, psi^{nt+1} = psi^{nt+2} = 0, and
+ *     dJ/dc(x) += sum_{k=1..nt} (2 / c(x)) psi^k(x) (W * u^{k-1})(x).
+ * The forward field is rebuilt from checkpoints of (u^{k-1}, u^k) taken every
+ * ckpt_every steps and recomputed one segment at a time into the workspace.
+ *   grad        [dev, in/out] model-sized; the gradient of every shot is ADDED
+ *   ckpt_every  segment length K, 1 <= K <= nt
+ * Other arguments as in fd_forward; traces are (re)written too.
+ */
+int fd_adjoint_gradient(const fd_grid* g, const float* vel, const fd_shot* shots, int nshots,
+                        int ckpt_every, float* grad, void* workspace, size_t ws_bytes,
+                        void* hip_stream);
+
+/*
+ * Workspace size in bytes for fd_forward (mode 0) or fd_adjoint_gradient
+ * (mode 1, with segment length ckpt_every).  Returns 0 for invalid input.
+ */
+size_t fd_workspace_bytes(const fd_grid* g, const fd_shot* shots, int nshots, int mode,
+                          int ckpt_every);
+
+/*
+ * Kernel tile configuration used for a stencil: rows per thread along the
+ * marching axis (2D: z; 3D: y) and the z-chunk of the 3D kernels.
+ * fd_set_tile overrides the built-in choice (as found by the autotuner);
+ * rows must be one of 1, 2, 4, 8 and zchunk a multiple of 8 in [8, 512].
+ */
+int fd_set_tile(int stencil_id, int rows, int zchunk);
+int fd_get_tile(int stencil_id, int* rows, int* zchunk);
+
+/* Message for the last non-OK return on this thread ("" if none). */
+const char* fd_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FDWAVE_H */

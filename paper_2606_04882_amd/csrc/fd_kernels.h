@@ -1,0 +1,179 @@
+// Internal declarations shared by the HIP kernels and the host library.
+// Not part of the public ABI (see include/fdwave.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fdw {
+
+enum { SH_CROSS = 0, SH_RHOMBUS = 1, SH_SQUARE = 2 };
+constexpr int kMaxOrbits = 64;
+constexpr int kBlock = 256;   // threads per block: 4 waves of 64
+constexpr int kTileX = 64;    // tile width along x = one wave
+
+// FP32 weights, one per orbit in canonical order (orbit 0, the centre, is
+// never read: the kernels use the centre-free difference form).  wd is the
+// same weights laid out densely by 2D offset group: wd[dx*(M+1) + dz] is the
+// weight of (dx, dz) (0 outside the shape), used by the dense 2D kernels.
+constexpr int kMaxDense = 81;
+struct Weights {
+    float w[kMaxOrbits];
+    float wd[kMaxDense];
+};
+
+// ---------------------------------------------------------------------------
+// Compile-time stencil geometry.  A 2D orbit representative is (p, q) with
+// p >= q >= 0; a 3D one (p, q, r) with p >= q >= r >= 0.  Orbits are ordered
+// lexicographically ascending by representative.
+// ---------------------------------------------------------------------------
+__host__ __device__ constexpr bool in_shape2(int shape, int M, int p, int q) {
+    return shape == SH_CROSS ? (q == 0 && p <= M)
+         : shape == SH_RHOMBUS ? (p + q <= M) : (p <= M);
+}
+
+__host__ __device__ constexpr int orbit2(int shape, int M, int a, int b) {
+    int idx = 0;
+    for (int p = 0; p <= M; ++p)
+        for (int q = 0; q <= p; ++q) {
+            if (p == a && q == b) return idx;
+            if (in_shape2(shape, M, p, q)) ++idx;
+        }
+    return -1;
+}
+
+// index of the orbit containing offset (dx, dz), any signs/order
+__host__ __device__ constexpr int orbit2_of(int shape, int M, int dx, int dz) {
+    int a = dx < 0 ? -dx : dx, b = dz < 0 ? -dz : dz;
+    return a >= b ? orbit2(shape, M, a, b) : orbit2(shape, M, b, a);
+}
+
+// largest |dz| in the shape for a given |dx|
+__host__ __device__ constexpr int maxdz2(int shape, int M, int dx) {
+    return shape == SH_CROSS ? (dx == 0 ? M : 0) : shape == SH_RHOMBUS ? M - dx : M;
+}
+
+__host__ __device__ constexpr bool in_shape3(int shape, int M, int p, int q, int r) {
+    return shape == SH_CROSS ? (q == 0 && r == 0 && p <= M)
+         : shape == SH_RHOMBUS ? (p + q + r <= M) : (p <= M);
+}
+
+__host__ __device__ constexpr int orbit3(int shape, int M, int a, int b, int c) {
+    int idx = 0;
+    for (int p = 0; p <= M; ++p)
+        for (int q = 0; q <= p; ++q)
+            for (int r = 0; r <= q; ++r) {
+                if (p == a && q == b && r == c) return idx;
+                if (in_shape3(shape, M, p, q, r)) ++idx;
+            }
+    return -1;
+}
+
+__host__ __device__ constexpr int cabs_(int x) { return x < 0 ? -x : x; }
+__host__ __device__ constexpr int cmax_(int a, int b) { return a > b ? a : b; }
+__host__ __device__ constexpr int cmin_(int a, int b) { return a < b ? a : b; }
+
+__host__ __device__ constexpr int orbit3_of(int shape, int M, int dx, int dy, int dz) {
+    int a = cabs_(dx), b = cabs_(dy), c = cabs_(dz);
+    int hi = cmax_(a, cmax_(b, c)), lo = cmin_(a, cmin_(b, c));
+    int mid = a + b + c - hi - lo;
+    return orbit3(shape, M, hi, mid, lo);
+}
+
+// ---------------------------------------------------------------------------
+// Block -> tile mapping.  Workgroups are dealt round-robin to the 8 XCDs;
+// remap so that each XCD owns a contiguous run of tiles (neighbouring tiles
+// share halo rows in that XCD's L2).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int xcd_tile(int bid, int ntiles) {
+    const int q = ntiles >> 3, r = ntiles & 7;
+    const int xcd = bid & 7, slot = bid >> 3;
+    return xcd * q + (xcd < r ? xcd : r) + slot;
+}
+
+// Damping factors for a node at band depths (dx, dy, dz) (cells):
+// e = eta_max dt/2 * sum (d/nb)^2, a = 1 - e, b = 1 / (1 + e).
+struct Sponge {
+    int nb;
+    float escale;   // eta_max * dt / 2
+    float inv_nb;   // 1 / nb
+};
+
+__device__ __forceinline__ int band_depth(int i, int n, int nb) {
+    int d = nb - i;
+    int d2 = i - (n - 1 - nb);
+    d = d > d2 ? d : d2;
+    return d > 0 ? d : 0;
+}
+
+// ---------------------------------------------------------------------------
+// Per-step parameters of the single-shot forward kernels.
+// ---------------------------------------------------------------------------
+struct StepArgs {
+    const float* __restrict__ ucur;  // u^n over the window (dense, x fastest)
+    const float* uprev;              // u^{n-1} (may equal unext: in-place update)
+    float* unext;                    // u^{n+1}
+    const float* __restrict__ v;     // model v at the window origin
+    long long ldv_y, ldv_z;          // model strides of v (row, plane)
+    int nx, ny, nz;                  // window extent (ny = 1 in 2D)
+    int tiles_x, tiles_y, ntiles;    // tile grid
+    int zchunk;                      // 3D: planes per block
+    Sponge sp;
+    long long src;                   // source node (linear, window) or -1
+    float q;                         // dt^2 / h^ndim
+    const float* __restrict__ wavelet;
+    int step;                        // n: the source sample s^n drives n -> n+1
+    // receiver gather of u^n (= trace n-1), done by the first threads of the grid
+    int nrec;
+    const long long* __restrict__ rec_lin;
+    float* __restrict__ trace_out;   // traces + (n-1)*nrec, or nullptr
+    Weights w;
+};
+
+// Per-step parameters of the adjoint + gradient kernels.
+struct AdjArgs {
+    const float* __restrict__ pcur;  // psi^{k+1}
+    const float* pprev;              // psi^{k+2} (may equal pnext)
+    float* pnext;                    // psi^k
+    const float* __restrict__ ufwd;  // u^k, paired with psi^{k+1} in the gradient
+    const float* __restrict__ v;     // model v at the window origin
+    float* __restrict__ grad;        // model gradient at the window origin (+=)
+    float gscale;                    // 2 dt / h: 2/c = gscale / sqrt(v)
+    long long ldv_y, ldv_z;
+    int nx, ny, nz;
+    int tiles_x, tiles_y, ntiles;
+    int zchunk;
+    Sponge sp;
+    int with_grad;                   // accumulate (2/c) psi^{k+1} (W u^k) into grad
+    int with_update;                 // write psi^k
+    Weights w;
+};
+
+// Launchers (one per translation unit).  Return false when the requested
+// (shape, M, rows) combination was not compiled.
+bool launch_fwd2d(const StepArgs& a, int shape, int M, int rows, hipStream_t s);
+bool launch_fwd3d(const StepArgs& a, int shape, int M, int rows, hipStream_t s);
+bool launch_adj2d(const AdjArgs& a, int shape, int M, int rows, hipStream_t s);
+bool launch_adj3d(const AdjArgs& a, int shape, int M, int rows, hipStream_t s);
+bool have_fwd2d(int shape, int M, int rows);
+bool have_fwd3d(int shape, int M, int rows);
+
+// Small helper kernels (k_misc.hip).
+void launch_vprep(const float* vel, float* v, long long n, double dt_over_h, int* flags,
+                  hipStream_t s);
+void launch_fill(float* p, long long n, float val, hipStream_t s);
+void launch_fill_i32(int* p, long long n, int val, hipStream_t s);
+void launch_copy(float* dst, const float* src, long long n, hipStream_t s);
+void launch_rec_index(const int* rec, int nrec, int ndim, int nx, int ny, int nz,
+                      long long* lin, int* flags, hipStream_t s);
+void launch_gather(const float* u, const long long* lin, int nrec, float* out, hipStream_t s);
+// psi(x_r) += b(x_r) v(x_r) rho_r at every receiver (atomic: duplicates add up)
+void launch_inject(float* psi, const long long* lin, int nrec, const float* rho, const float* v,
+                   long long ldv_y, long long ldv_z, Sponge sp, int nx, int ny, int nz,
+                   hipStream_t s);
+void launch_check_finite(const float* p, long long n, int* flags, hipStream_t s);
+
+// flags[] slots in the workspace
+enum { FLAG_BAD_REC = 0, FLAG_NONFINITE = 1, FLAG_BAD_VEL = 2, FLAG_COUNT = 4 };
+
+}  // namespace fdw

@@ -1,0 +1,832 @@
+// Host side of the C ABI declared in include/fdwave.h: argument validation,
+// stencil registry (orbits, stability limit), workspace layout, kernel
+// orchestration, HIP-graph cache, and the checkpointed adjoint.
+#include "../../include/fdwave.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <list>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "fd_kernels.h"
+
+using namespace fdw;
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIP_OK(expr)                                                                   \
+    do {                                                                               \
+        hipError_t e_ = (expr);                                                        \
+        if (e_ != hipSuccess)                                                          \
+            return fail(FD_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));    \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// orbits: one weight per orbit of the sign-flip / axis-permutation group
+// (the point symmetry of Sec. 3.2).  Representative = absolute offsets in
+// descending order; orbits in ascending lexicographic order.
+// ---------------------------------------------------------------------------
+struct Orbit {
+    int rep[3];
+    int count;
+};
+
+bool in_shape(int ndim, int shape, int M, int a, int b, int c) {
+    // a >= b >= c >= 0 (c = 0 in 2D)
+    (void)ndim;
+    switch (shape) {
+        case FD_CROSS: return b == 0 && c == 0 && a <= M;
+        case FD_RHOMBUS: return a + b + c <= M;
+        case FD_SQUARE: return a <= M;
+    }
+    return false;
+}
+
+std::vector<Orbit> make_orbits(int ndim, int shape, int M) {
+    std::vector<Orbit> out;
+    for (int a = 0; a <= M; ++a)
+        for (int b = 0; b <= a; ++b)
+            for (int c = 0; c <= (ndim == 3 ? b : 0); ++c) {
+                if (!in_shape(ndim, shape, M, a, b, c)) continue;
+                Orbit o{{a, b, c}, 0};
+                out.push_back(o);
+            }
+    // count points: enumerate the full box
+    auto find = [&](int a, int b, int c) -> int {
+        for (size_t i = 0; i < out.size(); ++i)
+            if (out[i].rep[0] == a && out[i].rep[1] == b && out[i].rep[2] == c) return (int)i;
+        return -1;
+    };
+    const int zr = ndim == 3 ? M : 0;
+    for (int x = -M; x <= M; ++x)
+        for (int y = -M; y <= M; ++y)
+            for (int z = -zr; z <= zr; ++z) {
+                int v[3] = {std::abs(x), std::abs(y), std::abs(z)};
+                std::sort(v, v + 3, [](int p, int q) { return p > q; });
+                int i = find(v[0], v[1], v[2]);
+                if (i >= 0) out[i].count++;
+            }
+    return out;
+}
+
+bool valid_shape(int ndim, int shape, int M) {
+    return (ndim == 2 || ndim == 3) && shape >= FD_CROSS && shape <= FD_SQUARE && M >= 1 &&
+           M <= FD_MAX_RADIUS;
+}
+
+// S(k) = sum_d w_d cos(k.d).  Summing an orbit over sign flips turns
+// cos(k.d) into a product of cosines, so S is a sum over non-negative offset
+// tuples of mult * w * prod_i cos(k_i |d_i|).
+struct Symbol {
+    int ndim, M;
+    std::vector<double> coef;  // [(M+1)^ndim] weight * sign multiplicity per |offset| tuple
+    double eval(const double* k) const {
+        const int n = M + 1;
+        double cx[FD_MAX_RADIUS + 1], cy[FD_MAX_RADIUS + 1], cz[FD_MAX_RADIUS + 1];
+        for (int m = 0; m < n; ++m) {
+            cx[m] = std::cos(k[0] * m);
+            cy[m] = ndim == 3 ? std::cos(k[1] * m) : 1.0;
+            cz[m] = std::cos(k[ndim - 1] * m);
+        }
+        double s = 0.0;
+        if (ndim == 2) {
+            for (int a = 0; a < n; ++a)
+                for (int c = 0; c < n; ++c) s += coef[a * n + c] * cx[a] * cz[c];
+        } else {
+            for (int a = 0; a < n; ++a)
+                for (int b = 0; b < n; ++b)
+                    for (int c = 0; c < n; ++c) s += coef[(a * n + b) * n + c] * cx[a] * cy[b] * cz[c];
+        }
+        return s;
+    }
+};
+
+Symbol make_symbol(int ndim, int shape, int M, const std::vector<Orbit>& orbs,
+                   const double* w) {
+    Symbol S{ndim, M, {}};
+    const int n = M + 1;
+    S.coef.assign(ndim == 2 ? n * n : n * n * n, 0.0);
+    for (int a = 0; a <= M; ++a)
+        for (int b = 0; b <= (ndim == 3 ? M : 0); ++b)
+            for (int c = 0; c <= M; ++c) {
+                int v[3] = {a, b, c};
+                if (ndim == 2) { v[1] = c; v[2] = 0; }
+                int s[3] = {v[0], v[1], v[2]};
+                std::sort(s, s + 3, [](int p, int q) { return p > q; });
+                if (!in_shape(ndim, shape, M, s[0], s[1], s[2])) continue;
+                int oi = -1;
+                for (size_t i = 0; i < orbs.size(); ++i)
+                    if (orbs[i].rep[0] == s[0] && orbs[i].rep[1] == s[1] && orbs[i].rep[2] == s[2])
+                        oi = (int)i;
+                int mult = (a ? 2 : 1) * (c ? 2 : 1) * (ndim == 3 && b ? 2 : 1);
+                int idx = ndim == 2 ? a * n + c : (a * n + b) * n + c;
+                S.coef[idx] += mult * w[oi];
+            }
+    return S;
+}
+
+// max over [0, pi]^ndim of -S and of S: dense sample, then a shrinking
+// pattern search around the best sample.
+void symbol_extrema(const Symbol& S, double* max_neg, double* max_pos) {
+    const int ns = S.ndim == 2 ? 257 : 65;
+    const double h = M_PI / (ns - 1);
+    double best = -1e300, bpos = -1e300;
+    double kbest[3] = {0, 0, 0};
+    double k[3];
+    const int ny = S.ndim == 3 ? ns : 1;
+    for (int i = 0; i < ns; ++i)
+        for (int j = 0; j < ny; ++j)
+            for (int l = 0; l < ns; ++l) {
+                k[0] = i * h;
+                if (S.ndim == 3) { k[1] = j * h; k[2] = l * h; } else { k[1] = l * h; }
+                const double s = S.eval(k);
+                if (-s > best) { best = -s; std::memcpy(kbest, k, sizeof k); }
+                bpos = std::max(bpos, s);
+            }
+    double step = h;
+    for (int it = 0; it < 60; ++it) {
+        bool improved = false;
+        const int nd = S.ndim;
+        int tot = nd == 2 ? 9 : 27;
+        for (int t = 0; t < tot; ++t) {
+            int d[3] = {t % 3 - 1, (t / 3) % 3 - 1, (t / 9) % 3 - 1};
+            double kk[3];
+            for (int q = 0; q < nd; ++q) kk[q] = std::min(M_PI, std::max(0.0, kbest[q] + step * d[q]));
+            const double s = S.eval(kk);
+            if (-s > best) { best = -s; std::memcpy(kbest, kk, sizeof kk); improved = true; }
+        }
+        if (!improved) step *= 0.5;
+    }
+    *max_neg = best;
+    *max_pos = bpos;
+}
+
+// ---------------------------------------------------------------------------
+// stencil registry
+// ---------------------------------------------------------------------------
+struct Stencil {
+    int ndim, shape, M, nw;
+    std::vector<double> w64;
+    Weights w32;
+    double cfl;
+    int rows, zchunk;
+};
+
+std::mutex g_mu;
+std::vector<Stencil> g_stencils;
+
+int default_rows(int ndim, int shape, int M) {
+    (void)shape;
+    (void)M;
+    return ndim == 2 ? 4 : 2;
+}
+
+bool get_stencil(int id, Stencil* out) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (id < 0 || id >= (int)g_stencils.size()) return false;
+    *out = g_stencils[id];
+    return true;
+}
+
+// ---------------------------------------------------------------------------
+// workspace layout
+// ---------------------------------------------------------------------------
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+struct ShotLayout {
+    size_t bufA, bufB, rec;   // forward ping-pong fields, receiver indices
+};
+struct Layout {
+    size_t flags, v;
+    std::vector<ShotLayout> shots;
+    // adjoint scratch (shared by all shots, sized for the largest window)
+    size_t psiA, psiB, ckpt, seg;
+    size_t total;
+};
+
+long long window_points(const fd_shot& s, int ndim) {
+    return s.extent[0] * (ndim == 3 ? s.extent[1] : 1) * s.extent[2];
+}
+
+Layout make_layout(const fd_grid* g, const fd_shot* shots, int nshots, int mode, int K) {
+    Layout L;
+    size_t off = 0;
+    L.flags = off;
+    off += 256;
+    const long long mpts = g->n[0] * (g->ndim == 3 ? g->n[1] : 1) * g->n[2];
+    L.v = off;
+    off = align256(off + sizeof(float) * (size_t)mpts);
+    long long wmax = 0;
+    for (int i = 0; i < nshots; ++i) {
+        const long long wp = window_points(shots[i], g->ndim);
+        wmax = std::max(wmax, wp);
+        ShotLayout s;
+        s.bufA = off;
+        off = align256(off + sizeof(float) * (size_t)wp);
+        s.bufB = off;
+        off = align256(off + sizeof(float) * (size_t)wp);
+        s.rec = off;
+        off = align256(off + sizeof(long long) * (size_t)std::max(shots[i].nrec, 0));
+        L.shots.push_back(s);
+    }
+    L.psiA = L.psiB = L.ckpt = L.seg = 0;
+    if (mode == 1) {
+        const int nseg = (g->nt + K - 1) / K;
+        L.psiA = off;
+        off = align256(off + sizeof(float) * (size_t)wmax);
+        L.psiB = off;
+        off = align256(off + sizeof(float) * (size_t)wmax);
+        L.ckpt = off;
+        off = align256(off + sizeof(float) * (size_t)wmax * 2 * (size_t)nseg);
+        L.seg = off;
+        off = align256(off + sizeof(float) * (size_t)wmax * (size_t)K);
+    }
+    L.total = off;
+    return L;
+}
+
+// ---------------------------------------------------------------------------
+// validation
+// ---------------------------------------------------------------------------
+int check_grid(const fd_grid* g) {
+    if (!g) return fail(FD_EINVAL, "grid is NULL");
+    if (g->ndim != 2 && g->ndim != 3) return fail(FD_EINVAL, "ndim must be 2 or 3 (got %d)", g->ndim);
+    if (g->nt < 1) return fail(FD_EINVAL, "nt must be >= 1 (got %d)", g->nt);
+    if (g->n[0] < 1 || g->n[2] < 1 || (g->ndim == 3 && g->n[1] < 1))
+        return fail(FD_EINVAL, "model extents must be >= 1");
+    if (g->ndim == 2 && g->n[1] != 1) return fail(FD_EINVAL, "2D models need n[1] == 1");
+    if (g->n[0] > (1LL << 30) || g->n[1] > (1LL << 30) || g->n[2] > (1LL << 30))
+        return fail(FD_EINVAL, "model extent too large");
+    if (!(g->h > 0) || !(g->dt > 0) || !std::isfinite(g->h) || !std::isfinite(g->dt))
+        return fail(FD_EINVAL, "h and dt must be positive and finite");
+    if (g->nb < 0) return fail(FD_EINVAL, "nb must be >= 0");
+    if (!(g->eta_max >= 0) || !std::isfinite(g->eta_max)) return fail(FD_EINVAL, "eta_max must be >= 0");
+    if (!(g->vmax > 0) || !std::isfinite(g->vmax)) return fail(FD_EINVAL, "vmax must be positive");
+    return FD_OK;
+}
+
+int check_shot(const fd_grid* g, const fd_shot& s, int i, bool adjoint, Stencil* st) {
+    if (!get_stencil(s.stencil_id, st)) return fail(FD_EINVAL, "shot %d: unknown stencil id %d", i, s.stencil_id);
+    if (st->ndim != g->ndim) return fail(FD_EINVAL, "shot %d: stencil is %dD, grid is %dD", i, st->ndim, g->ndim);
+    for (int a = 0; a < 3; ++a) {
+        if (g->ndim == 2 && a == 1) {
+            if (s.origin[1] != 0 || s.extent[1] != 1) return fail(FD_EINVAL, "shot %d: 2D windows need origin[1]=0, extent[1]=1", i);
+            continue;
+        }
+        if (s.extent[a] < 1 || s.origin[a] < 0 || s.origin[a] + s.extent[a] > g->n[a])
+            return fail(FD_EINVAL, "shot %d: window axis %d [%lld, %lld) outside the model [0, %lld)", i, a,
+                        s.origin[a], s.origin[a] + s.extent[a], g->n[a]);
+    }
+    for (int a = 0; a < 3; ++a) {
+        if (g->ndim == 2 && a == 1) continue;
+        if (s.src[a] < 0 || s.src[a] >= s.extent[a])
+            return fail(FD_EINVAL, "shot %d: source coordinate %d = %d outside the window", i, a, s.src[a]);
+    }
+    if (!s.wavelet) return fail(FD_EINVAL, "shot %d: wavelet is NULL", i);
+    if (s.nrec < 0) return fail(FD_EINVAL, "shot %d: nrec < 0", i);
+    if (s.nrec > 0 && (!s.rec || !s.traces)) return fail(FD_EINVAL, "shot %d: rec/traces NULL with nrec > 0", i);
+    if (adjoint && s.nrec > 0 && !s.trace_adj) return fail(FD_EINVAL, "shot %d: trace_adj is NULL", i);
+    const double courant = g->vmax * g->dt / g->h;
+    if (courant > st->cfl)
+        return fail(FD_EUNSTABLE, "shot %d: Courant number vmax*dt/h = %.6g exceeds the stencil's limit %.6g",
+                    i, courant, st->cfl);
+    const bool have = g->ndim == 2 ? have_fwd2d(st->shape, st->M, st->rows)
+                                   : have_fwd3d(st->shape, st->M, st->rows);
+    if (!have)
+        return fail(FD_EUNSUPPORTED, "shot %d: no compiled %dD kernel for shape %d, M = %d, rows = %d", i,
+                    g->ndim, st->shape, st->M, st->rows);
+    return FD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// graph cache: one instantiated graph per distinct call signature
+// ---------------------------------------------------------------------------
+int g_graph_fallbacks = 0;
+
+struct GraphCache {
+    std::mutex mu;
+    std::list<std::pair<std::vector<uint64_t>, hipGraphExec_t>> lru;
+    std::map<int, hipStream_t> capture_streams;
+    static constexpr size_t kCap = 24;
+} g_graphs;
+
+void key_push(std::vector<uint64_t>& k, const void* p, size_t n) {
+    const unsigned char* c = (const unsigned char*)p;
+    for (size_t i = 0; i < n; i += 8) {
+        uint64_t w = 0;
+        std::memcpy(&w, c + i, std::min<size_t>(8, n - i));
+        k.push_back(w);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// per-call context and the enqueued work
+// ---------------------------------------------------------------------------
+struct ShotCtx {
+    const fd_shot* s;
+    Stencil st;
+    int nx, ny, nz;
+    long long npts;
+    const float* v;   // model v at the window origin
+    float* bufA;
+    float* bufB;
+    long long* rec;
+    long long src;
+};
+
+struct CallCtx {
+    const fd_grid* g;
+    const float* vel;
+    int nshots;
+    std::vector<ShotCtx> shots;
+    Layout L;
+    char* ws;
+    int* flags;
+    float* vfield;
+    long long ldv_y, ldv_z;
+    Sponge sp;
+    float q;
+    // adjoint
+    int K;
+    float* grad;
+};
+
+// offset of a window origin in model-sized arrays
+long long model_offset(const CallCtx& c, const fd_shot& s) {
+    return s.origin[2] * c.ldv_z + s.origin[1] * c.ldv_y + s.origin[0];
+}
+
+void fill_tiles(StepArgs& a, int ndim, int rows, int zchunk) {
+    if (ndim == 2) {
+        a.tiles_x = (a.nx + kTileX - 1) / kTileX;
+        a.tiles_y = 1;
+        const int tz = (a.nz + 4 * rows - 1) / (4 * rows);
+        a.ntiles = a.tiles_x * tz;
+        a.zchunk = 0;
+    } else {
+        a.tiles_x = (a.nx + kTileX - 1) / kTileX;
+        a.tiles_y = (a.ny + 4 * rows - 1) / (4 * rows);
+        const int tz = (a.nz + zchunk - 1) / zchunk;
+        a.ntiles = a.tiles_x * a.tiles_y * tz;
+        a.zchunk = zchunk;
+    }
+}
+
+StepArgs base_step(const CallCtx& c, const ShotCtx& s) {
+    StepArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.v = s.v;
+    a.ldv_y = c.ldv_y;
+    a.ldv_z = c.ldv_z;
+    a.nx = s.nx;
+    a.ny = s.ny;
+    a.nz = s.nz;
+    fill_tiles(a, c.g->ndim, s.st.rows, s.st.zchunk);
+    a.sp = c.sp;
+    a.src = s.src;
+    a.q = c.q;
+    a.wavelet = s.s->wavelet;
+    a.nrec = s.s->nrec;
+    a.rec_lin = s.rec;
+    a.w = s.st.w32;
+    return a;
+}
+
+bool launch_step(const CallCtx& c, const ShotCtx& s, const StepArgs& a, hipStream_t st) {
+    if (c.g->ndim == 2) return launch_fwd2d(a, s.st.shape, s.st.M, s.st.rows, st);
+    return launch_fwd3d(a, s.st.shape, s.st.M, s.st.rows, st);
+}
+
+// forward run of one shot with optional checkpoint saving (ckpt != nullptr:
+// slot j receives (u^{jK-1}, u^{jK})).
+int enqueue_forward_shot(const CallCtx& c, const ShotCtx& s, float* ckpt, int K, hipStream_t st) {
+    const long long n = s.npts;
+    float* prev = s.bufA;
+    float* cur = s.bufB;
+    if (s.s->init_prev) launch_copy(prev, s.s->init_prev, n, st); else launch_fill(prev, n, 0.f, st);
+    if (s.s->init_cur) launch_copy(cur, s.s->init_cur, n, st); else launch_fill(cur, n, 0.f, st);
+    launch_rec_index(s.s->rec, s.s->nrec, c.g->ndim, s.nx, s.ny, s.nz, s.rec, c.flags, st);
+    if (ckpt) {
+        launch_copy(ckpt, prev, n, st);
+        launch_copy(ckpt + n, cur, n, st);
+    }
+    StepArgs a = base_step(c, s);
+    for (int step = 0; step < c.g->nt; ++step) {
+        a.ucur = cur;
+        a.uprev = prev;
+        a.unext = prev;
+        a.step = step;
+        a.trace_out = (step > 0 && s.s->nrec > 0) ? s.s->traces + (size_t)(step - 1) * s.s->nrec : nullptr;
+        if (!launch_step(c, s, a, st)) return fail(FD_EUNSUPPORTED, "kernel not compiled");
+        std::swap(prev, cur);
+        if (ckpt && (step + 1) % K == 0 && step + 1 < c.g->nt) {
+            float* slot = ckpt + (size_t)((step + 1) / K) * 2 * n;
+            launch_copy(slot, prev, n, st);
+            launch_copy(slot + n, cur, n, st);
+        }
+    }
+    if (s.s->nrec > 0)
+        launch_gather(cur, s.rec, s.s->nrec, s.s->traces + (size_t)(c.g->nt - 1) * s.s->nrec, st);
+    if (s.s->final_prev) launch_copy(s.s->final_prev, prev, n, st);
+    if (s.s->final_cur) launch_copy(s.s->final_cur, cur, n, st);
+    if (c.g->check_finite && s.s->nrec > 0)
+        launch_check_finite(s.s->traces, (long long)c.g->nt * s.s->nrec, c.flags, st);
+    return FD_OK;
+}
+
+AdjArgs base_adj(const CallCtx& c, const ShotCtx& s) {
+    AdjArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.v = s.v;
+    a.grad = c.grad + model_offset(c, *s.s);
+    a.gscale = (float)(2.0 * c.g->dt / c.g->h);
+    a.ldv_y = c.ldv_y;
+    a.ldv_z = c.ldv_z;
+    a.nx = s.nx;
+    a.ny = s.ny;
+    a.nz = s.nz;
+    StepArgs t;
+    t.nx = s.nx; t.ny = s.ny; t.nz = s.nz;
+    fill_tiles(t, c.g->ndim, s.st.rows, s.st.zchunk);
+    a.tiles_x = t.tiles_x;
+    a.tiles_y = t.tiles_y;
+    a.ntiles = t.ntiles;
+    a.zchunk = t.zchunk;
+    a.sp = c.sp;
+    a.w = s.st.w32;
+    return a;
+}
+
+bool launch_adj(const CallCtx& c, const ShotCtx& s, const AdjArgs& a, hipStream_t st) {
+    if (c.g->ndim == 2) return launch_adj2d(a, s.st.shape, s.st.M, s.st.rows, st);
+    return launch_adj3d(a, s.st.shape, s.st.M, s.st.rows, st);
+}
+
+// forward with checkpoints, then segment-wise recompute + adjoint, one shot
+int enqueue_adjoint_shot(const CallCtx& c, const ShotCtx& s, hipStream_t st) {
+    const int nt = c.g->nt, K = c.K;
+    const long long n = s.npts;
+    float* ckpt = (float*)(c.ws + c.L.ckpt);
+    float* seg = (float*)(c.ws + c.L.seg);
+    float* pa = (float*)(c.ws + c.L.psiA);
+    float* pb = (float*)(c.ws + c.L.psiB);
+    int rc = enqueue_forward_shot(c, s, ckpt, K, st);
+    if (rc) return rc;
+    launch_fill(pa, n, 0.f, st);   // psi^{nt+1}
+    launch_fill(pb, n, 0.f, st);   // psi^{nt+2}
+    float* pcur = pa;
+    float* pprev = pb;
+    const int nseg = (nt + K - 1) / K;
+    StepArgs f = base_step(c, s);
+    f.trace_out = nullptr;
+    AdjArgs a = base_adj(c, s);
+    for (int j = nseg - 1; j >= 0; --j) {
+        const int s0 = j * K, e0 = std::min(nt, s0 + K);
+        const float* ck_prev = ckpt + (size_t)j * 2 * n;
+        const float* ck_cur = ck_prev + n;
+        // recompute u^{s0+1} .. u^{e0} into seg[0 .. e0-s0-1]
+        for (int step = s0; step < e0; ++step) {
+            const int i = step - s0;
+            f.ucur = i == 0 ? ck_cur : seg + (size_t)(i - 1) * n;
+            f.uprev = i == 0 ? ck_prev : (i == 1 ? ck_cur : seg + (size_t)(i - 2) * n);
+            f.unext = seg + (size_t)i * n;
+            f.step = step;
+            if (!launch_step(c, s, f, st)) return fail(FD_EUNSUPPORTED, "kernel not compiled");
+        }
+        // adjoint iterations k = e0 .. s0+1: psi^k from psi^{k+1}, psi^{k+2};
+        // gradient term (2/c) psi^{k+1} (W u^k) for k < nt
+        for (int k = e0; k > s0; --k) {
+            a.pcur = pcur;
+            a.pprev = pprev;
+            a.pnext = pprev;
+            a.ufwd = seg + (size_t)(k - s0 - 1) * n;
+            a.with_grad = k < nt;
+            a.with_update = 1;
+            if (!launch_adj(c, s, a, st)) return fail(FD_EUNSUPPORTED, "adjoint kernel not compiled");
+            if (s.s->nrec > 0)
+                launch_inject(pprev, s.rec, s.s->nrec, s.s->trace_adj + (size_t)(k - 1) * s.s->nrec, s.v,
+                              c.ldv_y, c.ldv_z, c.sp, s.nx, s.ny, s.nz, st);
+            std::swap(pcur, pprev);
+        }
+    }
+    // last gradient term (2/c) psi^1 (W u^0): non-zero only with initial data
+    if (s.s->init_cur) {
+        a.pcur = pcur;
+        a.pprev = pprev;
+        a.pnext = pprev;
+        a.ufwd = s.s->init_cur;
+        a.with_grad = 1;
+        a.with_update = 0;
+        if (!launch_adj(c, s, a, st)) return fail(FD_EUNSUPPORTED, "adjoint kernel not compiled");
+    }
+    return FD_OK;
+}
+
+int enqueue_call(const CallCtx& c, int mode, hipStream_t st) {
+    launch_fill_i32(c.flags, FLAG_COUNT, 0, st);
+    const long long mpts = c.g->n[0] * (c.g->ndim == 3 ? c.g->n[1] : 1) * c.g->n[2];
+    launch_vprep(c.vel, c.vfield, mpts, c.g->dt / c.g->h, c.flags, st);
+    for (const ShotCtx& s : c.shots) {
+        int rc = mode == 0 ? enqueue_forward_shot(c, s, nullptr, 0, st) : enqueue_adjoint_shot(c, s, st);
+        if (rc) return rc;
+    }
+    return FD_OK;
+}
+
+int get_capture_stream(int dev, hipStream_t* out) {
+    auto it = g_graphs.capture_streams.find(dev);
+    if (it != g_graphs.capture_streams.end()) {
+        *out = it->second;
+        return FD_OK;
+    }
+    hipStream_t s;
+    HIP_OK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    g_graphs.capture_streams[dev] = s;
+    *out = s;
+    return FD_OK;
+}
+
+int run_call(CallCtx& c, int mode, hipStream_t user) {
+    if (c.g->flags & FD_NO_GRAPH) {
+        int rc = enqueue_call(c, mode, user);
+        if (rc) return rc;
+        HIP_OK(hipGetLastError());
+        return FD_OK;
+    }
+    int dev = 0;
+    HIP_OK(hipGetDevice(&dev));
+    std::vector<uint64_t> key;
+    key.push_back((uint64_t)dev);
+    key.push_back((uint64_t)mode);
+    key.push_back((uint64_t)c.K);
+    key.push_back((uint64_t)(uintptr_t)c.grad);
+    key_push(key, c.g, sizeof(fd_grid));
+    key.push_back((uint64_t)(uintptr_t)c.vel);
+    key.push_back((uint64_t)(uintptr_t)c.ws);
+    for (const ShotCtx& s : c.shots) {
+        key_push(key, s.s, sizeof(fd_shot));
+        key.push_back(((uint64_t)s.st.rows << 32) | (uint32_t)s.st.zchunk);
+    }
+    std::lock_guard<std::mutex> lk(g_graphs.mu);
+    hipGraphExec_t exec = nullptr;
+    for (auto it = g_graphs.lru.begin(); it != g_graphs.lru.end(); ++it) {
+        if (it->first == key) {
+            exec = it->second;
+            g_graphs.lru.splice(g_graphs.lru.begin(), g_graphs.lru, it);
+            break;
+        }
+    }
+    if (!exec) {
+        hipStream_t cs;
+        int rc = get_capture_stream(dev, &cs);
+        if (rc) return rc;
+        HIP_OK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+        rc = enqueue_call(c, mode, cs);
+        hipGraph_t graph = nullptr;
+        hipError_t e = hipStreamEndCapture(cs, &graph);
+        if (rc) {
+            if (graph) hipGraphDestroy(graph);
+            return rc;
+        }
+        if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        if (graph) hipGraphDestroy(graph);
+        if (e != hipSuccess) {
+            // capture is an optimisation: queue the same work directly
+            (void)hipGetLastError();
+            g_graph_fallbacks++;
+            rc = enqueue_call(c, mode, user);
+            if (rc) return rc;
+            HIP_OK(hipGetLastError());
+            return FD_OK;
+        }
+        g_graphs.lru.emplace_front(key, exec);
+        while (g_graphs.lru.size() > GraphCache::kCap) {
+            hipGraphExecDestroy(g_graphs.lru.back().second);
+            g_graphs.lru.pop_back();
+        }
+    }
+    HIP_OK(hipGraphLaunch(exec, user));
+    return FD_OK;
+}
+
+int finish_checks(const CallCtx& c, hipStream_t user) {
+    if (!c.g->check_finite) return FD_OK;
+    HIP_OK(hipStreamSynchronize(user));
+    int flags[FLAG_COUNT];
+    HIP_OK(hipMemcpy(flags, c.flags, sizeof flags, hipMemcpyDeviceToHost));
+    if (flags[FLAG_BAD_VEL]) return fail(FD_EINVAL, "%d velocities are not positive and finite", flags[FLAG_BAD_VEL]);
+    if (flags[FLAG_BAD_REC]) return fail(FD_EINVAL, "%d receiver coordinates lie outside their window", flags[FLAG_BAD_REC]);
+    if (flags[FLAG_NONFINITE]) return fail(FD_ENONFINITE, "%d trace samples are not finite", flags[FLAG_NONFINITE]);
+    return FD_OK;
+}
+
+int prepare(CallCtx& c, const fd_grid* g, const float* vel, const fd_shot* shots, int nshots, int mode,
+            int K, void* workspace, size_t ws_bytes) {
+    int rc = check_grid(g);
+    if (rc) return rc;
+    if (!vel) return fail(FD_EINVAL, "vel is NULL");
+    if (!shots || nshots < 1) return fail(FD_EINVAL, "need at least one shot");
+    if (mode == 1 && (K < 1 || K > g->nt)) return fail(FD_EINVAL, "ckpt_every must be in [1, nt]");
+    c.g = g;
+    c.vel = vel;
+    c.nshots = nshots;
+    c.K = K;
+    c.L = make_layout(g, shots, nshots, mode, K);
+    if (!workspace) return fail(FD_EINVAL, "workspace is NULL");
+    if ((uintptr_t)workspace % 256) return fail(FD_EINVAL, "workspace must be 256-byte aligned");
+    if (ws_bytes < c.L.total)
+        return fail(FD_ENOMEM, "workspace too small: %zu < %zu bytes", ws_bytes, c.L.total);
+    c.ws = (char*)workspace;
+    c.flags = (int*)(c.ws + c.L.flags);
+    c.vfield = (float*)(c.ws + c.L.v);
+    // model strides: row (y) and plane (z); in 2D the z stride is the row
+    // length, and the 2D kernels address rows with ldv_y (== ldv_z)
+    c.ldv_y = g->n[0];
+    c.ldv_z = g->n[0] * (g->ndim == 3 ? g->n[1] : 1);
+    c.sp.nb = g->nb;
+    c.sp.escale = (float)(0.5 * g->eta_max * g->dt);
+    c.sp.inv_nb = g->nb > 0 ? (float)(1.0 / g->nb) : 0.f;
+    c.q = (float)(g->dt * g->dt / std::pow(g->h, g->ndim));
+    c.grad = nullptr;
+    for (int i = 0; i < nshots; ++i) {
+        ShotCtx s;
+        rc = check_shot(g, shots[i], i, mode == 1, &s.st);
+        if (rc) return rc;
+        s.s = &shots[i];
+        s.nx = (int)shots[i].extent[0];
+        s.ny = g->ndim == 3 ? (int)shots[i].extent[1] : 1;
+        s.nz = (int)shots[i].extent[2];
+        s.npts = window_points(shots[i], g->ndim);
+        s.v = c.vfield + model_offset(c, shots[i]);
+        s.bufA = (float*)(c.ws + c.L.shots[i].bufA);
+        s.bufB = (float*)(c.ws + c.L.shots[i].bufB);
+        s.rec = (long long*)(c.ws + c.L.shots[i].rec);
+        const int* p = shots[i].src;
+        s.src = g->ndim == 2 ? (long long)p[2] * s.nx + p[0]
+                             : ((long long)p[2] * s.ny + p[1]) * s.nx + p[0];
+        c.shots.push_back(s);
+    }
+    return FD_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char* fd_last_error(void) { return g_err.c_str(); }
+
+int fd_orbits(int ndim, int shape, int M, int* reps, int* counts, int* nw) {
+    if (!nw) return fail(FD_EINVAL, "nw is NULL");
+    if (!valid_shape(ndim, shape, M)) return fail(FD_EINVAL, "invalid ndim/shape/M (%d, %d, %d)", ndim, shape, M);
+    std::vector<Orbit> o = make_orbits(ndim, shape, M);
+    *nw = (int)o.size();
+    for (size_t i = 0; i < o.size(); ++i) {
+        if (reps)
+            for (int a = 0; a < ndim; ++a) reps[i * ndim + a] = o[i].rep[a];
+        if (counts) counts[i] = o[i].count;
+    }
+    return FD_OK;
+}
+
+int fd_weights_set(int ndim, int shape, int M, const double* w, int nw, int* stencil_id) {
+    if (!stencil_id || !w) return fail(FD_EINVAL, "NULL argument");
+    if (!valid_shape(ndim, shape, M)) return fail(FD_EINVAL, "invalid ndim/shape/M (%d, %d, %d)", ndim, shape, M);
+    std::vector<Orbit> o = make_orbits(ndim, shape, M);
+    if (nw != (int)o.size()) return fail(FD_EINVAL, "expected %zu weights, got %d", o.size(), nw);
+    if ((int)o.size() > kMaxOrbits) return fail(FD_EUNSUPPORTED, "too many orbits (%zu)", o.size());
+    double sum = 0.0, asum = 0.0;
+    for (int i = 0; i < nw; ++i) {
+        if (!std::isfinite(w[i])) return fail(FD_EINVAL, "weight %d is not finite", i);
+        sum += o[i].count * w[i];
+        asum += o[i].count * std::fabs(w[i]);
+    }
+    if (!(asum > 0)) return fail(FD_EINVAL, "all weights are zero");
+    if (std::fabs(sum) > 1e-9 * asum)
+        return fail(FD_EINVAL, "weights violate the zero-sum condition: sum count*w = %.3g", sum);
+    Symbol S = make_symbol(ndim, shape, M, o, w);
+    double mneg, mpos;
+    symbol_extrema(S, &mneg, &mpos);
+    if (mpos > 1e-9 * asum) return fail(FD_EUNSTABLE, "stencil symbol is positive (%.3g): unstable for every dt", mpos);
+    if (!(mneg > 0)) return fail(FD_EINVAL, "stencil symbol is identically zero");
+    Stencil st;
+    st.ndim = ndim;
+    st.shape = shape;
+    st.M = M;
+    st.nw = nw;
+    st.w64.assign(w, w + nw);
+    std::memset(&st.w32, 0, sizeof st.w32);
+    for (int i = 0; i < nw; ++i) st.w32.w[i] = (float)w[i];
+    if (ndim == 2) {
+        for (int dx = 0; dx <= M; ++dx)
+            for (int dz = 0; dz <= M; ++dz) {
+                int a = std::max(dx, dz), b = std::min(dx, dz);
+                for (int i = 0; i < nw; ++i)
+                    if (o[i].rep[0] == a && o[i].rep[1] == b) st.w32.wd[dx * (M + 1) + dz] = (float)w[i];
+            }
+    }
+    st.cfl = 2.0 / std::sqrt(mneg);
+    st.rows = default_rows(ndim, shape, M);
+    st.zchunk = 64;
+    std::lock_guard<std::mutex> lk(g_mu);
+    for (size_t i = 0; i < g_stencils.size(); ++i) {
+        const Stencil& e = g_stencils[i];
+        if (e.ndim == ndim && e.shape == shape && e.M == M && e.w64 == st.w64) {
+            *stencil_id = (int)i;
+            return FD_OK;
+        }
+    }
+    if ((int)g_stencils.size() >= FD_MAX_STENCILS) return fail(FD_EUNSUPPORTED, "too many stencils registered");
+    g_stencils.push_back(st);
+    *stencil_id = (int)g_stencils.size() - 1;
+    return FD_OK;
+}
+
+int fd_cfl_limit(int stencil_id, double* c_lim) {
+    Stencil st;
+    if (!c_lim) return fail(FD_EINVAL, "c_lim is NULL");
+    if (!get_stencil(stencil_id, &st)) return fail(FD_EINVAL, "unknown stencil id %d", stencil_id);
+    *c_lim = st.cfl;
+    return FD_OK;
+}
+
+int fd_set_tile(int stencil_id, int rows, int zchunk) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (stencil_id < 0 || stencil_id >= (int)g_stencils.size()) return fail(FD_EINVAL, "unknown stencil id");
+    if (rows != 1 && rows != 2 && rows != 4 && rows != 8) return fail(FD_EINVAL, "rows must be 1, 2, 4 or 8");
+    if (zchunk < 8 || zchunk > 512 || zchunk % 8) return fail(FD_EINVAL, "zchunk must be a multiple of 8 in [8, 512]");
+    Stencil& s = g_stencils[stencil_id];
+    const bool have = s.ndim == 2 ? have_fwd2d(s.shape, s.M, rows) : have_fwd3d(s.shape, s.M, rows);
+    if (!have) return fail(FD_EUNSUPPORTED, "no kernel compiled for rows = %d", rows);
+    s.rows = rows;
+    s.zchunk = zchunk;
+    return FD_OK;
+}
+
+int fd_get_tile(int stencil_id, int* rows, int* zchunk) {
+    Stencil st;
+    if (!get_stencil(stencil_id, &st)) return fail(FD_EINVAL, "unknown stencil id");
+    if (rows) *rows = st.rows;
+    if (zchunk) *zchunk = st.zchunk;
+    return FD_OK;
+}
+
+size_t fd_workspace_bytes(const fd_grid* g, const fd_shot* shots, int nshots, int mode, int ckpt_every) {
+    if (check_grid(g) || !shots || nshots < 1) return 0;
+    if (mode == 1 && (ckpt_every < 1 || ckpt_every > g->nt)) return 0;
+    return make_layout(g, shots, nshots, mode, mode == 1 ? ckpt_every : 1).total;
+}
+
+int fd_forward(const fd_grid* g, const float* vel, const fd_shot* shots, int nshots, void* workspace,
+               size_t ws_bytes, void* hip_stream) {
+    g_err.clear();
+    CallCtx c;
+    int rc = prepare(c, g, vel, shots, nshots, 0, 1, workspace, ws_bytes);
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)hip_stream;
+    rc = run_call(c, 0, st);
+    if (rc) return rc;
+    return finish_checks(c, st);
+}
+
+int fd_adjoint_gradient(const fd_grid* g, const float* vel, const fd_shot* shots, int nshots,
+                        int ckpt_every, float* grad, void* workspace, size_t ws_bytes, void* hip_stream) {
+    g_err.clear();
+    if (!grad) return fail(FD_EINVAL, "grad is NULL");
+    CallCtx c;
+    int rc = prepare(c, g, vel, shots, nshots, 1, ckpt_every, workspace, ws_bytes);
+    if (rc) return rc;
+    c.grad = grad;
+    hipStream_t st = (hipStream_t)hip_stream;
+    rc = run_call(c, 1, st);
+    if (rc) return rc;
+    return finish_checks(c, st);
+}
+
+}  // extern "C"

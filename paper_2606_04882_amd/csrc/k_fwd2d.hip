@@ -1,0 +1,123 @@
+// 2D forward step: shaped stencil + leapfrog + damping band + source, with
+// the receiver gather of the previous step fused in.
+//
+//   u^{n+1} = b [ 2 u^n - a u^{n-1} + v (W * u^n) + q s^n delta_{x,xs} ]
+//
+// (Sec. 3.1 eq. wave_eq with the damping term of Sec. 3.1; Sec. 3.2
+// eqs. spacexz_derivative2_sym and time_derivative1.)  One launch per step;
+// u^n is read-only during the launch, so the receiver samples of u^n (the
+// trace of step n-1) are gathered here as well, and u^{n+1} may overwrite
+// u^{n-1} in place: each point's u^{n-1} is read only by its own thread.
+//
+// Memory traffic per point: read u^n (plus halo, from L2), u^{n-1}, v;
+// write u^{n+1}: 16 B of algorithmic HBM traffic.
+#include "fd_kernels.h"
+#include "stencil2d.h"
+
+namespace fdw {
+
+template <int SHAPE, int M, int RY>
+__global__ __launch_bounds__(kBlock) void k_fwd2d(StepArgs p) {
+    constexpr int TY = 4 * RY, LW = kTileX + 2 * M, LH = TY + 2 * M;
+    __shared__ float tile[LH * LW];
+    const int tid = threadIdx.x, tx = tid & 63, ty = tid >> 6;
+
+    if (p.trace_out) {
+        for (int r = blockIdx.x * kBlock + tid; r < p.nrec; r += gridDim.x * kBlock) {
+            const long long i = p.rec_lin[r];
+            p.trace_out[r] = i >= 0 ? p.ucur[i] : 0.f;
+        }
+    }
+
+    const int t = xcd_tile(blockIdx.x, p.ntiles);
+    const int bz = t / p.tiles_x, bx = t - bz * p.tiles_x;
+    const int x0 = bx * kTileX, z0 = bz * TY;
+    load_tile2d<M, RY>(tile, p.ucur, p.nx, p.nz, x0, z0);
+
+    // pointwise operands, issued before the barrier so their latency overlaps
+    const int gx = x0 + tx;
+    const bool colok = gx < p.nx;
+    float up[RY], vv[RY];
+#pragma unroll
+    for (int j = 0; j < RY; ++j) {
+        const int gz = z0 + ty * RY + j;
+        up[j] = 0.f;
+        vv[j] = 0.f;
+        if (colok && gz < p.nz) {
+            up[j] = p.uprev[(long long)gz * p.nx + gx];
+            vv[j] = p.v[(long long)gz * p.ldv_y + gx];
+        }
+    }
+    __syncthreads();
+
+    float uc[RY], acc[RY];
+    stencil2d<SHAPE, M, RY, LW>(tile, tx, ty, p.w, uc, acc);
+    if (!colok) return;
+
+    const int dxb = p.sp.nb > 0 ? band_depth(gx, p.nx, p.sp.nb) : 0;
+#pragma unroll
+    for (int j = 0; j < RY; ++j) {
+        const int gz = z0 + ty * RY + j;
+        if (gz >= p.nz) break;
+        const long long k = (long long)gz * p.nx + gx;
+        const int dzb = p.sp.nb > 0 ? band_depth(gz, p.nz, p.sp.nb) : 0;
+        float r;
+        if ((dxb | dzb) == 0) {
+            r = fmaf(vv[j], acc[j], 2.f * uc[j] - up[j]);
+            if (k == p.src) r += p.q * p.wavelet[p.step];
+        } else {
+            const float ex = dxb * p.sp.inv_nb, ez = dzb * p.sp.inv_nb;
+            const float e = p.sp.escale * fmaf(ex, ex, ez * ez);
+            r = fmaf(-(1.f - e), up[j], 2.f * uc[j]);
+            r = fmaf(vv[j], acc[j], r);
+            if (k == p.src) r += p.q * p.wavelet[p.step];
+            r = r / (1.f + e);
+        }
+        p.unext[k] = r;
+    }
+}
+
+template <int SHAPE, int M, int RY>
+static void run(const StepArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL((k_fwd2d<SHAPE, M, RY>), dim3(a.ntiles), dim3(kBlock), 0, s, a);
+}
+
+template <int SHAPE, int M>
+static bool dispatch_rows(const StepArgs& a, int rows, hipStream_t s) {
+    switch (rows) {
+        case 2: run<SHAPE, M, 2>(a, s); return true;
+        case 4: run<SHAPE, M, 4>(a, s); return true;
+        case 8: run<SHAPE, M, 8>(a, s); return true;
+        default: return false;
+    }
+}
+
+template <int SHAPE>
+static bool dispatch_m(const StepArgs& a, int M, int rows, hipStream_t s) {
+    switch (M) {
+        case 1: return dispatch_rows<SHAPE, 1>(a, rows, s);
+        case 2: return dispatch_rows<SHAPE, 2>(a, rows, s);
+        case 3: return dispatch_rows<SHAPE, 3>(a, rows, s);
+        case 4: return dispatch_rows<SHAPE, 4>(a, rows, s);
+        case 5: return dispatch_rows<SHAPE, 5>(a, rows, s);
+        case 6: return dispatch_rows<SHAPE, 6>(a, rows, s);
+        case 7: return dispatch_rows<SHAPE, 7>(a, rows, s);
+        case 8: return dispatch_rows<SHAPE, 8>(a, rows, s);
+        default: return false;
+    }
+}
+
+bool have_fwd2d(int shape, int M, int rows) {
+    return shape >= 0 && shape <= 2 && M >= 1 && M <= 8 && (rows == 2 || rows == 4 || rows == 8);
+}
+
+bool launch_fwd2d(const StepArgs& a, int shape, int M, int rows, hipStream_t s) {
+    switch (shape) {
+        case SH_CROSS: return dispatch_m<SH_CROSS>(a, M, rows, s);
+        case SH_RHOMBUS: return dispatch_m<SH_RHOMBUS>(a, M, rows, s);
+        case SH_SQUARE: return dispatch_m<SH_SQUARE>(a, M, rows, s);
+        default: return false;
+    }
+}
+
+}  // namespace fdw

@@ -1,0 +1,142 @@
+// 2D stencil evaluation from an LDS tile, shared by the forward and adjoint
+// kernels.
+//
+// Layout: the block computes a 64 (x) by 4*RY (z) tile; thread (tx, ty)
+// owns column x0 + tx and rows z0 + ty*RY .. z0 + ty*RY + RY - 1.  The LDS
+// tile holds u over the block tile plus an M-cell halo on every side, row
+// major with LW = 64 + 2M floats per row; lanes of a wave read consecutive
+// floats, so LDS reads are bank-conflict free.
+//
+// Arithmetic (difference form, Sec. 3.2 eq. spacexz_derivative2_sym with the
+// centre weight eliminated through the r = 0 condition): points are taken in
+// symmetric groups {(+-dx, +-dz)} sharing one orbit weight w and
+//     L += w * (sum_of_group - |group| * u(x))
+// so that every term is a small difference of nearby values; the centre
+// weight (large, -sum |o| w_o) never multiplies u directly.  Groups are taken
+// dx = 0..M outer, dz inner; x-mirror pairs are summed once per column and
+// reused by every output row and every dz.
+#pragma once
+
+#include "fd_kernels.h"
+
+namespace fdw {
+
+template <int SHAPE, int M, int RY, int LW, int DZ>
+__device__ __forceinline__ void s2_col0(const float* col, const float* uc, float* acc,
+                                        const Weights& W) {
+    if constexpr (DZ <= M) {
+        constexpr int o = orbit2(SHAPE, M, DZ, 0);
+        const float w = W.w[o];
+#pragma unroll
+        for (int j = 0; j < RY; ++j)
+            acc[j] = fmaf(w, fmaf(-2.f, uc[j], col[j + M + DZ] + col[j + M - DZ]), acc[j]);
+        s2_col0<SHAPE, M, RY, LW, DZ + 1>(col, uc, acc, W);
+    }
+}
+
+template <int SHAPE, int M, int RY, int MZ, int DX, int DZ>
+__device__ __forceinline__ void s2_dz(const float* cs, const float* uc, float* acc,
+                                      const Weights& W) {
+    if constexpr (DZ <= MZ) {
+        constexpr int o = orbit2_of(SHAPE, M, DX, DZ);
+        const float w = W.w[o];
+#pragma unroll
+        for (int j = 0; j < RY; ++j)
+            acc[j] = fmaf(w, fmaf(-4.f, uc[j], cs[j + MZ + DZ] + cs[j + MZ - DZ]), acc[j]);
+        s2_dz<SHAPE, M, RY, MZ, DX, DZ + 1>(cs, uc, acc, W);
+    }
+}
+
+template <int SHAPE, int M, int RY, int LW, int DX>
+__device__ __forceinline__ void s2_dx(const float* tile, int tx, int ty, const float* uc,
+                                      float* acc, const Weights& W) {
+    if constexpr (DX <= M) {
+        constexpr int MZ = maxdz2(SHAPE, M, DX);
+        float cs[RY + 2 * MZ];
+#pragma unroll
+        for (int j = 0; j < RY + 2 * MZ; ++j) {
+            const float* row = tile + (ty * RY + M - MZ + j) * LW + tx + M;
+            cs[j] = row[-DX] + row[DX];
+        }
+        constexpr int o0 = orbit2(SHAPE, M, DX, 0);
+        const float w0 = W.w[o0];
+#pragma unroll
+        for (int j = 0; j < RY; ++j) acc[j] = fmaf(w0, fmaf(-2.f, uc[j], cs[j + MZ]), acc[j]);
+        s2_dz<SHAPE, M, RY, MZ, DX, 1>(cs, uc, acc, W);
+        s2_dx<SHAPE, M, RY, LW, DX + 1>(tile, tx, ty, uc, acc, W);
+    }
+}
+
+// Dense shapes (rhombus, square): the column offset dx runs as a real loop,
+// uniform across the wave, so only one column group of LDS values is live at
+// a time (a fully unrolled form lets the compiler hoist every group's reads
+// and exhausts the register file).  W.wd holds the weight of group (dx, dz)
+// at wd[dx*(M+1) + dz]; the group extent along z for a given dx is
+// maxdz2(SHAPE, M, dx), a wave-uniform value.
+template <int SHAPE, int M, int RY, int LW>
+__device__ __forceinline__ void s2_dense_dx(const float* tile, int tx, int ty, const float* uc,
+                                            float* acc, const Weights& W) {
+#pragma unroll 1
+    for (int dx = 1; dx <= M; ++dx) {
+        const int mz = SHAPE == SH_RHOMBUS ? M - dx : M;
+        const float* wrow = W.wd + dx * (M + 1);
+        float cs[RY + 2 * M];
+#pragma unroll
+        for (int j = 0; j < RY + 2 * M; ++j) {
+            cs[j] = 0.f;
+            if (j >= M - mz && j < M + RY + mz) {
+                const float* row = tile + (ty * RY + j) * LW + tx + M;
+                cs[j] = row[-dx] + row[dx];
+            }
+        }
+        const float w0 = wrow[0];
+#pragma unroll
+        for (int j = 0; j < RY; ++j) acc[j] = fmaf(w0, fmaf(-2.f, uc[j], cs[j + M]), acc[j]);
+#pragma unroll
+        for (int dz = 1; dz <= M; ++dz) {
+            if (dz <= mz) {
+                const float w = wrow[dz];
+#pragma unroll
+                for (int j = 0; j < RY; ++j)
+                    acc[j] = fmaf(w, fmaf(-4.f, uc[j], cs[j + M + dz] + cs[j + M - dz]), acc[j]);
+            }
+        }
+    }
+}
+
+// acc[j] = (W * u)(x, z_j) for the thread's RY outputs; uc[j] = u(x, z_j).
+template <int SHAPE, int M, int RY, int LW>
+__device__ __forceinline__ void stencil2d(const float* tile, int tx, int ty, const Weights& W,
+                                          float* uc, float* acc) {
+    float col[RY + 2 * M];
+#pragma unroll
+    for (int j = 0; j < RY + 2 * M; ++j) col[j] = tile[(ty * RY + j) * LW + tx + M];
+#pragma unroll
+    for (int j = 0; j < RY; ++j) {
+        uc[j] = col[j + M];
+        acc[j] = 0.f;
+    }
+    s2_col0<SHAPE, M, RY, LW, 1>(col, uc, acc, W);
+    if constexpr (SHAPE == SH_CROSS)
+        s2_dx<SHAPE, M, RY, LW, 1>(tile, tx, ty, uc, acc, W);
+    else
+        s2_dense_dx<SHAPE, M, RY, LW>(tile, tx, ty, uc, acc, W);
+}
+
+// Cooperative load of the (4*RY + 2M) x (64 + 2M) tile of field f (window
+// nx x nz, dense rows) with zeros beyond the window.
+template <int M, int RY>
+__device__ __forceinline__ void load_tile2d(float* tile, const float* __restrict__ f, int nx,
+                                            int nz, int x0, int z0) {
+    constexpr int LW = kTileX + 2 * M, LH = 4 * RY + 2 * M;
+    for (int i = threadIdx.x; i < LH * LW; i += kBlock) {
+        const int r = i / LW, c = i - r * LW;
+        const int gz = z0 - M + r, gx = x0 - M + c;
+        float val = 0.f;
+        if ((unsigned)gz < (unsigned)nz && (unsigned)gx < (unsigned)nx)
+            val = f[(long long)gz * nx + gx];
+        tile[i] = val;
+    }
+}
+
+}  // namespace fdw

@@ -1,0 +1,267 @@
+"""Thin Python binding of the C ABI in include/fdwave.h.
+
+Argument marshalling only: every step of the wave propagation runs in the
+HIP kernels of libfdwave.so.  PyTorch supplies device memory (tensors) and the
+current HIP stream.  The shared library must have been built in-tree
+(`python -m paper_2606_04882_amd.build`); importing this module without it
+raises immediately - there is no CPU fallback.
+
+Names follow the C entry points: fd_orbits, fd_weights_set, fd_cfl_limit,
+fd_forward, fd_adjoint_gradient, fd_workspace_bytes, fd_set_tile,
+fd_get_tile, fd_last_error.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+from typing import List, Optional, Sequence, Tuple
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfdwave.so")
+
+FD_OK, FD_EINVAL, FD_EUNSTABLE, FD_ENOMEM, FD_EDEVICE, FD_ENONFINITE, FD_EUNSUPPORTED = range(7)
+FD_CROSS, FD_RHOMBUS, FD_SQUARE = 0, 1, 2
+FD_NO_GRAPH, FD_NO_BATCH = 1, 2
+SHAPES = {"cross": FD_CROSS, "rhombus": FD_RHOMBUS, "square": FD_SQUARE}
+_STATUS = {1: "EINVAL", 2: "EUNSTABLE", 3: "ENOMEM", 4: "EDEVICE", 5: "ENONFINITE", 6: "EUNSUPPORTED"}
+
+
+class FdError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"FD_{_STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class FdGrid(ctypes.Structure):
+    _fields_ = [("ndim", ctypes.c_int), ("nt", ctypes.c_int), ("n", ctypes.c_longlong * 3),
+                ("h", ctypes.c_double), ("dt", ctypes.c_double), ("nb", ctypes.c_int),
+                ("eta_max", ctypes.c_double), ("vmax", ctypes.c_double),
+                ("check_finite", ctypes.c_int), ("flags", ctypes.c_int)]
+
+
+class FdShot(ctypes.Structure):
+    _fields_ = [("origin", ctypes.c_longlong * 3), ("extent", ctypes.c_longlong * 3),
+                ("stencil_id", ctypes.c_int), ("src", ctypes.c_int * 3),
+                ("wavelet", ctypes.c_void_p), ("nrec", ctypes.c_int), ("rec", ctypes.c_void_p),
+                ("traces", ctypes.c_void_p), ("trace_adj", ctypes.c_void_p),
+                ("init_prev", ctypes.c_void_p), ("init_cur", ctypes.c_void_p),
+                ("final_prev", ctypes.c_void_p), ("final_cur", ctypes.c_void_p)]
+
+
+def _load() -> ctypes.CDLL:
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2606_04882_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.POINTER
+    lib.fd_last_error.restype = ctypes.c_char_p
+    lib.fd_orbits.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, P(ctypes.c_int), P(ctypes.c_int),
+                              P(ctypes.c_int)]
+    lib.fd_weights_set.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, P(ctypes.c_double),
+                                   ctypes.c_int, P(ctypes.c_int)]
+    lib.fd_cfl_limit.argtypes = [ctypes.c_int, P(ctypes.c_double)]
+    lib.fd_set_tile.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int]
+    lib.fd_get_tile.argtypes = [ctypes.c_int, P(ctypes.c_int), P(ctypes.c_int)]
+    lib.fd_workspace_bytes.restype = ctypes.c_size_t
+    lib.fd_workspace_bytes.argtypes = [P(FdGrid), P(FdShot), ctypes.c_int, ctypes.c_int, ctypes.c_int]
+    lib.fd_forward.argtypes = [P(FdGrid), ctypes.c_void_p, P(FdShot), ctypes.c_int, ctypes.c_void_p,
+                               ctypes.c_size_t, ctypes.c_void_p]
+    lib.fd_adjoint_gradient.argtypes = [P(FdGrid), ctypes.c_void_p, P(FdShot), ctypes.c_int, ctypes.c_int,
+                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
+    return lib
+
+
+_lib = _load()
+
+
+def _check(rc: int):
+    if rc != FD_OK:
+        raise FdError(rc, _lib.fd_last_error().decode())
+
+
+# ---------------------------------------------------------------------------
+# stencils
+# ---------------------------------------------------------------------------
+def fd_orbits(ndim: int, shape, M: int) -> Tuple[np.ndarray, np.ndarray]:
+    """(representatives [nw, ndim], point counts [nw]) in canonical order."""
+    shape = SHAPES.get(shape, shape)
+    nw = ctypes.c_int()
+    _check(_lib.fd_orbits(ndim, shape, M, None, None, ctypes.byref(nw)))
+    reps = np.zeros(nw.value * ndim, dtype=np.int32)
+    counts = np.zeros(nw.value, dtype=np.int32)
+    _check(_lib.fd_orbits(ndim, shape, M, reps.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                          counts.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), ctypes.byref(nw)))
+    return reps.reshape(nw.value, ndim), counts
+
+
+def fd_weights_set(ndim: int, shape, M: int, w: Sequence[float]) -> int:
+    shape = SHAPES.get(shape, shape)
+    arr = np.ascontiguousarray(np.asarray(w, dtype=np.float64))
+    sid = ctypes.c_int()
+    _check(_lib.fd_weights_set(ndim, shape, M, arr.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                               len(arr), ctypes.byref(sid)))
+    return sid.value
+
+
+def fd_cfl_limit(stencil_id: int) -> float:
+    c = ctypes.c_double()
+    _check(_lib.fd_cfl_limit(stencil_id, ctypes.byref(c)))
+    return c.value
+
+
+def fd_set_tile(stencil_id: int, rows: int, zchunk: int = 64):
+    _check(_lib.fd_set_tile(stencil_id, rows, zchunk))
+
+
+def fd_get_tile(stencil_id: int) -> Tuple[int, int]:
+    r, z = ctypes.c_int(), ctypes.c_int()
+    _check(_lib.fd_get_tile(stencil_id, ctypes.byref(r), ctypes.byref(z)))
+    return r.value, z.value
+
+
+def fd_last_error() -> str:
+    return _lib.fd_last_error().decode()
+
+
+# ---------------------------------------------------------------------------
+# calls
+# ---------------------------------------------------------------------------
+@dataclass
+class Grid:
+    """Model grid, time axis and damping band (fd_grid)."""
+    shape: Tuple[int, ...]          # array shape (nz, nx) or (nz, ny, nx)
+    h: float
+    dt: float
+    nt: int
+    nb: int = 0
+    eta_max: float = 0.0
+    vmax: float = 0.0
+    check_finite: bool = False
+    flags: int = 0
+
+    def c(self) -> FdGrid:
+        g = FdGrid()
+        g.ndim = len(self.shape)
+        g.nt = int(self.nt)
+        if g.ndim == 2:
+            g.n[0], g.n[1], g.n[2] = self.shape[1], 1, self.shape[0]
+        else:
+            g.n[0], g.n[1], g.n[2] = self.shape[2], self.shape[1], self.shape[0]
+        g.h, g.dt, g.nb, g.eta_max = float(self.h), float(self.dt), int(self.nb), float(self.eta_max)
+        g.vmax = float(self.vmax)
+        g.check_finite = int(bool(self.check_finite))
+        g.flags = int(self.flags)
+        return g
+
+
+@dataclass
+class Shot:
+    """One shot (fd_shot).  Tensors live on the GPU; coordinates are x first."""
+    stencil_id: int
+    src: Tuple[int, ...]
+    wavelet: torch.Tensor                 # [nt] float32
+    rec: Optional[torch.Tensor] = None    # [nrec, ndim] int32
+    origin: Tuple[int, ...] = (0, 0, 0)   # (x, y, z)
+    extent: Optional[Tuple[int, ...]] = None  # (x, y, z); None: whole model
+    traces: Optional[torch.Tensor] = None     # [nt, nrec] float32 output
+    trace_adj: Optional[torch.Tensor] = None  # [nt, nrec] float32
+    init: Optional[Tuple[torch.Tensor, torch.Tensor]] = None
+    final: Optional[Tuple[torch.Tensor, torch.Tensor]] = None
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("tensors passed to the GPU library must live on the GPU")
+    if not t.is_contiguous():
+        raise ValueError("tensors passed to the GPU library must be contiguous")
+    return t.data_ptr()
+
+
+def _shot_c(s: Shot, grid: Grid) -> FdShot:
+    nd = len(grid.shape)
+    c = FdShot()
+    o = tuple(s.origin) + (0,) * (3 - len(s.origin))
+    if s.extent is None:
+        ext = (grid.shape[1], 1, grid.shape[0]) if nd == 2 else (grid.shape[2], grid.shape[1], grid.shape[0])
+    else:
+        ext = tuple(s.extent)
+    for i in range(3):
+        c.origin[i] = int(o[i])
+        c.extent[i] = int(ext[i])
+    c.stencil_id = int(s.stencil_id)
+    src = (s.src[0], 0, s.src[1]) if nd == 2 else tuple(s.src)
+    for i in range(3):
+        c.src[i] = int(src[i])
+    c.wavelet = _ptr(s.wavelet)
+    c.nrec = 0 if s.rec is None else int(s.rec.shape[0])
+    c.rec = _ptr(s.rec)
+    c.traces = _ptr(s.traces)
+    c.trace_adj = _ptr(s.trace_adj)
+    if s.init is not None:
+        c.init_prev, c.init_cur = _ptr(s.init[0]), _ptr(s.init[1])
+    if s.final is not None:
+        c.final_prev, c.final_cur = _ptr(s.final[0]), _ptr(s.final[1])
+    return c
+
+
+_ws_cache: dict = {}
+
+
+def workspace(nbytes: int, device) -> torch.Tensor:
+    """A reused device buffer of at least nbytes (stable pointer helps the
+    library's graph cache)."""
+    key = torch.device(device)
+    buf = _ws_cache.get(key)
+    if buf is None or buf.numel() < nbytes:
+        _ws_cache.pop(key, None)
+        buf = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
+        _ws_cache[key] = buf
+    return buf
+
+
+def fd_workspace_bytes(grid: Grid, shots: Sequence[Shot], mode: int = 0, ckpt_every: int = 1) -> int:
+    g = grid.c()
+    arr = (FdShot * len(shots))(*[_shot_c(s, grid) for s in shots])
+    return int(_lib.fd_workspace_bytes(ctypes.byref(g), arr, len(shots), mode, ckpt_every))
+
+
+def _stream_handle(device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def fd_forward(grid: Grid, vel: torch.Tensor, shots: Sequence[Shot], ws: Optional[torch.Tensor] = None):
+    """Forward modelling; traces are written into each shot's `traces`."""
+    if vel.dtype != torch.float32 or tuple(vel.shape) != tuple(grid.shape):
+        raise ValueError(f"vel must be float32 of shape {grid.shape}")
+    g = grid.c()
+    arr = (FdShot * len(shots))(*[_shot_c(s, grid) for s in shots])
+    nbytes = int(_lib.fd_workspace_bytes(ctypes.byref(g), arr, len(shots), 0, 1))
+    if nbytes == 0:
+        raise FdError(FD_EINVAL, "invalid grid/shots for fd_workspace_bytes")
+    if ws is None:
+        ws = workspace(nbytes, vel.device)
+    _check(_lib.fd_forward(ctypes.byref(g), _ptr(vel), arr, len(shots), _ptr(ws), ws.numel(),
+                           ctypes.c_void_p(_stream_handle(vel.device))))
+
+
+def fd_adjoint_gradient(grid: Grid, vel: torch.Tensor, shots: Sequence[Shot], ckpt_every: int,
+                        grad: torch.Tensor, ws: Optional[torch.Tensor] = None):
+    """Adjoint run; dJ/dc of every shot is added into `grad`."""
+    if vel.dtype != torch.float32 or tuple(vel.shape) != tuple(grid.shape):
+        raise ValueError(f"vel must be float32 of shape {grid.shape}")
+    if grad.dtype != torch.float32 or tuple(grad.shape) != tuple(grid.shape):
+        raise ValueError("grad must be float32 with the model's shape")
+    g = grid.c()
+    arr = (FdShot * len(shots))(*[_shot_c(s, grid) for s in shots])
+    nbytes = int(_lib.fd_workspace_bytes(ctypes.byref(g), arr, len(shots), 1, ckpt_every))
+    if nbytes == 0:
+        raise FdError(FD_EINVAL, "invalid grid/shots/ckpt_every for fd_workspace_bytes")
+    if ws is None:
+        ws = workspace(nbytes, vel.device)
+    _check(_lib.fd_adjoint_gradient(ctypes.byref(g), _ptr(vel), arr, len(shots), ckpt_every, _ptr(grad),
+                                    _ptr(ws), ws.numel(), ctypes.c_void_p(_stream_handle(vel.device))))

@@ -1,0 +1,260 @@
+"""Benchmark: grid-point updates per second of the leapfrog shaped-stencil
+forward path on one MI355X, plus the FWI gradient time per shot.
+
+A "step" is one pass of the whole forward hot path over the default workload:
+the 1001 x 1001 layered 2D model advanced 2000 time steps with each of the
+eight stencils (Taylor cross M=4,8; DispTE cross M=4,8; DispTE rhombus M=4,8;
+SpecLS square M=4,8), sources, damping band and 501 receivers included.
+value = total grid-point updates / wall time (inputs resident in HBM).
+
+Also reported on the same line:
+  roofline      the kernel with the largest share of the step time, timed with
+                HIP events on the stream it runs on; algorithmic bytes or flops
+                per update times updates per launch, over the average launch
+                duration; HBM traffic from rocprofv3 counters when available
+  cpu_baseline  the FP64 oracle on this host's cores, on a bounded sample of
+                the same workload (a few steps per stencil), in Gpt-updates/s
+  fwi           FWI gradient (forward + checkpointed adjoint) seconds per shot
+                on the 601 x 301 workload, against the plain form (per-step
+                launches, full forward storage, shot after shot)
+  variants      per-stencil Gpt-updates/s
+"""
+from __future__ import annotations
+
+import argparse
+import faulthandler
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FP32_PEAK_TFLOPS = 157.3
+BYTES_PER_UPDATE = 16.0  # read u^n, u^{n-1}, v; write u^{n+1}
+
+
+def flops_per_update(ndim: int, shape: str, M: int) -> float:
+    """Algorithmic FP32 flops of one update with symmetric orbit sums:
+    (P - 1) additions over the stencil points, one multiply-add per orbit
+    (2 flops each), and 4 for the leapfrog update (P points, n_orb orbits)."""
+    from paper_2606_04882_amd.fdwave import fd_orbits
+    _, counts = fd_orbits(ndim, shape, M)
+    P, n_orb = int(counts.sum()), len(counts) - 1
+    return (P - 1) + 2 * n_orb + 4
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--nt", type=int, default=2000, help="time steps per stencil pass")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fwi", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    return ap.parse_args()
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def main():
+    faulthandler.enable()
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: the path is single-GPU (shots would be sharded "
+              "across GPUs with one gradient all-reduce); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2606_04882_amd import configs, design, fdwave as F
+
+    dev = torch.device("cuda:0")
+    w = configs.large_2d(nt=args.nt)
+    vel_np = configs.large_2d_model(w)
+    vel = torch.tensor(vel_np, device=dev)
+    wav = torch.tensor(w.wavelet().astype(np.float32), device=dev)
+    rec = torch.tensor(w.rec.astype(np.int32), device=dev)
+    grid = F.Grid(shape=w.shape, h=w.h, dt=w.dt, nt=w.nt, nb=w.nb, eta_max=w.eta_max, vmax=w.c_max)
+    variants = []
+    log("registering stencils")
+    for scheme, shape, M in w.stencils:
+        wts = design.weights(2, scheme, shape, M, w.courant)
+        sid = F.fd_weights_set(2, shape, M, wts)
+        shot = F.Shot(stencil_id=sid, src=w.src, wavelet=wav, rec=rec,
+                      traces=torch.zeros(w.nt, len(w.rec), device=dev))
+        nbytes = F.fd_workspace_bytes(grid, [shot])
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        variants.append({"name": f"{scheme}-{shape}-M{M}", "shape": shape, "M": M, "sid": sid,
+                         "shot": shot, "ws": ws, "rows": F.fd_get_tile(sid)[0]})
+
+    stream = torch.cuda.current_stream(dev)
+    npts = int(np.prod(w.shape))
+    updates_per_step = npts * w.nt * len(variants)
+
+    def one_step(events=None):
+        for i, v in enumerate(variants):
+            if events is not None:
+                events[i][0].record(stream)
+            F.fd_forward(grid, vel, [v["shot"]], ws=v["ws"])
+            if events is not None:
+                events[i][1].record(stream)
+
+    log(f"setup done: {len(variants)} stencils, {npts} points, nt={w.nt}")
+    for _ in range(max(args.warmup, 1)):
+        one_step()
+    torch.cuda.synchronize()
+    log("warm-up done")
+
+    evs = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+            for _ in variants] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        one_step(evs[k])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    elapsed = t1 - t0
+    value = updates_per_step * args.steps / elapsed
+
+    per_variant = []
+    for i, v in enumerate(variants):
+        ms = sum(evs[k][i][0].elapsed_time(evs[k][i][1]) for k in range(args.steps)) / args.steps
+        per_variant.append({"stencil": v["name"], "ms": round(ms, 4),
+                            "gupd_s": round(npts * w.nt / (ms * 1e-3) / 1e9, 2), "rows": v["rows"]})
+    dom = max(range(len(variants)), key=lambda i: per_variant[i]["ms"])
+    dv = variants[dom]
+    launch_ms = per_variant[dom]["ms"] / w.nt   # one kernel launch per time step
+    flops = flops_per_update(2, dv["shape"], dv["M"])
+    gbs = npts * BYTES_PER_UPDATE / (launch_ms * 1e-3) / 1e9
+    tfl = npts * flops / (launch_ms * 1e-3) / 1e12
+    if gbs / HBM_PEAK_GBS >= tfl / FP32_PEAK_TFLOPS:
+        roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    else:
+        roof = {"bound": "alu", "achieved": round(tfl, 2), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(tfl / FP32_PEAK_TFLOPS, 4)}
+    roof["kernel"] = f"k_fwd2d<{dv['shape']},M={dv['M']},rows={dv['rows']}>"
+    roof["traffic"] = None
+    roof["launch_us"] = round(launch_ms * 1e3, 3)
+
+    line = {
+        "metric": "Gpt-updates/s (forward, 2D 1001x1001, 8 stencils)",
+        "value": round(value / 1e9, 3),
+        "unit": "Gpt-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(elapsed / args.steps * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded layered model, Ricker source)",
+        "config": {"workload": w.name, "grid": list(w.shape), "nt": w.nt, "stencils": len(variants),
+                   "updates_per_step": updates_per_step, "pct_hbm_effective":
+                   round(100 * value * BYTES_PER_UPDATE / (HBM_PEAK_GBS * 1e9), 2)},
+        "roofline": roof,
+        "variants": per_variant,
+    }
+
+    log(f"timed: {value / 1e9:.1f} Gupd/s")
+    if not args.no_fwi:
+        line["fwi"] = fwi_bench(torch, F, design, configs, dev)
+        log("fwi done")
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(w, vel_np, args.cpu_seconds)
+        log("cpu baseline done")
+    print(json.dumps(line))
+
+
+def fwi_bench(torch, F, design, configs, dev):
+    """FWI gradient on the 601 x 301 workload: 16 shots, 3000 steps, DispTE
+    cross M=4, checkpoints every 100 steps; s/shot of the graph-replayed
+    checkpointed adjoint vs the plain form (direct per-step launches, full
+    forward storage, shot after shot)."""
+    w = configs.fwi()
+    true_m, start_m = configs.fwi_models(w)
+    grid = F.Grid(shape=w.shape, h=w.h, dt=w.dt, nt=w.nt, nb=w.nb, eta_max=w.eta_max, vmax=w.c_max)
+    sid = F.fd_weights_set(2, "cross", 4, design.weights(2, "dispte", "cross", 4, w.courant))
+    wav = torch.tensor(w.wavelet().astype(np.float32), device=dev)
+    rec = torch.tensor(w.rec.astype(np.int32), device=dev)
+    vt, vs = torch.tensor(true_m, device=dev), torch.tensor(start_m, device=dev)
+    shots = []
+    for src in w.extra["sources"]:
+        sh = F.Shot(stencil_id=sid, src=src, wavelet=wav, rec=rec,
+                    traces=torch.zeros(w.nt, len(w.rec), device=dev))
+        shots.append(sh)
+    F.fd_forward(grid, vt, shots)
+    dobs = [s.traces.clone() for s in shots]
+    F.fd_forward(grid, vs, shots)
+    for s, d in zip(shots, dobs):
+        s.trace_adj = (s.traces - d).contiguous()
+    K = w.extra["ckpt_every"]
+
+    def timed(g, k, reps):
+        grad = torch.zeros(w.shape, device=dev)
+        F.fd_adjoint_gradient(g, vs, shots, k, grad)   # warm-up (graph capture)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            grad.zero_()
+            F.fd_adjoint_gradient(g, vs, shots, k, grad)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps / len(shots), grad
+
+    t_fast, g_fast = timed(grid, K, 2)
+    plain = F.Grid(shape=w.shape, h=w.h, dt=w.dt, nt=w.nt, nb=w.nb, eta_max=w.eta_max, vmax=w.c_max,
+                   flags=F.FD_NO_GRAPH | F.FD_NO_BATCH)
+    t_plain, g_plain = timed(plain, w.nt, 1)
+    diff = float((g_fast - g_plain).norm() / g_plain.norm())
+    return {"workload": w.name, "shots": len(shots), "nt": w.nt, "ckpt_every": K,
+            "s_per_shot": round(t_fast, 5), "plain_s_per_shot": round(t_plain, 5),
+            "speedup_vs_plain": round(t_plain / t_fast, 3), "grad_rel_diff_vs_plain": diff}
+
+
+def cpu_baseline(w, vel_np, budget_s):
+    """The FP64 oracle (plain C, OpenMP over the slowest axis) on this host:
+    each of the eight stencils advanced a few steps on the full 1001 x 1001
+    model; rate in Gpt-updates/s.  Bounded to about budget_s seconds."""
+    from oracle import stepper as S
+    from oracle import weights as W
+    from fractions import Fraction
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    v = S.v_from_c(vel_np.astype(np.float64), w.dt, w.h)
+    q = S.source_term(w.wavelet(), w.dt, w.h, 2)
+    sts = []
+    for scheme, shape, M in w.stencils:
+        if scheme == "taylor":
+            wo = W.to_float(W.taylor(2, M))
+        elif scheme == "dispte":
+            wo = W.to_float(W.dispte(2, shape, M, Fraction(w.courant)))
+        else:
+            wo = W.specls(2, shape, M)
+        offs, ws = W.expand(2, shape, M, wo)
+        sts.append(S.Stencil(offs, ws))
+    # one step of each stencil to size the sample
+    t0 = time.perf_counter()
+    for st in sts:
+        S.forward(st, v, w.dt, 1, w.nb, w.eta_max, w.src, q[:1], w.rec)
+    one = time.perf_counter() - t0
+    nsteps = max(1, min(50, int(budget_s / max(one, 1e-3))))
+    t0 = time.perf_counter()
+    for st in sts:
+        S.forward(st, v, w.dt, nsteps, w.nb, w.eta_max, w.src, q[:nsteps], w.rec)
+    el = time.perf_counter() - t0
+    rate = len(sts) * nsteps * int(np.prod(w.shape)) / el
+    return {"value": round(rate / 1e9, 5), "unit": "Gpt-updates/s", "cores": cores, "kind": "oracle",
+            "sample": f"8 stencils x {nsteps} steps on the full {w.shape[1]}x{w.shape[0]} model, FP64",
+            "seconds": round(el, 2)}
+
+
+if __name__ == "__main__":
+    main()

@@ -329,7 +329,7 @@ int g_graph_fallbacks = 0;
 
 struct GraphCache {
     std::mutex mu;
-    std::list<std::pair<std::vector<uint64_t>, hipGraphExec_t>> lru;
+    std::list<std::pair<std::vector<uint64_t>, std::vector<hipGraphExec_t>>> lru;
     std::map<int, hipStream_t> capture_streams;
     static constexpr size_t kCap = 24;
 } g_graphs;
@@ -342,6 +342,44 @@ void key_push(std::vector<uint64_t>& k, const void* p, size_t n) {
         k.push_back(w);
     }
 }
+
+// Splits captured work into graphs of bounded size: HIP graph capture and
+// instantiation cost grow with the node count, and a multi-shot adjoint
+// would otherwise become one graph of ~10^5 nodes.  In direct mode (no
+// capture) cuts do nothing.
+struct Recorder {
+    bool capturing = false;
+    hipStream_t stream = nullptr;
+    std::vector<hipGraphExec_t> execs;
+    int nodes = 0;
+    int err = FD_OK;
+    static constexpr int kMaxNodes = 2048;
+
+    void launched(int n = 1) {
+        nodes += n;
+        if (nodes >= kMaxNodes) cut();
+    }
+    // End the current capture, keep its graph, and start capturing again.
+    // After a failure the remaining work is still captured (and later
+    // discarded) so that nothing runs outside the caller's stream order.
+    void cut() {
+        if (!capturing || nodes == 0) return;
+        hipGraph_t graph = nullptr;
+        hipError_t e = hipStreamEndCapture(stream, &graph);
+        hipGraphExec_t exec = nullptr;
+        if (e == hipSuccess && err == FD_OK) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        if (graph) hipGraphDestroy(graph);
+        if (exec) execs.push_back(exec);
+        if (e != hipSuccess && err == FD_OK)
+            err = fail(FD_EDEVICE, "graph capture failed: %s", hipGetErrorString(e));
+        nodes = 0;
+        e = hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) {
+            if (err == FD_OK) err = fail(FD_EDEVICE, "graph capture failed: %s", hipGetErrorString(e));
+            capturing = false;
+        }
+    }
+};
 
 // ---------------------------------------------------------------------------
 // per-call context and the enqueued work
@@ -421,41 +459,62 @@ bool launch_step(const CallCtx& c, const ShotCtx& s, const StepArgs& a, hipStrea
     return launch_fwd3d(a, s.st.shape, s.st.M, s.st.rows, st);
 }
 
-// forward run of one shot with optional checkpoint saving (ckpt != nullptr:
-// slot j receives (u^{jK-1}, u^{jK})).
-int enqueue_forward_shot(const CallCtx& c, const ShotCtx& s, float* ckpt, int K, hipStream_t st) {
+// forward run of one shot.  With ckpt != nullptr, slot j receives
+// (u^{jK-1}, u^{jK}) for every segment start jK, and the steps of the last
+// segment [tail, nt) write u^{n+1} out of place into seg[n - tail] (so the
+// adjoint needs no recompute for that segment).
+int enqueue_forward_shot(const CallCtx& c, const ShotCtx& s, float* ckpt, int K, float* seg,
+                         Recorder& R) {
+    hipStream_t st = R.stream;
     const long long n = s.npts;
+    const int nt = c.g->nt;
     float* prev = s.bufA;
     float* cur = s.bufB;
     if (s.s->init_prev) launch_copy(prev, s.s->init_prev, n, st); else launch_fill(prev, n, 0.f, st);
     if (s.s->init_cur) launch_copy(cur, s.s->init_cur, n, st); else launch_fill(cur, n, 0.f, st);
     launch_rec_index(s.s->rec, s.s->nrec, c.g->ndim, s.nx, s.ny, s.nz, s.rec, c.flags, st);
+    const int tail = ckpt ? ((nt - 1) / K) * K : nt;
     if (ckpt) {
         launch_copy(ckpt, prev, n, st);
         launch_copy(ckpt + n, cur, n, st);
     }
     StepArgs a = base_step(c, s);
-    for (int step = 0; step < c.g->nt; ++step) {
-        a.ucur = cur;
-        a.uprev = prev;
-        a.unext = prev;
+    const float* ucur = cur;
+    const float* uprev = prev;
+    for (int step = 0; step < nt; ++step) {
         a.step = step;
         a.trace_out = (step > 0 && s.s->nrec > 0) ? s.s->traces + (size_t)(step - 1) * s.s->nrec : nullptr;
-        if (!launch_step(c, s, a, st)) return fail(FD_EUNSUPPORTED, "kernel not compiled");
-        std::swap(prev, cur);
-        if (ckpt && (step + 1) % K == 0 && step + 1 < c.g->nt) {
-            float* slot = ckpt + (size_t)((step + 1) / K) * 2 * n;
-            launch_copy(slot, prev, n, st);
-            launch_copy(slot + n, cur, n, st);
+        if (step < tail) {
+            a.ucur = cur;
+            a.uprev = prev;
+            a.unext = prev;
+        } else {
+            const int i = step - tail;
+            a.ucur = i == 0 ? cur : seg + (size_t)(i - 1) * n;
+            a.uprev = i == 0 ? prev : (i == 1 ? cur : seg + (size_t)(i - 2) * n);
+            a.unext = seg + (size_t)i * n;
         }
+        if (!launch_step(c, s, a, st)) return fail(FD_EUNSUPPORTED, "kernel not compiled");
+        R.launched();
+        if (step < tail) {
+            std::swap(prev, cur);
+            if (ckpt && (step + 1) % K == 0 && step + 1 < nt) {
+                float* slot = ckpt + (size_t)((step + 1) / K) * 2 * n;
+                launch_copy(slot, prev, n, st);
+                launch_copy(slot + n, cur, n, st);
+            }
+        }
+        ucur = a.unext;
+        uprev = a.ucur;
     }
     if (s.s->nrec > 0)
-        launch_gather(cur, s.rec, s.s->nrec, s.s->traces + (size_t)(c.g->nt - 1) * s.s->nrec, st);
-    if (s.s->final_prev) launch_copy(s.s->final_prev, prev, n, st);
-    if (s.s->final_cur) launch_copy(s.s->final_cur, cur, n, st);
+        launch_gather(ucur, s.rec, s.s->nrec, s.s->traces + (size_t)(nt - 1) * s.s->nrec, st);
+    if (s.s->final_prev) launch_copy(s.s->final_prev, uprev, n, st);
+    if (s.s->final_cur) launch_copy(s.s->final_cur, ucur, n, st);
     if (c.g->check_finite && s.s->nrec > 0)
-        launch_check_finite(s.s->traces, (long long)c.g->nt * s.s->nrec, c.flags, st);
-    return FD_OK;
+        launch_check_finite(s.s->traces, (long long)nt * s.s->nrec, c.flags, st);
+    R.launched(4);
+    return R.err;
 }
 
 AdjArgs base_adj(const CallCtx& c, const ShotCtx& s) {
@@ -487,15 +546,17 @@ bool launch_adj(const CallCtx& c, const ShotCtx& s, const AdjArgs& a, hipStream_
 }
 
 // forward with checkpoints, then segment-wise recompute + adjoint, one shot
-int enqueue_adjoint_shot(const CallCtx& c, const ShotCtx& s, hipStream_t st) {
+int enqueue_adjoint_shot(const CallCtx& c, const ShotCtx& s, Recorder& R) {
+    hipStream_t st = R.stream;
     const int nt = c.g->nt, K = c.K;
     const long long n = s.npts;
     float* ckpt = (float*)(c.ws + c.L.ckpt);
     float* seg = (float*)(c.ws + c.L.seg);
     float* pa = (float*)(c.ws + c.L.psiA);
     float* pb = (float*)(c.ws + c.L.psiB);
-    int rc = enqueue_forward_shot(c, s, ckpt, K, st);
+    int rc = enqueue_forward_shot(c, s, ckpt, K, seg, R);
     if (rc) return rc;
+    R.cut();
     launch_fill(pa, n, 0.f, st);   // psi^{nt+1}
     launch_fill(pb, n, 0.f, st);   // psi^{nt+2}
     float* pcur = pa;
@@ -508,14 +569,16 @@ int enqueue_adjoint_shot(const CallCtx& c, const ShotCtx& s, hipStream_t st) {
         const int s0 = j * K, e0 = std::min(nt, s0 + K);
         const float* ck_prev = ckpt + (size_t)j * 2 * n;
         const float* ck_cur = ck_prev + n;
-        // recompute u^{s0+1} .. u^{e0} into seg[0 .. e0-s0-1]
-        for (int step = s0; step < e0; ++step) {
+        // recompute u^{s0+1} .. u^{e0} into seg[0 .. e0-s0-1] (the last
+        // segment is already there from the forward pass)
+        for (int step = s0; step < e0 && j < nseg - 1; ++step) {
             const int i = step - s0;
             f.ucur = i == 0 ? ck_cur : seg + (size_t)(i - 1) * n;
             f.uprev = i == 0 ? ck_prev : (i == 1 ? ck_cur : seg + (size_t)(i - 2) * n);
             f.unext = seg + (size_t)i * n;
             f.step = step;
             if (!launch_step(c, s, f, st)) return fail(FD_EUNSUPPORTED, "kernel not compiled");
+            R.launched();
         }
         // adjoint iterations k = e0 .. s0+1: psi^k from psi^{k+1}, psi^{k+2};
         // gradient term (2/c) psi^{k+1} (W u^k) for k < nt
@@ -531,7 +594,9 @@ int enqueue_adjoint_shot(const CallCtx& c, const ShotCtx& s, hipStream_t st) {
                 launch_inject(pprev, s.rec, s.s->nrec, s.s->trace_adj + (size_t)(k - 1) * s.s->nrec, s.v,
                               c.ldv_y, c.ldv_z, c.sp, s.nx, s.ny, s.nz, st);
             std::swap(pcur, pprev);
+            R.launched(2);
         }
+        R.cut();
     }
     // last gradient term (2/c) psi^1 (W u^0): non-zero only with initial data
     if (s.s->init_cur) {
@@ -542,19 +607,22 @@ int enqueue_adjoint_shot(const CallCtx& c, const ShotCtx& s, hipStream_t st) {
         a.with_grad = 1;
         a.with_update = 0;
         if (!launch_adj(c, s, a, st)) return fail(FD_EUNSUPPORTED, "adjoint kernel not compiled");
+        R.launched();
     }
-    return FD_OK;
+    return R.err;
 }
 
-int enqueue_call(const CallCtx& c, int mode, hipStream_t st) {
-    launch_fill_i32(c.flags, FLAG_COUNT, 0, st);
+int enqueue_call(const CallCtx& c, int mode, Recorder& R) {
+    launch_fill_i32(c.flags, FLAG_COUNT, 0, R.stream);
     const long long mpts = c.g->n[0] * (c.g->ndim == 3 ? c.g->n[1] : 1) * c.g->n[2];
-    launch_vprep(c.vel, c.vfield, mpts, c.g->dt / c.g->h, c.flags, st);
+    launch_vprep(c.vel, c.vfield, mpts, c.g->dt / c.g->h, c.flags, R.stream);
+    R.launched(2);
     for (const ShotCtx& s : c.shots) {
-        int rc = mode == 0 ? enqueue_forward_shot(c, s, nullptr, 0, st) : enqueue_adjoint_shot(c, s, st);
+        int rc = mode == 0 ? enqueue_forward_shot(c, s, nullptr, 0, nullptr, R)
+                           : enqueue_adjoint_shot(c, s, R);
         if (rc) return rc;
     }
-    return FD_OK;
+    return R.err;
 }
 
 int get_capture_stream(int dev, hipStream_t* out) {
@@ -570,13 +638,17 @@ int get_capture_stream(int dev, hipStream_t* out) {
     return FD_OK;
 }
 
+int run_direct(CallCtx& c, int mode, hipStream_t user) {
+    Recorder R;
+    R.stream = user;
+    int rc = enqueue_call(c, mode, R);
+    if (rc) return rc;
+    HIP_OK(hipGetLastError());
+    return FD_OK;
+}
+
 int run_call(CallCtx& c, int mode, hipStream_t user) {
-    if (c.g->flags & FD_NO_GRAPH) {
-        int rc = enqueue_call(c, mode, user);
-        if (rc) return rc;
-        HIP_OK(hipGetLastError());
-        return FD_OK;
-    }
+    if (c.g->flags & FD_NO_GRAPH) return run_direct(c, mode, user);
     int dev = 0;
     HIP_OK(hipGetDevice(&dev));
     std::vector<uint64_t> key;
@@ -592,44 +664,50 @@ int run_call(CallCtx& c, int mode, hipStream_t user) {
         key.push_back(((uint64_t)s.st.rows << 32) | (uint32_t)s.st.zchunk);
     }
     std::lock_guard<std::mutex> lk(g_graphs.mu);
-    hipGraphExec_t exec = nullptr;
+    const std::vector<hipGraphExec_t>* execs = nullptr;
     for (auto it = g_graphs.lru.begin(); it != g_graphs.lru.end(); ++it) {
         if (it->first == key) {
-            exec = it->second;
             g_graphs.lru.splice(g_graphs.lru.begin(), g_graphs.lru, it);
+            execs = &g_graphs.lru.begin()->second;
             break;
         }
     }
-    if (!exec) {
+    if (!execs) {
         hipStream_t cs;
         int rc = get_capture_stream(dev, &cs);
         if (rc) return rc;
+        Recorder R;
+        R.stream = cs;
+        R.capturing = true;
         HIP_OK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-        rc = enqueue_call(c, mode, cs);
-        hipGraph_t graph = nullptr;
-        hipError_t e = hipStreamEndCapture(cs, &graph);
-        if (rc) {
+        rc = enqueue_call(c, mode, R);
+        if (R.capturing) {
+            hipGraph_t graph = nullptr;
+            hipError_t e = hipStreamEndCapture(cs, &graph);
+            hipGraphExec_t exec = nullptr;
+            if (e == hipSuccess && !rc && !R.err && R.nodes > 0)
+                e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
             if (graph) hipGraphDestroy(graph);
-            return rc;
+            if (exec) R.execs.push_back(exec);
+            if (e != hipSuccess && !rc && !R.err)
+                R.err = fail(FD_EDEVICE, "graph capture failed: %s", hipGetErrorString(e));
         }
-        if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-        if (graph) hipGraphDestroy(graph);
-        if (e != hipSuccess) {
+        if (rc || R.err) {
+            for (hipGraphExec_t x : R.execs) hipGraphExecDestroy(x);
+            if (rc) return rc;
             // capture is an optimisation: queue the same work directly
             (void)hipGetLastError();
             g_graph_fallbacks++;
-            rc = enqueue_call(c, mode, user);
-            if (rc) return rc;
-            HIP_OK(hipGetLastError());
-            return FD_OK;
+            return run_direct(c, mode, user);
         }
-        g_graphs.lru.emplace_front(key, exec);
+        g_graphs.lru.emplace_front(key, R.execs);
+        execs = &g_graphs.lru.begin()->second;
         while (g_graphs.lru.size() > GraphCache::kCap) {
-            hipGraphExecDestroy(g_graphs.lru.back().second);
+            for (hipGraphExec_t x : g_graphs.lru.back().second) hipGraphExecDestroy(x);
             g_graphs.lru.pop_back();
         }
     }
-    HIP_OK(hipGraphLaunch(exec, user));
+    for (hipGraphExec_t x : *execs) HIP_OK(hipGraphLaunch(x, user));
     return FD_OK;
 }
 

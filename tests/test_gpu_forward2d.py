@@ -60,7 +60,7 @@ def test_small_config_500_steps(F):
     # by step 500 the wave has left through the damping band; the remaining
     # field is ~1e-15, so compare it against the traces' scale
     scale = np.abs(ref["traces"]).max()
-    assert np.abs(gpu["cur"] - ref["cur"]).max() <= 1e-6 * scale
+    assert np.abs(gpu["cur"] - ref["cur"]).max() <= 1e-5 * scale
     # snapshot while the wave is inside the grid
     half = gpu_run(F, vel, w.h, w.dt, 200, w.nb, w.eta_max, sid, w.src, wav[:200], w.rec, final=True)
     refh = oracle_traces(2, "cross", 4, wo, vel, w.h, w.dt, 200, w.nb, w.eta_max, w.src, wav[:200], w.rec)

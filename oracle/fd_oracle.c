@@ -97,8 +97,12 @@ static void apply_stencil(const ora_grid *g, int npts, const int *o3, const doub
             }
 }
 
-/* damping factors a = 1 - eta dt/2, b = 1/(1 + eta dt/2) for every node */
-static void sponge(const ora_grid *g, int nb, double eta_max, double dt, double *a, double *b) {
+/* damping factors a = 1 - eta dt/2, b = 1/(1 + eta dt/2) for every node.
+ * The band depth is measured in the coordinates of an enclosing grid: node
+ * (x, y, z) of this grid is node (x, y, z) + goff of a grid of extent gext
+ * (goff = 0, gext = n when the grid is the whole domain). */
+static void sponge(const ora_grid *g, int nb, double eta_max, double dt, const i64 *goff,
+                   const i64 *gext, double *a, double *b) {
     const i64 nx = g->n[0], ny = g->n[1], nz = g->n[2];
     for (i64 z = 0; z < nz; ++z)
         for (i64 y = 0; y < ny; ++y)
@@ -108,7 +112,7 @@ static void sponge(const ora_grid *g, int nb, double eta_max, double dt, double 
                     i64 idx[3] = {x, y, z};
                     for (int ax = 0; ax < 3; ++ax) {
                         if (g->ndim == 2 && ax == 1) continue;
-                        i64 i = idx[ax], n = g->n[ax];
+                        i64 i = idx[ax] + goff[ax], n = gext[ax];
                         i64 d = nb - i;
                         i64 d2 = i - (n - 1 - nb);
                         if (d2 > d) d = d2;
@@ -139,9 +143,16 @@ int ora_forward(int ndim, const i64 *n, int npts, const int *offs, const double 
                 const double *v, double dt, int nt, int nb, double eta_max,
                 const i64 *src, const double *q, int nrec, const i64 *rec, double *traces,
                 const double *init_prev, const double *init_cur,
-                double *final_prev, double *final_cur, double *store, int periodic) {
+                double *final_prev, double *final_cur, double *store, int periodic,
+                const i64 *goff_in, const i64 *gext_in) {
     if (ndim != 2 && ndim != 3) return -2;
     ora_grid g; grid_init(&g, ndim, n);
+    i64 goff[3] = {0, 0, 0}, gext[3] = {g.n[0], g.n[1], g.n[2]};
+    if (goff_in && gext_in) {   /* given x-first with ndim entries */
+        goff[0] = goff_in[0]; gext[0] = gext_in[0];
+        if (ndim == 3) { goff[1] = goff_in[1]; gext[1] = gext_in[1]; goff[2] = goff_in[2]; gext[2] = gext_in[2]; }
+        else { goff[2] = goff_in[1]; gext[2] = gext_in[1]; }
+    }
     const i64 N = g.npoints;
     int *o3 = (int *)malloc(sizeof(int) * 3 * (size_t)(npts > 0 ? npts : 1));
     double *um = (double *)calloc((size_t)N, sizeof(double));
@@ -153,7 +164,7 @@ int ora_forward(int ndim, const i64 *n, int npts, const int *offs, const double 
         free(o3); free(um); free(u0); free(lu); free(a); free(b); return -1;
     }
     expand_offsets(ndim, npts, offs, o3);
-    sponge(&g, nb, eta_max, dt, a, b);
+    sponge(&g, nb, eta_max, dt, goff, gext, a, b);
     if (init_prev) memcpy(um, init_prev, sizeof(double) * (size_t)N);
     if (init_cur) memcpy(u0, init_cur, sizeof(double) * (size_t)N);
     i64 isrc = src ? node_index(&g, src) : -1;
@@ -209,13 +220,16 @@ int ora_adjoint_gradient(int ndim, const i64 *n, int npts, const int *offs, cons
         return -1;
     }
     int rc = ora_forward(ndim, n, npts, offs, w, v, dt, nt, nb, eta_max, src, q, 0, NULL, NULL,
-                         init_prev, init_cur, NULL, NULL, store, 0);
+                         init_prev, init_cur, NULL, NULL, store, 0, NULL, NULL);
     if (rc) {
         free(store); free(o3); free(p1); free(p2); free(lp); free(lu); free(a); free(b);
         return rc;
     }
     expand_offsets(ndim, npts, offs, o3);
-    sponge(&g, nb, eta_max, dt, a, b);
+    {
+        i64 goff[3] = {0, 0, 0}, gext[3] = {g.n[0], g.n[1], g.n[2]};
+        sponge(&g, nb, eta_max, dt, goff, gext, a, b);
+    }
     for (i64 k = 0; k < N; ++k) grad[k] = 0.0;
 
     for (int k = nt; k >= 1; --k) {

@@ -49,7 +49,8 @@ def _load():
         lib.ora_forward.restype = ctypes.c_int
         lib.ora_forward.argtypes = [ctypes.c_int, _lp, ctypes.c_int, _ip, _dp, _dp, ctypes.c_double,
                                     ctypes.c_int, ctypes.c_int, ctypes.c_double, _lp, _dp,
-                                    ctypes.c_int, _lp, _dp, _dp, _dp, _dp, _dp, _dp, ctypes.c_int]
+                                    ctypes.c_int, _lp, _dp, _dp, _dp, _dp, _dp, _dp, ctypes.c_int,
+                                    _lp, _lp]
         lib.ora_adjoint_gradient.restype = ctypes.c_int
         lib.ora_adjoint_gradient.argtypes = [ctypes.c_int, _lp, ctypes.c_int, _ip, _dp, _dp, _dp,
                                              ctypes.c_double, ctypes.c_int, ctypes.c_int,
@@ -107,8 +108,12 @@ def source_term(wavelet: np.ndarray, dt: float, h: float, ndim: int) -> np.ndarr
 
 def forward(st: Stencil, v: np.ndarray, dt: float, nt: int, nb: int, eta_max: float,
             src: Optional[Sequence[int]], q: Optional[np.ndarray], rec: Optional[np.ndarray],
-            init=None, store: bool = False, periodic: bool = False):
+            init=None, store: bool = False, periodic: bool = False, crop=None):
     """Run nt steps.  v is model-shaped ([nz, nx] or [nz, ny, nx]).
+
+    crop = (offset, extent), both x first: this grid is the box at `offset`
+    inside a grid of `extent`, and the damping band is placed by the enclosing
+    grid's coordinates (used to reproduce a sub-box of a large run).
 
     Returns dict(traces [nt, nrec], prev = u^{nt-1}, cur = u^{nt},
     store = [nt+1, ...] (u^0..u^nt) if requested)."""
@@ -131,7 +136,9 @@ def forward(st: Stencil, v: np.ndarray, dt: float, nt: int, nb: int, eta_max: fl
                          srcl.ctypes.data_as(_lp) if srcl is not None else None, _d(qq), nrec,
                          recl.ctypes.data_as(_lp) if recl is not None else None,
                          _d(traces) if nrec else None, _d(ip), _d(ic), _d(prev), _d(cur),
-                         _d(stor), int(periodic))
+                         _d(stor), int(periodic),
+                         _ll(crop[0]).ctypes.data_as(_lp) if crop is not None else None,
+                         _ll(crop[1]).ctypes.data_as(_lp) if crop is not None else None)
     if rc != 0:
         raise RuntimeError(f"ora_forward failed ({rc})")
     return {"traces": traces, "prev": prev, "cur": cur, "store": stor}

@@ -200,9 +200,9 @@ std::mutex g_mu;
 std::vector<Stencil> g_stencils;
 
 int default_rows(int ndim, int shape, int M) {
-    (void)shape;
-    (void)M;
-    return ndim == 2 ? 4 : 2;
+    if (ndim == 2) return 4;
+    if (shape == FD_CROSS) return 2;
+    return M <= 4 ? 2 : 1;
 }
 
 bool get_stencil(int id, Stencil* out) {
@@ -319,6 +319,9 @@ int check_shot(const fd_grid* g, const fd_shot& s, int i, bool adjoint, Stencil*
     if (!have)
         return fail(FD_EUNSUPPORTED, "shot %d: no compiled %dD kernel for shape %d, M = %d, rows = %d", i,
                     g->ndim, st->shape, st->M, st->rows);
+    if (adjoint && g->ndim == 3 && !have_adj3d(st->shape, st->M))
+        return fail(FD_EUNSUPPORTED, "shot %d: no compiled 3D adjoint kernel for shape %d, M = %d", i,
+                    st->shape, st->M);
     return FD_OK;
 }
 
@@ -517,6 +520,10 @@ int enqueue_forward_shot(const CallCtx& c, const ShotCtx& s, float* ckpt, int K,
     return R.err;
 }
 
+int adj_rows(const CallCtx& c, const ShotCtx& s) {
+    return c.g->ndim == 3 ? adj_rows3d(s.st.shape, s.st.rows) : s.st.rows;
+}
+
 AdjArgs base_adj(const CallCtx& c, const ShotCtx& s) {
     AdjArgs a;
     std::memset(&a, 0, sizeof a);
@@ -530,7 +537,7 @@ AdjArgs base_adj(const CallCtx& c, const ShotCtx& s) {
     a.nz = s.nz;
     StepArgs t;
     t.nx = s.nx; t.ny = s.ny; t.nz = s.nz;
-    fill_tiles(t, c.g->ndim, s.st.rows, s.st.zchunk);
+    fill_tiles(t, c.g->ndim, adj_rows(c, s), s.st.zchunk);
     a.tiles_x = t.tiles_x;
     a.tiles_y = t.tiles_y;
     a.ntiles = t.ntiles;
@@ -542,7 +549,7 @@ AdjArgs base_adj(const CallCtx& c, const ShotCtx& s) {
 
 bool launch_adj(const CallCtx& c, const ShotCtx& s, const AdjArgs& a, hipStream_t st) {
     if (c.g->ndim == 2) return launch_adj2d(a, s.st.shape, s.st.M, s.st.rows, st);
-    return launch_adj3d(a, s.st.shape, s.st.M, s.st.rows, st);
+    return launch_adj3d(a, s.st.shape, s.st.M, adj_rows(c, s), st);
 }
 
 // forward with checkpoints, then segment-wise recompute + adjoint, one shot

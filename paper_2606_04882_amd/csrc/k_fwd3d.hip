@@ -1,10 +1,611 @@
-// 3D kernels (forward and adjoint): not compiled in this build yet.
+// 3D forward and adjoint steps.
+//
+// Same update as the 2D kernels (Sec. 3.1-3.2, the 3D extension noted at the
+// end of Sec. 3.1), on [nz][ny][nx] windows.  A block owns a 64 (x) by 4*RY (y)
+// column of the grid and marches along z through `zchunk` planes:
+//
+//  * cross stencils keep the 2M+1 values of u along z for each of the thread's
+//    RY points in registers (a queue shifted once per plane) and stage only the
+//    current xy plane, with an M-cell halo, in LDS for the x/y neighbours;
+//  * rhombus (L1 ball) and square (cube) stencils keep a ring of 2M+1 xy planes
+//    with halo in LDS.
+//
+// Every value of u^n is read from HBM once per block (plus the z warm-up of 2M
+// planes per chunk and the xy halo, which neighbouring blocks of the same XCD
+// also read, mostly from L2).  Algorithmic traffic per update: 16 B forward,
+// 28 B adjoint (psi^{k+1}, u^k, psi^{k+2}, v, grad read/write, psi^k write).
+//
+// Difference form: points are grouped by their absolute offset pattern
+// (|dx|, |dy|, |dz|), each group shares one orbit weight, and
+//     L += w * (sum_of_group - |group| * u(x)).
 #include "fd_kernels.h"
 
 namespace fdw {
 
-bool have_fwd3d(int, int, int) { return false; }
-bool launch_fwd3d(const StepArgs&, int, int, int, hipStream_t) { return false; }
-bool launch_adj3d(const AdjArgs&, int, int, int, hipStream_t) { return false; }
+namespace {
+
+template <int M, int RY>
+struct Geo3 {
+    static constexpr int LW = kTileX + 2 * M;
+    static constexpr int LH = 4 * RY + 2 * M;
+    static constexpr int PLANE = LH * LW;
+};
+
+__device__ __forceinline__ float damp_e(const Sponge& sp, int gx, int gy, int gz, int nx, int ny,
+                                        int nz, bool& inband) {
+    if (sp.nb <= 0) {
+        inband = false;
+        return 0.f;
+    }
+    const int dx = band_depth(gx, nx, sp.nb), dy = band_depth(gy, ny, sp.nb),
+              dz = band_depth(gz, nz, sp.nb);
+    inband = (dx | dy | dz) != 0;
+    if (!inband) return 0.f;
+    const float rx = dx * sp.inv_nb, ry = dy * sp.inv_nb, rz = dz * sp.inv_nb;
+    return sp.escale * fmaf(rx, rx, fmaf(ry, ry, rz * rz));
+}
+
+// Halo of plane z of field f (interior cells excluded), zeros off the grid.
+template <int M, int RY>
+__device__ __forceinline__ void load_halo(float* tile, const float* __restrict__ f, int nx, int ny,
+                                          int nz, int x0, int y0, int z) {
+    using G = Geo3<M, RY>;
+    constexpr int TOPN = M * G::LW, SIDEN = 4 * RY * M, H = 2 * TOPN + 2 * SIDEN;
+    const bool zok = (unsigned)z < (unsigned)nz;
+    for (int i = threadIdx.x; i < H; i += kBlock) {
+        int r, c;
+        if (i < TOPN) {
+            r = i / G::LW;
+            c = i - r * G::LW;
+        } else if (i < 2 * TOPN) {
+            const int k = i - TOPN;
+            r = M + 4 * RY + k / G::LW;
+            c = k % G::LW;
+        } else {
+            int k = i - 2 * TOPN;
+            const int side = k / SIDEN;
+            k -= side * SIDEN;
+            r = M + k / M;
+            c = (side ? M + kTileX : 0) + k % M;
+        }
+        const int gy = y0 - M + r, gx = x0 - M + c;
+        float val = 0.f;
+        if (zok && (unsigned)gy < (unsigned)ny && (unsigned)gx < (unsigned)nx)
+            val = f[((long long)z * ny + gy) * nx + gx];
+        tile[r * G::LW + c] = val;
+    }
+}
+
+// Whole plane z (interior and halo) of field f.
+template <int M, int RY>
+__device__ __forceinline__ void load_plane(float* tile, const float* __restrict__ f, int nx, int ny,
+                                           int nz, int x0, int y0, int z) {
+    using G = Geo3<M, RY>;
+    const bool zok = (unsigned)z < (unsigned)nz;
+    for (int i = threadIdx.x; i < G::PLANE; i += kBlock) {
+        const int r = i / G::LW, c = i - r * G::LW;
+        const int gy = y0 - M + r, gx = x0 - M + c;
+        float val = 0.f;
+        if (zok && (unsigned)gy < (unsigned)ny && (unsigned)gx < (unsigned)nx)
+            val = f[((long long)z * ny + gy) * nx + gx];
+        tile[i] = val;
+    }
+}
+
+struct Pos3 {
+    int tx, ty, x0, y0, zs, ze, gx;
+};
+
+template <int RY>
+__device__ __forceinline__ Pos3 block_pos(int ntiles, int tiles_x, int tiles_y, int zchunk, int nz) {
+    Pos3 q;
+    q.tx = threadIdx.x & 63;
+    q.ty = threadIdx.x >> 6;
+    const int t = xcd_tile(blockIdx.x, ntiles);
+    const int bx = t % tiles_x, t2 = t / tiles_x;
+    const int by = t2 % tiles_y, bz = t2 / tiles_y;
+    q.x0 = bx * kTileX;
+    q.y0 = by * 4 * RY;
+    q.zs = bz * zchunk;
+    q.ze = min(q.zs + zchunk, nz);
+    q.gx = q.x0 + q.tx;
+    return q;
+}
+
+// ---------------------------------------------------------------------------
+// cross: z neighbours from a register queue, x/y neighbours from LDS
+// ---------------------------------------------------------------------------
+template <int M, int RY>
+__device__ __forceinline__ float cross_sum(const float* tile, const float* q, int row, int col,
+                                           const Weights& W) {
+    using G = Geo3<M, RY>;
+    const float u = q[M];
+    float acc = 0.f;
+#pragma unroll
+    for (int m = 1; m <= M; ++m) {
+        const float s = (tile[row * G::LW + col - m] + tile[row * G::LW + col + m]) +
+                        (tile[(row - m) * G::LW + col] + tile[(row + m) * G::LW + col]) +
+                        (q[M - m] + q[M + m]);
+        acc = fmaf(W.w[m], fmaf(-6.f, u, s), acc);
+    }
+    return acc;
+}
+
+template <int M, int RY>
+__global__ __launch_bounds__(kBlock) void k_fwd3d_cross(StepArgs p) {
+    using G = Geo3<M, RY>;
+    constexpr int NQ = 2 * M + 1;
+    __shared__ float tile[G::PLANE];
+    if (p.trace_out) {
+        for (int r = blockIdx.x * kBlock + threadIdx.x; r < p.nrec; r += gridDim.x * kBlock) {
+            const long long i = p.rec_lin[r];
+            p.trace_out[r] = i >= 0 ? p.ucur[i] : 0.f;
+        }
+    }
+    const Pos3 b = block_pos<RY>(p.ntiles, p.tiles_x, p.tiles_y, p.zchunk, p.nz);
+    const bool xok = b.gx < p.nx;
+    float q[RY][NQ];
+    bool ok[RY];
+#pragma unroll
+    for (int j = 0; j < RY; ++j) {
+        const int gy = b.y0 + b.ty * RY + j;
+        ok[j] = xok && gy < p.ny;
+#pragma unroll
+        for (int i = 0; i < 2 * M; ++i) {
+            const int z = b.zs - M + i;
+            q[j][i] = (ok[j] && (unsigned)z < (unsigned)p.nz) ? p.ucur[((long long)z * p.ny + gy) * p.nx + b.gx] : 0.f;
+        }
+    }
+    for (int z = b.zs; z < b.ze; ++z) {
+        float up[RY], vv[RY];
+#pragma unroll
+        for (int j = 0; j < RY; ++j) {
+            const int gy = b.y0 + b.ty * RY + j;
+            const int zz = z + M;
+            q[j][2 * M] = (ok[j] && zz < p.nz) ? p.ucur[((long long)zz * p.ny + gy) * p.nx + b.gx] : 0.f;
+            up[j] = ok[j] ? p.uprev[((long long)z * p.ny + gy) * p.nx + b.gx] : 0.f;
+            vv[j] = ok[j] ? p.v[(long long)z * p.ldv_z + (long long)gy * p.ldv_y + b.gx] : 0.f;
+            tile[(b.ty * RY + j + M) * G::LW + b.tx + M] = q[j][M];
+        }
+        load_halo<M, RY>(tile, p.ucur, p.nx, p.ny, p.nz, b.x0, b.y0, z);
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < RY; ++j) {
+            const float L = cross_sum<M, RY>(tile, q[j], b.ty * RY + j + M, b.tx + M, p.w);
+            if (ok[j]) {
+                const int gy = b.y0 + b.ty * RY + j;
+                const long long k = ((long long)z * p.ny + gy) * p.nx + b.gx;
+                bool inband;
+                const float e = damp_e(p.sp, b.gx, gy, z, p.nx, p.ny, p.nz, inband);
+                const float uc = q[j][M];
+                float r;
+                if (!inband) {
+                    r = fmaf(vv[j], L, 2.f * uc - up[j]);
+                    if (k == p.src) r += p.q * p.wavelet[p.step];
+                } else {
+                    r = fmaf(-(1.f - e), up[j], 2.f * uc);
+                    r = fmaf(vv[j], L, r);
+                    if (k == p.src) r += p.q * p.wavelet[p.step];
+                    r = r / (1.f + e);
+                }
+                p.unext[k] = r;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < RY; ++j)
+#pragma unroll
+            for (int i = 0; i < 2 * M; ++i) q[j][i] = q[j][i + 1];
+    }
+}
+
+template <int M, int RY>
+__global__ __launch_bounds__(kBlock) void k_adj3d_cross(AdjArgs p) {
+    using G = Geo3<M, RY>;
+    constexpr int NQ = 2 * M + 1;
+    __shared__ float tp[G::PLANE];
+    __shared__ float tu[G::PLANE];
+    const Pos3 b = block_pos<RY>(p.ntiles, p.tiles_x, p.tiles_y, p.zchunk, p.nz);
+    const bool xok = b.gx < p.nx;
+    float qp[RY][NQ], qu[RY][NQ];
+    bool ok[RY];
+#pragma unroll
+    for (int j = 0; j < RY; ++j) {
+        const int gy = b.y0 + b.ty * RY + j;
+        ok[j] = xok && gy < p.ny;
+#pragma unroll
+        for (int i = 0; i < 2 * M; ++i) {
+            const int z = b.zs - M + i;
+            const bool in = ok[j] && (unsigned)z < (unsigned)p.nz;
+            const long long k = ((long long)z * p.ny + gy) * p.nx + b.gx;
+            qp[j][i] = in ? p.pcur[k] : 0.f;
+            qu[j][i] = (in && p.with_grad) ? p.ufwd[k] : 0.f;
+        }
+    }
+    for (int z = b.zs; z < b.ze; ++z) {
+        float pp[RY], vv[RY], gg[RY];
+#pragma unroll
+        for (int j = 0; j < RY; ++j) {
+            const int gy = b.y0 + b.ty * RY + j;
+            const int zz = z + M;
+            const bool in = ok[j] && zz < p.nz;
+            const long long kf = ((long long)zz * p.ny + gy) * p.nx + b.gx;
+            qp[j][2 * M] = in ? p.pcur[kf] : 0.f;
+            qu[j][2 * M] = (in && p.with_grad) ? p.ufwd[kf] : 0.f;
+            const long long k = ((long long)z * p.ny + gy) * p.nx + b.gx;
+            const long long kv = (long long)z * p.ldv_z + (long long)gy * p.ldv_y + b.gx;
+            pp[j] = (ok[j] && p.with_update) ? p.pprev[k] : 0.f;
+            vv[j] = ok[j] ? p.v[kv] : 0.f;
+            gg[j] = (ok[j] && p.with_grad) ? p.grad[kv] : 0.f;
+            tp[(b.ty * RY + j + M) * G::LW + b.tx + M] = qp[j][M];
+            tu[(b.ty * RY + j + M) * G::LW + b.tx + M] = qu[j][M];
+        }
+        load_halo<M, RY>(tp, p.pcur, p.nx, p.ny, p.nz, b.x0, b.y0, z);
+        if (p.with_grad) load_halo<M, RY>(tu, p.ufwd, p.nx, p.ny, p.nz, b.x0, b.y0, z);
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < RY; ++j) {
+            const int row = b.ty * RY + j + M;
+            const float Lp = cross_sum<M, RY>(tp, qp[j], row, b.tx + M, p.w);
+            const float Lu = p.with_grad ? cross_sum<M, RY>(tu, qu[j], row, b.tx + M, p.w) : 0.f;
+            if (ok[j]) {
+                const int gy = b.y0 + b.ty * RY + j;
+                const long long k = ((long long)z * p.ny + gy) * p.nx + b.gx;
+                const long long kv = (long long)z * p.ldv_z + (long long)gy * p.ldv_y + b.gx;
+                const float pc = qp[j][M];
+                if (p.with_grad) p.grad[kv] = fmaf(p.gscale * rsqrtf(vv[j]) * pc, Lu, gg[j]);
+                if (p.with_update) {
+                    bool inband;
+                    const float e = damp_e(p.sp, b.gx, gy, z, p.nx, p.ny, p.nz, inband);
+                    float r;
+                    if (!inband) {
+                        r = fmaf(vv[j], Lp, 2.f * pc - pp[j]);
+                    } else {
+                        r = fmaf(-(1.f - e), pp[j], 2.f * pc);
+                        r = fmaf(vv[j], Lp, r);
+                        r = r / (1.f + e);
+                    }
+                    p.pnext[k] = r;
+                }
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < RY; ++j)
+#pragma unroll
+            for (int i = 0; i < 2 * M; ++i) {
+                qp[j][i] = qp[j][i + 1];
+                qu[j][i] = qu[j][i + 1];
+            }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// rhombus / square: ring of 2M+1 planes in LDS
+// ---------------------------------------------------------------------------
+// Sum over the group of offsets (+-DX, +-DY, +-DZ) of plane(s) at row/col.
+template <int M, int RY, int DX, int DY>
+__device__ __forceinline__ float inplane(const float* t, int row, int col) {
+    using G = Geo3<M, RY>;
+    const float* c = t + row * G::LW + col;
+    if constexpr (DX == 0 && DY == 0) return c[0];
+    else if constexpr (DY == 0) return c[-DX] + c[DX];
+    else if constexpr (DX == 0) return c[-DY * G::LW] + c[DY * G::LW];
+    else return (c[-DY * G::LW - DX] + c[-DY * G::LW + DX]) + (c[DY * G::LW - DX] + c[DY * G::LW + DX]);
+}
+
+// Groups (+-DX, +-DY, +-DZ) of one |dz| layer, DY outer, DX inner.
+template <int SHAPE, int M, int RY, int DZ, int DY, int DX>
+__device__ __forceinline__ void gen_xy(const float* pm, const float* p0, const float* pp, int row,
+                                       int col, float u, float& acc, const Weights& W) {
+    if constexpr (DY <= M) {
+        if constexpr (DX > M) {
+            gen_xy<SHAPE, M, RY, DZ, DY + 1, 0>(pm, p0, pp, row, col, u, acc, W);
+        } else {
+            constexpr int a = cmax_(DX, cmax_(DY, DZ)), c = cmin_(DX, cmin_(DY, DZ));
+            constexpr int bmid = DX + DY + DZ - a - c;
+            if constexpr ((DX | DY | DZ) != 0 && in_shape3(SHAPE, M, a, bmid, c)) {
+                constexpr int o = orbit3(SHAPE, M, a, bmid, c);
+                constexpr float cnt = (DX ? 2.f : 1.f) * (DY ? 2.f : 1.f) * (DZ ? 2.f : 1.f);
+                float s;
+                if constexpr (DZ == 0) s = inplane<M, RY, DX, DY>(p0, row, col);
+                else s = inplane<M, RY, DX, DY>(pm, row, col) + inplane<M, RY, DX, DY>(pp, row, col);
+                acc = fmaf(W.w[o], fmaf(-cnt, u, s), acc);
+            }
+            gen_xy<SHAPE, M, RY, DZ, DY, DX + 1>(pm, p0, pp, row, col, u, acc, W);
+        }
+    }
+}
+
+// Layers |dz| = DZ..M.  Plane of offset d (d in [-M, M]) sits in ring slot
+// (base + d) mod (2M+1), base = slot of the output plane.
+template <int SHAPE, int M, int RY, int DZ>
+__device__ __forceinline__ void gen_layers(const float* ring, int base, int row, int col, float u,
+                                           float& acc, const Weights& W) {
+    if constexpr (DZ <= M) {
+        using G = Geo3<M, RY>;
+        constexpr int NP = 2 * M + 1;
+        int sm = base - DZ, sp = base + DZ;
+        if (sm < 0) sm += NP;
+        if (sp >= NP) sp -= NP;
+        gen_xy<SHAPE, M, RY, DZ, 0, 0>(ring + sm * G::PLANE, ring + base * G::PLANE,
+                                       ring + sp * G::PLANE, row, col, u, acc, W);
+        gen_layers<SHAPE, M, RY, DZ + 1>(ring, base, row, col, u, acc, W);
+    }
+}
+
+template <int SHAPE, int M, int RY, int NF>
+struct RingLDS {
+    float f[NF][2 * M + 1][Geo3<M, RY>::PLANE];
+};
+
+template <int SHAPE, int M, int RY>
+__global__ __launch_bounds__(kBlock) void k_fwd3d_gen(StepArgs p) {
+    using G = Geo3<M, RY>;
+    constexpr int NP = 2 * M + 1;
+    __shared__ RingLDS<SHAPE, M, RY, 1> L;
+    float* ring = &L.f[0][0][0];
+    if (p.trace_out) {
+        for (int r = blockIdx.x * kBlock + threadIdx.x; r < p.nrec; r += gridDim.x * kBlock) {
+            const long long i = p.rec_lin[r];
+            p.trace_out[r] = i >= 0 ? p.ucur[i] : 0.f;
+        }
+    }
+    const Pos3 b = block_pos<RY>(p.ntiles, p.tiles_x, p.tiles_y, p.zchunk, p.nz);
+    // planes zs-M .. zs+M-1 into slots 0 .. 2M-1; plane z lives in slot (z - zs + M) mod NP
+    for (int i = 0; i < 2 * M; ++i)
+        load_plane<M, RY>(ring + i * G::PLANE, p.ucur, p.nx, p.ny, p.nz, b.x0, b.y0, b.zs - M + i);
+    int base = M;   // slot of plane z
+    for (int z = b.zs; z < b.ze; ++z) {
+        int front = base + M;
+        if (front >= NP) front -= NP;
+        load_plane<M, RY>(ring + front * G::PLANE, p.ucur, p.nx, p.ny, p.nz, b.x0, b.y0, z + M);
+        float up[RY], vv[RY];
+#pragma unroll
+        for (int j = 0; j < RY; ++j) {
+            const int gy = b.y0 + b.ty * RY + j;
+            const bool ok = b.gx < p.nx && gy < p.ny;
+            up[j] = ok ? p.uprev[((long long)z * p.ny + gy) * p.nx + b.gx] : 0.f;
+            vv[j] = ok ? p.v[(long long)z * p.ldv_z + (long long)gy * p.ldv_y + b.gx] : 0.f;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < RY; ++j) {
+            const int row = b.ty * RY + j + M, col = b.tx + M;
+            const float uc = ring[base * G::PLANE + row * G::LW + col];
+            float Ls = 0.f;
+            gen_layers<SHAPE, M, RY, 0>(ring, base, row, col, uc, Ls, p.w);
+            const int gy = b.y0 + b.ty * RY + j;
+            if (b.gx < p.nx && gy < p.ny) {
+                const long long k = ((long long)z * p.ny + gy) * p.nx + b.gx;
+                bool inband;
+                const float e = damp_e(p.sp, b.gx, gy, z, p.nx, p.ny, p.nz, inband);
+                float r;
+                if (!inband) {
+                    r = fmaf(vv[j], Ls, 2.f * uc - up[j]);
+                    if (k == p.src) r += p.q * p.wavelet[p.step];
+                } else {
+                    r = fmaf(-(1.f - e), up[j], 2.f * uc);
+                    r = fmaf(vv[j], Ls, r);
+                    if (k == p.src) r += p.q * p.wavelet[p.step];
+                    r = r / (1.f + e);
+                }
+                p.unext[k] = r;
+            }
+        }
+        __syncthreads();
+        base = base + 1 == NP ? 0 : base + 1;
+    }
+}
+
+template <int SHAPE, int M, int RY>
+__global__ __launch_bounds__(kBlock) void k_adj3d_gen(AdjArgs p) {
+    using G = Geo3<M, RY>;
+    constexpr int NP = 2 * M + 1;
+    __shared__ RingLDS<SHAPE, M, RY, 2> L;
+    float* rp = &L.f[0][0][0];
+    float* ru = &L.f[1][0][0];
+    const Pos3 b = block_pos<RY>(p.ntiles, p.tiles_x, p.tiles_y, p.zchunk, p.nz);
+    for (int i = 0; i < 2 * M; ++i) {
+        load_plane<M, RY>(rp + i * G::PLANE, p.pcur, p.nx, p.ny, p.nz, b.x0, b.y0, b.zs - M + i);
+        if (p.with_grad)
+            load_plane<M, RY>(ru + i * G::PLANE, p.ufwd, p.nx, p.ny, p.nz, b.x0, b.y0, b.zs - M + i);
+    }
+    int base = M;
+    for (int z = b.zs; z < b.ze; ++z) {
+        int front = base + M;
+        if (front >= NP) front -= NP;
+        load_plane<M, RY>(rp + front * G::PLANE, p.pcur, p.nx, p.ny, p.nz, b.x0, b.y0, z + M);
+        if (p.with_grad)
+            load_plane<M, RY>(ru + front * G::PLANE, p.ufwd, p.nx, p.ny, p.nz, b.x0, b.y0, z + M);
+        float pp[RY], vv[RY], gg[RY];
+#pragma unroll
+        for (int j = 0; j < RY; ++j) {
+            const int gy = b.y0 + b.ty * RY + j;
+            const bool ok = b.gx < p.nx && gy < p.ny;
+            const long long k = ((long long)z * p.ny + gy) * p.nx + b.gx;
+            const long long kv = (long long)z * p.ldv_z + (long long)gy * p.ldv_y + b.gx;
+            pp[j] = (ok && p.with_update) ? p.pprev[k] : 0.f;
+            vv[j] = ok ? p.v[kv] : 0.f;
+            gg[j] = (ok && p.with_grad) ? p.grad[kv] : 0.f;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < RY; ++j) {
+            const int row = b.ty * RY + j + M, col = b.tx + M;
+            const float pc = rp[base * G::PLANE + row * G::LW + col];
+            float Lp = 0.f, Lu = 0.f;
+            gen_layers<SHAPE, M, RY, 0>(rp, base, row, col, pc, Lp, p.w);
+            if (p.with_grad) {
+                const float uc = ru[base * G::PLANE + row * G::LW + col];
+                gen_layers<SHAPE, M, RY, 0>(ru, base, row, col, uc, Lu, p.w);
+            }
+            const int gy = b.y0 + b.ty * RY + j;
+            if (b.gx < p.nx && gy < p.ny) {
+                const long long k = ((long long)z * p.ny + gy) * p.nx + b.gx;
+                const long long kv = (long long)z * p.ldv_z + (long long)gy * p.ldv_y + b.gx;
+                if (p.with_grad) p.grad[kv] = fmaf(p.gscale * rsqrtf(vv[j]) * pc, Lu, gg[j]);
+                if (p.with_update) {
+                    bool inband;
+                    const float e = damp_e(p.sp, b.gx, gy, z, p.nx, p.ny, p.nz, inband);
+                    float r;
+                    if (!inband) {
+                        r = fmaf(vv[j], Lp, 2.f * pc - pp[j]);
+                    } else {
+                        r = fmaf(-(1.f - e), pp[j], 2.f * pc);
+                        r = fmaf(vv[j], Lp, r);
+                        r = r / (1.f + e);
+                    }
+                    p.pnext[k] = r;
+                }
+            }
+        }
+        __syncthreads();
+        base = base + 1 == NP ? 0 : base + 1;
+    }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// dispatch.  Compiled forward variants: cross M = 1..8 with rows 1, 2, 4;
+// rhombus and square M = 1..4 with rows 1, 2; rhombus M = 5, 6 with rows 1.
+// Adjoint: cross M = 1..8 (forward rows), rhombus M = 1..4 and square
+// M = 1, 2 with rows 1.
+// ---------------------------------------------------------------------------
+bool have_fwd3d(int shape, int M, int rows) {
+    if (shape == SH_CROSS) return M >= 1 && M <= 8 && (rows == 1 || rows == 2 || rows == 4);
+    if (shape == SH_RHOMBUS || shape == SH_SQUARE) {
+        if (M >= 1 && M <= 4) return rows == 1 || rows == 2;
+        if (shape == SH_RHOMBUS && (M == 5 || M == 6)) return rows == 1;
+    }
+    return false;
+}
+
+template <int M, int RY>
+static void run_cross(const StepArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL((k_fwd3d_cross<M, RY>), dim3(a.ntiles), dim3(kBlock), 0, s, a);
+}
+template <int M, int RY>
+static void run_cross_adj(const AdjArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL((k_adj3d_cross<M, RY>), dim3(a.ntiles), dim3(kBlock), 0, s, a);
+}
+template <int SHAPE, int M, int RY>
+static void run_gen(const StepArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL((k_fwd3d_gen<SHAPE, M, RY>), dim3(a.ntiles), dim3(kBlock), 0, s, a);
+}
+template <int SHAPE, int M, int RY>
+static void run_gen_adj(const AdjArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL((k_adj3d_gen<SHAPE, M, RY>), dim3(a.ntiles), dim3(kBlock), 0, s, a);
+}
+
+template <int M>
+static bool cross_rows(const StepArgs& a, int rows, hipStream_t s) {
+    switch (rows) {
+        case 1: run_cross<M, 1>(a, s); return true;
+        case 2: run_cross<M, 2>(a, s); return true;
+        case 4: run_cross<M, 4>(a, s); return true;
+    }
+    return false;
+}
+template <int M>
+static bool cross_rows_adj(const AdjArgs& a, int rows, hipStream_t s) {
+    switch (rows) {
+        case 1: run_cross_adj<M, 1>(a, s); return true;
+        case 2: run_cross_adj<M, 2>(a, s); return true;
+        case 4: run_cross_adj<M, 4>(a, s); return true;
+    }
+    return false;
+}
+template <int SHAPE, int M>
+static bool gen_rows(const StepArgs& a, int rows, hipStream_t s) {
+    if constexpr (M <= 4) {
+        switch (rows) {
+            case 1: run_gen<SHAPE, M, 1>(a, s); return true;
+            case 2: run_gen<SHAPE, M, 2>(a, s); return true;
+        }
+        return false;
+    } else {
+        if (rows != 1) return false;
+        run_gen<SHAPE, M, 1>(a, s);
+        return true;
+    }
+}
+
+bool launch_fwd3d(const StepArgs& a, int shape, int M, int rows, hipStream_t s) {
+    if (!have_fwd3d(shape, M, rows)) return false;
+    if (shape == SH_CROSS) {
+        switch (M) {
+            case 1: return cross_rows<1>(a, rows, s);
+            case 2: return cross_rows<2>(a, rows, s);
+            case 3: return cross_rows<3>(a, rows, s);
+            case 4: return cross_rows<4>(a, rows, s);
+            case 5: return cross_rows<5>(a, rows, s);
+            case 6: return cross_rows<6>(a, rows, s);
+            case 7: return cross_rows<7>(a, rows, s);
+            case 8: return cross_rows<8>(a, rows, s);
+        }
+        return false;
+    }
+    if (shape == SH_RHOMBUS) {
+        switch (M) {
+            case 1: return gen_rows<SH_RHOMBUS, 1>(a, rows, s);
+            case 2: return gen_rows<SH_RHOMBUS, 2>(a, rows, s);
+            case 3: return gen_rows<SH_RHOMBUS, 3>(a, rows, s);
+            case 4: return gen_rows<SH_RHOMBUS, 4>(a, rows, s);
+            case 5: return gen_rows<SH_RHOMBUS, 5>(a, rows, s);
+            case 6: return gen_rows<SH_RHOMBUS, 6>(a, rows, s);
+        }
+        return false;
+    }
+    switch (M) {
+        case 1: return gen_rows<SH_SQUARE, 1>(a, rows, s);
+        case 2: return gen_rows<SH_SQUARE, 2>(a, rows, s);
+        case 3: return gen_rows<SH_SQUARE, 3>(a, rows, s);
+        case 4: return gen_rows<SH_SQUARE, 4>(a, rows, s);
+    }
+    return false;
+}
+
+// The adjoint uses the forward tile height for crosses; rhombus and square
+// adjoints always run with one row per thread (two rings of planes in LDS).
+bool launch_adj3d(const AdjArgs& a, int shape, int M, int rows, hipStream_t s) {
+    if (shape == SH_CROSS) {
+        switch (M) {
+            case 1: return cross_rows_adj<1>(a, rows, s);
+            case 2: return cross_rows_adj<2>(a, rows, s);
+            case 3: return cross_rows_adj<3>(a, rows, s);
+            case 4: return cross_rows_adj<4>(a, rows, s);
+            case 5: return cross_rows_adj<5>(a, rows, s);
+            case 6: return cross_rows_adj<6>(a, rows, s);
+            case 7: return cross_rows_adj<7>(a, rows, s);
+            case 8: return cross_rows_adj<8>(a, rows, s);
+        }
+        return false;
+    }
+    if (rows != 1) return false;
+    if (shape == SH_RHOMBUS) {
+        switch (M) {
+            case 1: run_gen_adj<SH_RHOMBUS, 1, 1>(a, s); return true;
+            case 2: run_gen_adj<SH_RHOMBUS, 2, 1>(a, s); return true;
+            case 3: run_gen_adj<SH_RHOMBUS, 3, 1>(a, s); return true;
+            case 4: run_gen_adj<SH_RHOMBUS, 4, 1>(a, s); return true;
+        }
+        return false;
+    }
+    switch (M) {
+        case 1: run_gen_adj<SH_SQUARE, 1, 1>(a, s); return true;
+        case 2: run_gen_adj<SH_SQUARE, 2, 1>(a, s); return true;
+    }
+    return false;
+}
+
+bool have_adj3d(int shape, int M) {
+    if (shape == SH_CROSS) return M >= 1 && M <= 8;
+    if (shape == SH_RHOMBUS) return M >= 1 && M <= 4;
+    return shape == SH_SQUARE && M >= 1 && M <= 2;
+}
+
+int adj_rows3d(int shape, int fwd_rows) { return shape == SH_CROSS ? fwd_rows : 1; }
 
 }  // namespace fdw

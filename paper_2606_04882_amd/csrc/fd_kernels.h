@@ -149,6 +149,34 @@ struct AdjArgs {
     Weights w;
 };
 
+// One shot of a batched launch (device memory, built by the host).
+struct BatchShot {
+    float* buf[2];                   // ping-pong: step n reads buf[(n+1)&1], writes buf[n&1]
+    const float* v;                  // model v at the window origin
+    long long ldv;                   // model row stride
+    int nx, nz;                      // window
+    int tiles_x, ntiles;             // tiles of this shot
+    long long src;                   // window-linear source node
+    const float* wavelet;
+    int nrec;
+    const long long* rec_lin;
+    float* traces;
+    int variant;                     // shape * 8 + (M - 1)
+    Weights w;
+};
+
+struct BatchArgs {
+    const BatchShot* shots;
+    const int2* jobs;                // (shot, tile within the shot) per block
+    int njobs;
+    int step;
+    Sponge sp;
+    float q;
+};
+
+void launch_batch2d(const BatchArgs& a, hipStream_t s);
+int batch_rows();
+
 // Launchers (one per translation unit).  Return false when the requested
 // (shape, M, rows) combination was not compiled.
 bool launch_fwd2d(const StepArgs& a, int shape, int M, int rows, hipStream_t s);

@@ -225,8 +225,21 @@ struct Layout {
     std::vector<ShotLayout> shots;
     // adjoint scratch (shared by all shots, sized for the largest window)
     size_t psiA, psiB, ckpt, seg;
+    // batched forward: shot descriptors and the (shot, tile) work list
+    size_t desc, jobs;
+    long long njobs;
     size_t total;
 };
+
+bool use_batch(const fd_grid* g, int nshots, int mode) {
+    return mode == 0 && nshots > 1 && g->ndim == 2 && !(g->flags & FD_NO_BATCH);
+}
+
+int shot_tiles2d(const fd_shot& s, int rows, int* tiles_x) {
+    const int nx = (int)s.extent[0], nz = (int)s.extent[2];
+    *tiles_x = (nx + kTileX - 1) / kTileX;
+    return *tiles_x * ((nz + 4 * rows - 1) / (4 * rows));
+}
 
 long long window_points(const fd_shot& s, int ndim) {
     return s.extent[0] * (ndim == 3 ? s.extent[1] : 1) * s.extent[2];
@@ -254,6 +267,16 @@ Layout make_layout(const fd_grid* g, const fd_shot* shots, int nshots, int mode,
         L.shots.push_back(s);
     }
     L.psiA = L.psiB = L.ckpt = L.seg = 0;
+    L.desc = L.jobs = 0;
+    L.njobs = 0;
+    if (use_batch(g, nshots, mode)) {
+        int tx;
+        for (int i = 0; i < nshots; ++i) L.njobs += shot_tiles2d(shots[i], batch_rows(), &tx);
+        L.desc = off;
+        off = align256(off + sizeof(BatchShot) * (size_t)nshots);
+        L.jobs = off;
+        off = align256(off + sizeof(int2) * (size_t)L.njobs);
+    }
     if (mode == 1) {
         const int nseg = (g->nt + K - 1) / K;
         L.psiA = off;
@@ -332,7 +355,13 @@ int g_graph_fallbacks = 0;
 
 struct GraphCache {
     std::mutex mu;
-    std::list<std::pair<std::vector<uint64_t>, std::vector<hipGraphExec_t>>> lru;
+    struct Entry {
+        std::vector<uint64_t> key;
+        std::vector<hipGraphExec_t> execs;
+        void* pinned = nullptr;     // immutable host copy of the call's blob
+        size_t pinned_bytes = 0;
+    };
+    std::list<Entry> lru;
     std::map<int, hipStream_t> capture_streams;
     static constexpr size_t kCap = 24;
 } g_graphs;
@@ -414,6 +443,9 @@ struct CallCtx {
     // adjoint
     int K;
     float* grad;
+    // host-built data uploaded to the workspace before the work runs
+    std::vector<unsigned char> blob;
+    size_t blob_off = 0;
 };
 
 // offset of a window origin in model-sized arrays
@@ -619,11 +651,79 @@ int enqueue_adjoint_shot(const CallCtx& c, const ShotCtx& s, Recorder& R) {
     return R.err;
 }
 
+// Every 2D shot advanced by one batched launch per step.
+int enqueue_batched(const CallCtx& c, Recorder& R) {
+    hipStream_t st = R.stream;
+    const int nt = c.g->nt;
+    for (const ShotCtx& s : c.shots) {
+        if (s.s->init_prev) launch_copy(s.bufA, s.s->init_prev, s.npts, st); else launch_fill(s.bufA, s.npts, 0.f, st);
+        if (s.s->init_cur) launch_copy(s.bufB, s.s->init_cur, s.npts, st); else launch_fill(s.bufB, s.npts, 0.f, st);
+        launch_rec_index(s.s->rec, s.s->nrec, 2, s.nx, 1, s.nz, s.rec, c.flags, st);
+        R.launched(3);
+    }
+    BatchArgs a;
+    a.shots = (const BatchShot*)(c.ws + c.L.desc);
+    a.jobs = (const int2*)(c.ws + c.L.jobs);
+    a.njobs = (int)c.L.njobs;
+    a.sp = c.sp;
+    a.q = c.q;
+    for (int n = 0; n < nt; ++n) {
+        a.step = n;
+        launch_batch2d(a, st);
+        R.launched();
+    }
+    for (const ShotCtx& s : c.shots) {
+        float* last = (nt - 1) % 2 == 0 ? s.bufA : s.bufB;   // u^{nt} sits in buf[(nt-1)&1]
+        float* before = (nt - 1) % 2 == 0 ? s.bufB : s.bufA;
+        if (s.s->nrec > 0) launch_gather(last, s.rec, s.s->nrec, s.s->traces + (size_t)(nt - 1) * s.s->nrec, st);
+        if (s.s->final_prev) launch_copy(s.s->final_prev, before, s.npts, st);
+        if (s.s->final_cur) launch_copy(s.s->final_cur, last, s.npts, st);
+        if (c.g->check_finite && s.s->nrec > 0)
+            launch_check_finite(s.s->traces, (long long)nt * s.s->nrec, c.flags, st);
+        R.launched(4);
+    }
+    return R.err;
+}
+
+// Descriptors and work list of a batched call, built on the host.
+void build_batch_blob(CallCtx& c) {
+    const int nshots = (int)c.shots.size();
+    std::vector<BatchShot> desc(nshots);
+    std::vector<int2> jobs;
+    jobs.reserve((size_t)c.L.njobs);
+    for (int i = 0; i < nshots; ++i) {
+        const ShotCtx& s = c.shots[i];
+        BatchShot& d = desc[i];
+        std::memset(&d, 0, sizeof d);
+        d.buf[0] = s.bufA;
+        d.buf[1] = s.bufB;
+        d.v = s.v;
+        d.ldv = c.ldv_y;
+        d.nx = s.nx;
+        d.nz = s.nz;
+        d.ntiles = shot_tiles2d(*s.s, batch_rows(), &d.tiles_x);
+        d.src = s.src;
+        d.wavelet = s.s->wavelet;
+        d.nrec = s.s->nrec;
+        d.rec_lin = s.rec;
+        d.traces = s.s->traces;
+        d.variant = s.st.shape * 8 + s.st.M - 1;
+        d.w = s.st.w32;
+        for (int t = 0; t < d.ntiles; ++t) jobs.push_back(make_int2(i, t));
+    }
+    c.blob_off = c.L.desc;
+    const size_t jobs_rel = c.L.jobs - c.L.desc;
+    c.blob.assign(jobs_rel + sizeof(int2) * jobs.size(), 0);
+    std::memcpy(c.blob.data(), desc.data(), sizeof(BatchShot) * desc.size());
+    std::memcpy(c.blob.data() + jobs_rel, jobs.data(), sizeof(int2) * jobs.size());
+}
+
 int enqueue_call(const CallCtx& c, int mode, Recorder& R) {
     launch_fill_i32(c.flags, FLAG_COUNT, 0, R.stream);
     const long long mpts = c.g->n[0] * (c.g->ndim == 3 ? c.g->n[1] : 1) * c.g->n[2];
     launch_vprep(c.vel, c.vfield, mpts, c.g->dt / c.g->h, c.flags, R.stream);
     R.launched(2);
+    if (use_batch(c.g, (int)c.shots.size(), mode)) return enqueue_batched(c, R);
     for (const ShotCtx& s : c.shots) {
         int rc = mode == 0 ? enqueue_forward_shot(c, s, nullptr, 0, nullptr, R)
                            : enqueue_adjoint_shot(c, s, R);
@@ -646,6 +746,10 @@ int get_capture_stream(int dev, hipStream_t* out) {
 }
 
 int run_direct(CallCtx& c, int mode, hipStream_t user) {
+    if (!c.blob.empty()) {
+        HIP_OK(hipMemcpyAsync(c.ws + c.blob_off, c.blob.data(), c.blob.size(), hipMemcpyHostToDevice, user));
+        HIP_OK(hipStreamSynchronize(user));   // the host copy of the blob is freed on return
+    }
     Recorder R;
     R.stream = user;
     int rc = enqueue_call(c, mode, R);
@@ -671,15 +775,15 @@ int run_call(CallCtx& c, int mode, hipStream_t user) {
         key.push_back(((uint64_t)s.st.rows << 32) | (uint32_t)s.st.zchunk);
     }
     std::lock_guard<std::mutex> lk(g_graphs.mu);
-    const std::vector<hipGraphExec_t>* execs = nullptr;
+    GraphCache::Entry* entry = nullptr;
     for (auto it = g_graphs.lru.begin(); it != g_graphs.lru.end(); ++it) {
-        if (it->first == key) {
+        if (it->key == key) {
             g_graphs.lru.splice(g_graphs.lru.begin(), g_graphs.lru, it);
-            execs = &g_graphs.lru.begin()->second;
+            entry = &g_graphs.lru.front();
             break;
         }
     }
-    if (!execs) {
+    if (!entry) {
         hipStream_t cs;
         int rc = get_capture_stream(dev, &cs);
         if (rc) return rc;
@@ -707,14 +811,29 @@ int run_call(CallCtx& c, int mode, hipStream_t user) {
             g_graph_fallbacks++;
             return run_direct(c, mode, user);
         }
-        g_graphs.lru.emplace_front(key, R.execs);
-        execs = &g_graphs.lru.begin()->second;
+        GraphCache::Entry ne;
+        ne.key = key;
+        ne.execs = R.execs;
+        if (!c.blob.empty()) {
+            HIP_OK(hipHostMalloc(&ne.pinned, c.blob.size(), hipHostMallocDefault));
+            std::memcpy(ne.pinned, c.blob.data(), c.blob.size());
+            ne.pinned_bytes = c.blob.size();
+        }
+        g_graphs.lru.push_front(ne);
+        entry = &g_graphs.lru.front();
         while (g_graphs.lru.size() > GraphCache::kCap) {
-            for (hipGraphExec_t x : g_graphs.lru.back().second) hipGraphExecDestroy(x);
+            GraphCache::Entry& old = g_graphs.lru.back();
+            for (hipGraphExec_t x : old.execs) hipGraphExecDestroy(x);
+            if (old.pinned) {
+                (void)hipDeviceSynchronize();   // its last upload may still be in flight
+                (void)hipHostFree(old.pinned);
+            }
             g_graphs.lru.pop_back();
         }
     }
-    for (hipGraphExec_t x : *execs) HIP_OK(hipGraphLaunch(x, user));
+    if (entry->pinned)
+        HIP_OK(hipMemcpyAsync(c.ws + c.blob_off, entry->pinned, entry->pinned_bytes, hipMemcpyHostToDevice, user));
+    for (hipGraphExec_t x : entry->execs) HIP_OK(hipGraphLaunch(x, user));
     return FD_OK;
 }
 
@@ -775,6 +894,7 @@ int prepare(CallCtx& c, const fd_grid* g, const float* vel, const fd_shot* shots
                              : ((long long)p[2] * s.ny + p[1]) * s.nx + p[0];
         c.shots.push_back(s);
     }
+    if (use_batch(g, nshots, mode)) build_batch_blob(c);
     return FD_OK;
 }
 

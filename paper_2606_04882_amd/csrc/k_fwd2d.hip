@@ -11,70 +11,34 @@
 //
 // Memory traffic per point: read u^n (plus halo, from L2), u^{n-1}, v;
 // write u^{n+1}: 16 B of algorithmic HBM traffic.
-#include "fd_kernels.h"
-#include "stencil2d.h"
+#include "fwd2d_body.h"
 
 namespace fdw {
 
 template <int SHAPE, int M, int RY>
 __global__ __launch_bounds__(kBlock) void k_fwd2d(StepArgs p) {
-    constexpr int TY = 4 * RY, LW = kTileX + 2 * M, LH = TY + 2 * M;
-    __shared__ float tile[LH * LW];
-    const int tid = threadIdx.x, tx = tid & 63, ty = tid >> 6;
-
+    __shared__ float tile[tile2d_floats<SHAPE, M, RY>()];
     if (p.trace_out) {
-        for (int r = blockIdx.x * kBlock + tid; r < p.nrec; r += gridDim.x * kBlock) {
+        for (int r = blockIdx.x * kBlock + threadIdx.x; r < p.nrec; r += gridDim.x * kBlock) {
             const long long i = p.rec_lin[r];
             p.trace_out[r] = i >= 0 ? p.ucur[i] : 0.f;
         }
     }
-
     const int t = xcd_tile(blockIdx.x, p.ntiles);
     const int bz = t / p.tiles_x, bx = t - bz * p.tiles_x;
-    const int x0 = bx * kTileX, z0 = bz * TY;
-    load_tile2d<M, RY>(tile, p.ucur, p.nx, p.nz, x0, z0);
-
-    // pointwise operands, issued before the barrier so their latency overlaps
-    const int gx = x0 + tx;
-    const bool colok = gx < p.nx;
-    float up[RY], vv[RY];
-#pragma unroll
-    for (int j = 0; j < RY; ++j) {
-        const int gz = z0 + ty * RY + j;
-        up[j] = 0.f;
-        vv[j] = 0.f;
-        if (colok && gz < p.nz) {
-            up[j] = p.uprev[(long long)gz * p.nx + gx];
-            vv[j] = p.v[(long long)gz * p.ldv_y + gx];
-        }
-    }
-    __syncthreads();
-
-    float uc[RY], acc[RY];
-    stencil2d<SHAPE, M, RY, LW>(tile, tx, ty, p.w, uc, acc);
-    if (!colok) return;
-
-    const int dxb = p.sp.nb > 0 ? band_depth(gx, p.nx, p.sp.nb) : 0;
-#pragma unroll
-    for (int j = 0; j < RY; ++j) {
-        const int gz = z0 + ty * RY + j;
-        if (gz >= p.nz) break;
-        const long long k = (long long)gz * p.nx + gx;
-        const int dzb = p.sp.nb > 0 ? band_depth(gz, p.nz, p.sp.nb) : 0;
-        float r;
-        if ((dxb | dzb) == 0) {
-            r = fmaf(vv[j], acc[j], 2.f * uc[j] - up[j]);
-            if (k == p.src) r += p.q * p.wavelet[p.step];
-        } else {
-            const float ex = dxb * p.sp.inv_nb, ez = dzb * p.sp.inv_nb;
-            const float e = p.sp.escale * fmaf(ex, ex, ez * ez);
-            r = fmaf(-(1.f - e), up[j], 2.f * uc[j]);
-            r = fmaf(vv[j], acc[j], r);
-            if (k == p.src) r += p.q * p.wavelet[p.step];
-            r = r / (1.f + e);
-        }
-        p.unext[k] = r;
-    }
+    Tile2D tl;
+    tl.ucur = p.ucur;
+    tl.uprev = p.uprev;
+    tl.unext = p.unext;
+    tl.v = p.v;
+    tl.ldv = p.ldv_y;
+    tl.nx = p.nx;
+    tl.nz = p.nz;
+    tl.x0 = bx * kTileX;
+    tl.z0 = bz * 4 * RY;
+    tl.src = p.src;
+    tl.qs = p.src >= 0 ? p.q * p.wavelet[p.step] : 0.f;
+    fwd2d_tile<SHAPE, M, RY>(tl, p.sp, p.w, tile);
 }
 
 template <int SHAPE, int M, int RY>

@@ -57,6 +57,15 @@ def parse():
     ap.add_argument("--nt", type=int, default=2000, help="time steps per stencil pass")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fwi", action="store_true")
+    ap.add_argument("--no-vol3d", action="store_true")
+    ap.add_argument("--no-ragged", action="store_true")
+    ap.add_argument("--vol3d-nt", type=int, default=1000)
+    ap.add_argument("--ragged-nt", type=int, default=3000)
+    ap.add_argument("--no-tune", action="store_true", help="skip the tile autotuner")
+    ap.add_argument("--only", choices=["vol3d", "ragged", "fwi", "copy"], default=None,
+                    help="run one secondary workload alone (for profiling); no value line")
+    ap.add_argument("--copy-mib", type=int, default=1024,
+                    help="--only copy: size of a plain device-to-device copy (counter calibration)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     return ap.parse_args()
 
@@ -74,9 +83,27 @@ def main():
         sys.exit(2)
 
     import torch
-    from paper_2606_04882_amd import configs, design, fdwave as F
+    from paper_2606_04882_amd import autotune, configs, design, fdwave as F
 
     dev = torch.device("cuda:0")
+    if args.only:
+        if args.only == "copy":
+            n = args.copy_mib * (1 << 20) // 4
+            a = torch.ones(n, device=dev)
+            b = torch.empty_like(a)
+            for _ in range(3):
+                b.copy_(a)
+            torch.cuda.synchronize()
+            ms = _event_time(torch, lambda: b.copy_(a), reps=5)
+            res = {"copy_bytes": 4 * n, "ms": ms, "gbs_read_plus_write": 8 * n / (ms * 1e-3) / 1e9}
+        elif args.only == "vol3d":
+            res = vol3d_bench(torch, F, design, configs, dev, args.vol3d_nt, not args.no_tune)
+        elif args.only == "ragged":
+            res = ragged_bench(torch, F, design, configs, dev, args.ragged_nt)
+        else:
+            res = fwi_bench(torch, F, design, configs, dev)
+        print(json.dumps({"only": args.only, "result": res}))
+        return
     w = configs.large_2d(nt=args.nt)
     vel_np = configs.large_2d_model(w)
     vel = torch.tensor(vel_np, device=dev)
@@ -90,6 +117,8 @@ def main():
         sid = F.fd_weights_set(2, shape, M, wts)
         shot = F.Shot(stencil_id=sid, src=w.src, wavelet=wav, rec=rec,
                       traces=torch.zeros(w.nt, len(w.rec), device=dev))
+        if not args.no_tune:
+            autotune.tune(sid, 2, shape, M, grid, vel, w.src, nt=40, reps=2)
         nbytes = F.fd_workspace_bytes(grid, [shot])
         ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
         variants.append({"name": f"{scheme}-{shape}-M{M}", "shape": shape, "M": M, "sid": sid,
@@ -166,6 +195,12 @@ def main():
     }
 
     log(f"timed: {value / 1e9:.1f} Gupd/s")
+    if not args.no_vol3d:
+        line["vol3d"] = vol3d_bench(torch, F, design, configs, dev, args.vol3d_nt, not args.no_tune)
+        log("vol3d done")
+    if not args.no_ragged:
+        line["ragged"] = ragged_bench(torch, F, design, configs, dev, args.ragged_nt)
+        log("ragged done")
     if not args.no_fwi:
         line["fwi"] = fwi_bench(torch, F, design, configs, dev)
         log("fwi done")
@@ -173,6 +208,91 @@ def main():
         line["cpu_baseline"] = cpu_baseline(w, vel_np, args.cpu_seconds)
         log("cpu baseline done")
     print(json.dumps(line))
+
+
+def _event_time(torch, fn, reps=1):
+    """Average milliseconds of fn() between HIP events on the current stream."""
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(reps):
+        fn()
+    e1.record(s)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def vol3d_bench(torch, F, design, configs, dev, nt, tune=True):
+    """512^3 layered volume, 1000 steps each of Taylor cross M=4, M=8 and
+    DispTE rhombus M=4, 256 x 256 receivers: per-stencil Gpt-updates/s and
+    the HBM roofline of the per-step kernel (16 B per update)."""
+    w = configs.volume_3d(nt=nt)
+    vel = torch.tensor(configs.volume_3d_model(w), device=dev)
+    wav = torch.tensor(w.wavelet().astype(np.float32), device=dev)
+    rec = torch.tensor(w.rec.astype(np.int32), device=dev)
+    grid = F.Grid(shape=w.shape, h=w.h, dt=w.dt, nt=w.nt, nb=w.nb, eta_max=w.eta_max, vmax=w.c_max)
+    npts = int(np.prod(w.shape))
+    out = {"workload": w.name, "nt": w.nt, "stencils": []}
+    traces = torch.zeros(w.nt, len(w.rec), device=dev)
+    for scheme, shape, M in w.stencils:
+        sid = F.fd_weights_set(3, shape, M, design.weights(3, scheme, shape, M, w.courant))
+        tuned = None
+        if tune:
+            from paper_2606_04882_amd import autotune
+            tuned = autotune.tune(sid, 3, shape, M, grid, vel, w.src, nt=20, reps=2)["ms"]
+        shot = F.Shot(stencil_id=sid, src=w.src, wavelet=wav, rec=rec, traces=traces)
+        F.fd_forward(grid, vel, [shot])       # capture
+        torch.cuda.synchronize()
+        ms = _event_time(torch, lambda: F.fd_forward(grid, vel, [shot]))
+        launch_us = ms * 1e3 / w.nt
+        gbs = npts * BYTES_PER_UPDATE / (launch_us * 1e-6) / 1e9
+        flops = flops_per_update(3, shape, M)
+        rows, zc = F.fd_get_tile(sid)
+        out["stencils"].append({
+            "stencil": f"{scheme}-{shape}-M{M}", "ms": round(ms, 2),
+            "gupd_s": round(npts * w.nt / (ms * 1e-3) / 1e9, 2), "launch_us": round(launch_us, 2),
+            "hbm_gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+            "tflops": round(npts * flops / (launch_us * 1e-6) / 1e12, 2),
+            "kernel": f"k_fwd3d_{'cross' if shape == 'cross' else 'gen'}<M={M},rows={rows},zchunk={zc}>",
+            "tuning_ms_per_20_steps": tuned})
+    del vel
+    torch.cuda.empty_cache()
+    return out
+
+
+def ragged_bench(torch, F, design, configs, dev, nt):
+    """64 shots on uneven windows of a 2000 x 600 model, mixed Taylor cross /
+    SpecLS square stencils with M = 4..8, 3000 steps: one batched launch per
+    step replayed from a HIP graph, against the plain per-shot loop (direct
+    per-step launches, shot after shot)."""
+    w = configs.ragged(nt=nt)
+    vel = torch.tensor(configs.ragged_model(w), device=dev)
+    wav = torch.tensor(w.wavelet().astype(np.float32), device=dev)
+    shots = []
+    for sp in w.extra["shots"]:
+        scheme, shape, M = sp.stencil
+        sid = F.fd_weights_set(2, shape, M, design.weights(2, scheme, shape, M, w.courant))
+        shots.append(F.Shot(stencil_id=sid, src=sp.src, wavelet=wav,
+                            rec=torch.tensor(sp.rec.astype(np.int32), device=dev),
+                            traces=torch.zeros(w.nt, len(sp.rec), device=dev),
+                            origin=(sp.origin[0], 0, sp.origin[1]), extent=(sp.extent[0], 1, sp.extent[1])))
+    upd = sum(sp.extent[0] * sp.extent[1] for sp in w.extra["shots"]) * w.nt
+    grid = F.Grid(shape=w.shape, h=w.h, dt=w.dt, nt=w.nt, nb=w.nb, eta_max=w.eta_max, vmax=w.c_max)
+    F.fd_forward(grid, vel, shots)
+    torch.cuda.synchronize()
+    ref = [s.traces.clone() for s in shots]
+    ms = _event_time(torch, lambda: F.fd_forward(grid, vel, shots), reps=2)
+    plain = F.Grid(shape=w.shape, h=w.h, dt=w.dt, nt=w.nt, nb=w.nb, eta_max=w.eta_max, vmax=w.c_max,
+                   flags=F.FD_NO_GRAPH | F.FD_NO_BATCH)
+    t0 = time.perf_counter()
+    F.fd_forward(plain, vel, shots)
+    torch.cuda.synchronize()
+    ms_plain = (time.perf_counter() - t0) * 1e3
+    same = all(torch.equal(a, s.traces) for a, s in zip(ref, shots))
+    return {"workload": w.name, "shots": len(shots), "nt": w.nt, "updates": upd,
+            "batched_ms": round(ms, 2), "batched_gupd_s": round(upd / (ms * 1e-3) / 1e9, 2),
+            "plain_ms": round(ms_plain, 2), "plain_gupd_s": round(upd / (ms_plain * 1e-3) / 1e9, 2),
+            "speedup_vs_plain": round(ms_plain / ms, 3), "traces_bitwise_equal": bool(same)}
 
 
 def fwi_bench(torch, F, design, configs, dev):
@@ -245,7 +365,7 @@ def cpu_baseline(w, vel_np, budget_s):
     for st in sts:
         S.forward(st, v, w.dt, 1, w.nb, w.eta_max, w.src, q[:1], w.rec)
     one = time.perf_counter() - t0
-    nsteps = max(1, min(50, int(budget_s / max(one, 1e-3))))
+    nsteps = max(1, min(400, int(budget_s / max(one, 1e-3))))
     t0 = time.perf_counter()
     for st in sts:
         S.forward(st, v, w.dt, nsteps, w.nb, w.eta_max, w.src, q[:nsteps], w.rec)

@@ -29,9 +29,7 @@ __device__ __forceinline__ void fwd2d_tile(const Tile2D& t, const Sponge& sp, co
                                            float* tile) {
     constexpr int LW = kTileX + 2 * M;
     const int tid = threadIdx.x, tx = tid & 63, ty = tid >> 6;
-    load_tile2d<M, RY>(tile, t.ucur, t.nx, t.nz, t.x0, t.z0);
-
-    // pointwise operands, issued before the barrier so their latency overlaps
+    // pointwise operands first, then the tile: all global loads in flight together
     const int gx = t.x0 + tx;
     const bool colok = gx < t.nx;
     float up[RY], vv[RY];
@@ -45,6 +43,7 @@ __device__ __forceinline__ void fwd2d_tile(const Tile2D& t, const Sponge& sp, co
             vv[j] = t.v[(long long)gz * t.ldv + gx];
         }
     }
+    load_tile2d<M, RY>(tile, t.ucur, t.nx, t.nz, t.x0, t.z0);
     __syncthreads();
 
     float uc[RY], acc[RY];

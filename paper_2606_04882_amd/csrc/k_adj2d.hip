@@ -25,9 +25,6 @@ __global__ __launch_bounds__(kBlock) void k_adj2d(AdjArgs p) {
     const int t = xcd_tile(blockIdx.x, p.ntiles);
     const int bz = t / p.tiles_x, bx = t - bz * p.tiles_x;
     const int x0 = bx * kTileX, z0 = bz * TY;
-    load_tile2d<M, RY>(tp, p.pcur, p.nx, p.nz, x0, z0);
-    if (p.with_grad) load_tile2d<M, RY>(tu, p.ufwd, p.nx, p.nz, x0, z0);
-
     const int gx = x0 + tx;
     const bool colok = gx < p.nx;
     float pp[RY], vv[RY], gg[RY];
@@ -43,6 +40,8 @@ __global__ __launch_bounds__(kBlock) void k_adj2d(AdjArgs p) {
             if (p.with_grad) gg[j] = p.grad[(long long)gz * p.ldv_y + gx];
         }
     }
+    load_tile2d<M, RY>(tp, p.pcur, p.nx, p.nz, x0, z0);
+    if (p.with_grad) load_tile2d<M, RY>(tu, p.ufwd, p.nx, p.nz, x0, z0);
     __syncthreads();
 
     float pc[RY], lp[RY];

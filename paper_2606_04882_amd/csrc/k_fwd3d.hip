@@ -45,35 +45,65 @@ __device__ __forceinline__ float damp_e(const Sponge& sp, int gx, int gy, int gz
     return sp.escale * fmaf(rx, rx, fmaf(ry, ry, rz * rz));
 }
 
-// Halo of plane z of field f (interior cells excluded), zeros off the grid.
+// Halo of plane z of field f (interior cells excluded), zeros off the grid,
+// in two halves so that the loads of the next plane can be in flight while
+// the current plane is computed: fetch_halo issues the global loads into
+// registers, store_halo writes them to LDS.
+template <int M, int RY>
+struct Halo {
+    static constexpr int LW = Geo3<M, RY>::LW;
+    static constexpr int TOPN = M * LW, SIDEN = 4 * RY * M, H = 2 * TOPN + 2 * SIDEN;
+    static constexpr int NL = (H + kBlock - 1) / kBlock;
+    float val[NL];
+
+    __device__ __forceinline__ static int pos(int i, int& r, int& c) {
+        if (i < TOPN) {
+            r = i / LW;
+            c = i - r * LW;
+        } else if (i < 2 * TOPN) {
+            const int q = i - TOPN;
+            r = M + 4 * RY + q / LW;
+            c = q % LW;
+        } else {
+            int q = i - 2 * TOPN;
+            const int side = q / SIDEN;
+            q -= side * SIDEN;
+            r = M + q / M;
+            c = (side ? M + kTileX : 0) + q % M;
+        }
+        return r * LW + c;
+    }
+    __device__ __forceinline__ void fetch(const float* __restrict__ f, int nx, int ny, int nz, int x0,
+                                          int y0, int z) {
+        const bool zok = (unsigned)z < (unsigned)nz;
+#pragma unroll
+        for (int k = 0; k < NL; ++k) {
+            const int i = threadIdx.x + k * kBlock;
+            int r, c;
+            pos(i, r, c);
+            const int gy = y0 - M + r, gx = x0 - M + c;
+            val[k] = 0.f;
+            if (i < H && zok && (unsigned)gy < (unsigned)ny && (unsigned)gx < (unsigned)nx)
+                val[k] = f[((long long)z * ny + gy) * nx + gx];
+        }
+    }
+    __device__ __forceinline__ void store(float* tile) const {
+#pragma unroll
+        for (int k = 0; k < NL; ++k) {
+            const int i = threadIdx.x + k * kBlock;
+            int r, c;
+            const int at = pos(i, r, c);
+            if (i < H) tile[at] = val[k];
+        }
+    }
+};
+
 template <int M, int RY>
 __device__ __forceinline__ void load_halo(float* tile, const float* __restrict__ f, int nx, int ny,
                                           int nz, int x0, int y0, int z) {
-    using G = Geo3<M, RY>;
-    constexpr int TOPN = M * G::LW, SIDEN = 4 * RY * M, H = 2 * TOPN + 2 * SIDEN;
-    const bool zok = (unsigned)z < (unsigned)nz;
-    for (int i = threadIdx.x; i < H; i += kBlock) {
-        int r, c;
-        if (i < TOPN) {
-            r = i / G::LW;
-            c = i - r * G::LW;
-        } else if (i < 2 * TOPN) {
-            const int k = i - TOPN;
-            r = M + 4 * RY + k / G::LW;
-            c = k % G::LW;
-        } else {
-            int k = i - 2 * TOPN;
-            const int side = k / SIDEN;
-            k -= side * SIDEN;
-            r = M + k / M;
-            c = (side ? M + kTileX : 0) + k % M;
-        }
-        const int gy = y0 - M + r, gx = x0 - M + c;
-        float val = 0.f;
-        if (zok && (unsigned)gy < (unsigned)ny && (unsigned)gx < (unsigned)nx)
-            val = f[((long long)z * ny + gy) * nx + gx];
-        tile[r * G::LW + c] = val;
-    }
+    Halo<M, RY> h;
+    h.fetch(f, nx, ny, nz, x0, y0, z);
+    h.store(tile);
 }
 
 // Whole plane z (interior and halo) of field f.
@@ -81,14 +111,22 @@ template <int M, int RY>
 __device__ __forceinline__ void load_plane(float* tile, const float* __restrict__ f, int nx, int ny,
                                            int nz, int x0, int y0, int z) {
     using G = Geo3<M, RY>;
+    constexpr int NL = (G::PLANE + kBlock - 1) / kBlock;
     const bool zok = (unsigned)z < (unsigned)nz;
-    for (int i = threadIdx.x; i < G::PLANE; i += kBlock) {
+    float val[NL];
+#pragma unroll
+    for (int k = 0; k < NL; ++k) {
+        const int i = threadIdx.x + k * kBlock;
         const int r = i / G::LW, c = i - r * G::LW;
         const int gy = y0 - M + r, gx = x0 - M + c;
-        float val = 0.f;
-        if (zok && (unsigned)gy < (unsigned)ny && (unsigned)gx < (unsigned)nx)
-            val = f[((long long)z * ny + gy) * nx + gx];
-        tile[i] = val;
+        val[k] = 0.f;
+        if (i < G::PLANE && zok && (unsigned)gy < (unsigned)ny && (unsigned)gx < (unsigned)nx)
+            val[k] = f[((long long)z * ny + gy) * nx + gx];
+    }
+#pragma unroll
+    for (int k = 0; k < NL; ++k) {
+        const int i = threadIdx.x + k * kBlock;
+        if (i < G::PLANE) tile[i] = val[k];
     }
 }
 
@@ -131,11 +169,16 @@ __device__ __forceinline__ float cross_sum(const float* tile, const float* q, in
     return acc;
 }
 
+// Operands of plane z+1 (queue front u(z+1+M), u^{n-1}, v and the halo of
+// u(z+1)) are fetched while plane z is computed; the xy plane alternates
+// between two LDS buffers, so one barrier per plane suffices (a buffer is
+// rewritten only after every thread has passed the barrier of the plane in
+// between).
 template <int M, int RY>
 __global__ __launch_bounds__(kBlock) void k_fwd3d_cross(StepArgs p) {
     using G = Geo3<M, RY>;
     constexpr int NQ = 2 * M + 1;
-    __shared__ float tile[G::PLANE];
+    __shared__ float tiles[2][G::PLANE];
     if (p.trace_out) {
         for (int r = blockIdx.x * kBlock + threadIdx.x; r < p.nrec; r += gridDim.x * kBlock) {
             const long long i = p.rec_lin[r];
@@ -144,58 +187,77 @@ __global__ __launch_bounds__(kBlock) void k_fwd3d_cross(StepArgs p) {
     }
     const Pos3 b = block_pos<RY>(p.ntiles, p.tiles_x, p.tiles_y, p.zchunk, p.nz);
     const bool xok = b.gx < p.nx;
+    const long long plane = (long long)p.nx * p.ny;
     float q[RY][NQ];
     bool ok[RY];
+    long long col[RY], vcol[RY];   // offsets of (x, y_j) within a window / model plane
 #pragma unroll
     for (int j = 0; j < RY; ++j) {
         const int gy = b.y0 + b.ty * RY + j;
         ok[j] = xok && gy < p.ny;
+        col[j] = (long long)gy * p.nx + b.gx;
+        vcol[j] = (long long)gy * p.ldv_y + b.gx;
 #pragma unroll
         for (int i = 0; i < 2 * M; ++i) {
             const int z = b.zs - M + i;
-            q[j][i] = (ok[j] && (unsigned)z < (unsigned)p.nz) ? p.ucur[((long long)z * p.ny + gy) * p.nx + b.gx] : 0.f;
+            q[j][i] = (ok[j] && (unsigned)z < (unsigned)p.nz) ? p.ucur[z * plane + col[j]] : 0.f;
         }
     }
-    for (int z = b.zs; z < b.ze; ++z) {
-        float up[RY], vv[RY];
+    Halo<M, RY> halo;
+    float front[RY], up[RY], vv[RY];
+    auto fetch = [&](int z) {
 #pragma unroll
         for (int j = 0; j < RY; ++j) {
-            const int gy = b.y0 + b.ty * RY + j;
             const int zz = z + M;
-            q[j][2 * M] = (ok[j] && zz < p.nz) ? p.ucur[((long long)zz * p.ny + gy) * p.nx + b.gx] : 0.f;
-            up[j] = ok[j] ? p.uprev[((long long)z * p.ny + gy) * p.nx + b.gx] : 0.f;
-            vv[j] = ok[j] ? p.v[(long long)z * p.ldv_z + (long long)gy * p.ldv_y + b.gx] : 0.f;
+            const bool in = ok[j] && z < b.ze;
+            front[j] = (in && zz < p.nz) ? p.ucur[zz * plane + col[j]] : 0.f;
+            up[j] = in ? p.uprev[z * plane + col[j]] : 0.f;
+            vv[j] = in ? p.v[(long long)z * p.ldv_z + vcol[j]] : 0.f;
+        }
+        if (z < b.ze) halo.fetch(p.ucur, p.nx, p.ny, p.nz, b.x0, b.y0, z);
+    };
+    fetch(b.zs);
+    int buf = 0;
+    for (int z = b.zs; z < b.ze; ++z) {
+        float* tile = tiles[buf];
+        float upc[RY], vvc[RY];
+#pragma unroll
+        for (int j = 0; j < RY; ++j) {
+            q[j][2 * M] = front[j];
+            upc[j] = up[j];
+            vvc[j] = vv[j];
             tile[(b.ty * RY + j + M) * G::LW + b.tx + M] = q[j][M];
         }
-        load_halo<M, RY>(tile, p.ucur, p.nx, p.ny, p.nz, b.x0, b.y0, z);
+        halo.store(tile);
+        fetch(z + 1);
         __syncthreads();
 #pragma unroll
         for (int j = 0; j < RY; ++j) {
             const float L = cross_sum<M, RY>(tile, q[j], b.ty * RY + j + M, b.tx + M, p.w);
             if (ok[j]) {
                 const int gy = b.y0 + b.ty * RY + j;
-                const long long k = ((long long)z * p.ny + gy) * p.nx + b.gx;
+                const long long k = z * plane + col[j];
                 bool inband;
                 const float e = damp_e(p.sp, b.gx, gy, z, p.nx, p.ny, p.nz, inband);
                 const float uc = q[j][M];
                 float r;
                 if (!inband) {
-                    r = fmaf(vv[j], L, 2.f * uc - up[j]);
+                    r = fmaf(vvc[j], L, 2.f * uc - upc[j]);
                     if (k == p.src) r += p.q * p.wavelet[p.step];
                 } else {
-                    r = fmaf(-(1.f - e), up[j], 2.f * uc);
-                    r = fmaf(vv[j], L, r);
+                    r = fmaf(-(1.f - e), upc[j], 2.f * uc);
+                    r = fmaf(vvc[j], L, r);
                     if (k == p.src) r += p.q * p.wavelet[p.step];
                     r = r / (1.f + e);
                 }
                 p.unext[k] = r;
             }
         }
-        __syncthreads();
 #pragma unroll
         for (int j = 0; j < RY; ++j)
 #pragma unroll
             for (int i = 0; i < 2 * M; ++i) q[j][i] = q[j][i + 1];
+        buf ^= 1;
     }
 }
 
@@ -318,20 +380,25 @@ __device__ __forceinline__ void gen_xy(const float* pm, const float* p0, const f
 }
 
 // Layers |dz| = DZ..M.  Plane of offset d (d in [-M, M]) sits in ring slot
-// (base + d) mod (2M+1), base = slot of the output plane.
+// (base + d) mod NR, base = slot of the output plane.
+template <int SHAPE, int M, int RY, int NR, int DZ>
+__device__ __forceinline__ void gen_layers_r(const float* ring, int base, int row, int col, float u,
+                                             float& acc, const Weights& W) {
+    if constexpr (DZ <= M) {
+        using G = Geo3<M, RY>;
+        int sm = base - DZ, sp = base + DZ;
+        if (sm < 0) sm += NR;
+        if (sp >= NR) sp -= NR;
+        gen_xy<SHAPE, M, RY, DZ, 0, 0>(ring + sm * G::PLANE, ring + base * G::PLANE,
+                                       ring + sp * G::PLANE, row, col, u, acc, W);
+        gen_layers_r<SHAPE, M, RY, NR, DZ + 1>(ring, base, row, col, u, acc, W);
+    }
+}
+
 template <int SHAPE, int M, int RY, int DZ>
 __device__ __forceinline__ void gen_layers(const float* ring, int base, int row, int col, float u,
                                            float& acc, const Weights& W) {
-    if constexpr (DZ <= M) {
-        using G = Geo3<M, RY>;
-        constexpr int NP = 2 * M + 1;
-        int sm = base - DZ, sp = base + DZ;
-        if (sm < 0) sm += NP;
-        if (sp >= NP) sp -= NP;
-        gen_xy<SHAPE, M, RY, DZ, 0, 0>(ring + sm * G::PLANE, ring + base * G::PLANE,
-                                       ring + sp * G::PLANE, row, col, u, acc, W);
-        gen_layers<SHAPE, M, RY, DZ + 1>(ring, base, row, col, u, acc, W);
-    }
+    gen_layers_r<SHAPE, M, RY, 2 * M + 1, DZ>(ring, base, row, col, u, acc, W);
 }
 
 template <int SHAPE, int M, int RY, int NF>
@@ -339,12 +406,45 @@ struct RingLDS {
     float f[NF][2 * M + 1][Geo3<M, RY>::PLANE];
 };
 
+// Registers holding one whole plane (interior and halo) between its global
+// loads and its LDS store.
+template <int M, int RY>
+struct PlaneRegs {
+    static constexpr int N = Geo3<M, RY>::PLANE, LW = Geo3<M, RY>::LW;
+    static constexpr int NL = (N + kBlock - 1) / kBlock;
+    float val[NL];
+    __device__ __forceinline__ void fetch(const float* __restrict__ f, int nx, int ny, int nz, int x0,
+                                          int y0, int z) {
+        const bool zok = (unsigned)z < (unsigned)nz;
+#pragma unroll
+        for (int k = 0; k < NL; ++k) {
+            const int i = threadIdx.x + k * kBlock;
+            const int r = i / LW, c = i - r * LW;
+            const int gy = y0 - M + r, gx = x0 - M + c;
+            val[k] = 0.f;
+            if (i < N && zok && (unsigned)gy < (unsigned)ny && (unsigned)gx < (unsigned)nx)
+                val[k] = f[((long long)z * ny + gy) * nx + gx];
+        }
+    }
+    __device__ __forceinline__ void store(float* tile) const {
+#pragma unroll
+        for (int k = 0; k < NL; ++k) {
+            const int i = threadIdx.x + k * kBlock;
+            if (i < N) tile[i] = val[k];
+        }
+    }
+};
+
+// Ring of 2M+2 planes: plane p lives in slot (p - zs + M) mod (2M+2).  While
+// plane z is computed, plane z+M+1 goes into the slot of plane z-M-1, which
+// no thread reads any more once the barrier at the top of iteration z has
+// passed; so one barrier per plane suffices, and the global loads of plane
+// z+M+2 are in flight during the computation.
 template <int SHAPE, int M, int RY>
 __global__ __launch_bounds__(kBlock) void k_fwd3d_gen(StepArgs p) {
     using G = Geo3<M, RY>;
-    constexpr int NP = 2 * M + 1;
-    __shared__ RingLDS<SHAPE, M, RY, 1> L;
-    float* ring = &L.f[0][0][0];
+    constexpr int NR = 2 * M + 2;
+    __shared__ float ring[NR * G::PLANE];
     if (p.trace_out) {
         for (int r = blockIdx.x * kBlock + threadIdx.x; r < p.nrec; r += gridDim.x * kBlock) {
             const long long i = p.rec_lin[r];
@@ -352,29 +452,43 @@ __global__ __launch_bounds__(kBlock) void k_fwd3d_gen(StepArgs p) {
         }
     }
     const Pos3 b = block_pos<RY>(p.ntiles, p.tiles_x, p.tiles_y, p.zchunk, p.nz);
-    // planes zs-M .. zs+M-1 into slots 0 .. 2M-1; plane z lives in slot (z - zs + M) mod NP
-    for (int i = 0; i < 2 * M; ++i)
-        load_plane<M, RY>(ring + i * G::PLANE, p.ucur, p.nx, p.ny, p.nz, b.x0, b.y0, b.zs - M + i);
-    int base = M;   // slot of plane z
-    for (int z = b.zs; z < b.ze; ++z) {
-        int front = base + M;
-        if (front >= NP) front -= NP;
-        load_plane<M, RY>(ring + front * G::PLANE, p.ucur, p.nx, p.ny, p.nz, b.x0, b.y0, z + M);
-        float up[RY], vv[RY];
+    PlaneRegs<M, RY> pf;
+    for (int i = 0; i < 2 * M + 1; ++i) {
+        pf.fetch(p.ucur, p.nx, p.ny, p.nz, b.x0, b.y0, b.zs - M + i);
+        pf.store(ring + i * G::PLANE);
+    }
+    float up[RY], vv[RY];
+    auto fetch_pointwise = [&](int z) {
 #pragma unroll
         for (int j = 0; j < RY; ++j) {
             const int gy = b.y0 + b.ty * RY + j;
-            const bool ok = b.gx < p.nx && gy < p.ny;
+            const bool ok = b.gx < p.nx && gy < p.ny && z < b.ze;
             up[j] = ok ? p.uprev[((long long)z * p.ny + gy) * p.nx + b.gx] : 0.f;
             vv[j] = ok ? p.v[(long long)z * p.ldv_z + (long long)gy * p.ldv_y + b.gx] : 0.f;
         }
+    };
+    pf.fetch(p.ucur, p.nx, p.ny, p.nz, b.x0, b.y0, b.zs + M + 1);
+    fetch_pointwise(b.zs);
+    int base = M;   // slot of plane z
+    for (int z = b.zs; z < b.ze; ++z) {
         __syncthreads();
+        int slot = base + M + 1;
+        if (slot >= NR) slot -= NR;
+        pf.store(ring + slot * G::PLANE);          // plane z+M+1, needed from the next plane on
+        float upc[RY], vvc[RY];
+#pragma unroll
+        for (int j = 0; j < RY; ++j) {
+            upc[j] = up[j];
+            vvc[j] = vv[j];
+        }
+        if (z + 1 < b.ze) pf.fetch(p.ucur, p.nx, p.ny, p.nz, b.x0, b.y0, z + M + 2);
+        fetch_pointwise(z + 1);
 #pragma unroll
         for (int j = 0; j < RY; ++j) {
             const int row = b.ty * RY + j + M, col = b.tx + M;
             const float uc = ring[base * G::PLANE + row * G::LW + col];
             float Ls = 0.f;
-            gen_layers<SHAPE, M, RY, 0>(ring, base, row, col, uc, Ls, p.w);
+            gen_layers_r<SHAPE, M, RY, NR, 0>(ring, base, row, col, uc, Ls, p.w);
             const int gy = b.y0 + b.ty * RY + j;
             if (b.gx < p.nx && gy < p.ny) {
                 const long long k = ((long long)z * p.ny + gy) * p.nx + b.gx;
@@ -382,19 +496,18 @@ __global__ __launch_bounds__(kBlock) void k_fwd3d_gen(StepArgs p) {
                 const float e = damp_e(p.sp, b.gx, gy, z, p.nx, p.ny, p.nz, inband);
                 float r;
                 if (!inband) {
-                    r = fmaf(vv[j], Ls, 2.f * uc - up[j]);
+                    r = fmaf(vvc[j], Ls, 2.f * uc - upc[j]);
                     if (k == p.src) r += p.q * p.wavelet[p.step];
                 } else {
-                    r = fmaf(-(1.f - e), up[j], 2.f * uc);
-                    r = fmaf(vv[j], Ls, r);
+                    r = fmaf(-(1.f - e), upc[j], 2.f * uc);
+                    r = fmaf(vvc[j], Ls, r);
                     if (k == p.src) r += p.q * p.wavelet[p.step];
                     r = r / (1.f + e);
                 }
                 p.unext[k] = r;
             }
         }
-        __syncthreads();
-        base = base + 1 == NP ? 0 : base + 1;
+        base = base + 1 == NR ? 0 : base + 1;
     }
 }
 

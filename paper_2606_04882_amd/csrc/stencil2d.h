@@ -124,18 +124,28 @@ __device__ __forceinline__ void stencil2d(const float* tile, int tx, int ty, con
 }
 
 // Cooperative load of the (4*RY + 2M) x (64 + 2M) tile of field f (window
-// nx x nz, dense rows) with zeros beyond the window.
+// nx x nz, dense rows) with zeros beyond the window.  All of a thread's global
+// loads are issued before any LDS store, so their latencies overlap instead of
+// adding up.
 template <int M, int RY>
 __device__ __forceinline__ void load_tile2d(float* tile, const float* __restrict__ f, int nx,
                                             int nz, int x0, int z0) {
-    constexpr int LW = kTileX + 2 * M, LH = 4 * RY + 2 * M;
-    for (int i = threadIdx.x; i < LH * LW; i += kBlock) {
+    constexpr int LW = kTileX + 2 * M, LH = 4 * RY + 2 * M, N = LH * LW;
+    constexpr int NL = (N + kBlock - 1) / kBlock;
+    float val[NL];
+#pragma unroll
+    for (int k = 0; k < NL; ++k) {
+        const int i = threadIdx.x + k * kBlock;
         const int r = i / LW, c = i - r * LW;
         const int gz = z0 - M + r, gx = x0 - M + c;
-        float val = 0.f;
-        if ((unsigned)gz < (unsigned)nz && (unsigned)gx < (unsigned)nx)
-            val = f[(long long)gz * nx + gx];
-        tile[i] = val;
+        val[k] = 0.f;
+        if (i < N && (unsigned)gz < (unsigned)nz && (unsigned)gx < (unsigned)nx)
+            val[k] = f[(long long)gz * nx + gx];
+    }
+#pragma unroll
+    for (int k = 0; k < NL; ++k) {
+        const int i = threadIdx.x + k * kBlock;
+        if (i < N) tile[i] = val[k];
     }
 }
 

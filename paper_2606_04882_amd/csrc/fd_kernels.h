@@ -149,9 +149,15 @@ struct AdjArgs {
     Weights w;
 };
 
-// One shot of a batched launch (device memory, built by the host).
+// One shot of a batched launch (device memory, built by the host).  Each
+// shot owns an arena of window-sized fields; kernels name fields by slot:
+// slot s >= 0 is arena + s * npts, SLOT_INIT_PREV / SLOT_INIT_CUR the
+// caller's initial state (zeros when absent), SLOT_ZERO a field of zeros.
+enum { SLOT_ZERO = -3, SLOT_INIT_CUR = -2, SLOT_INIT_PREV = -1 };
+
 struct BatchShot {
-    float* buf[2];                   // ping-pong: step n reads buf[(n+1)&1], writes buf[n&1]
+    float* arena;
+    long long npts;                  // window points
     const float* v;                  // model v at the window origin
     long long ldv;                   // model row stride
     int nx, nz;                      // window
@@ -161,19 +167,55 @@ struct BatchShot {
     int nrec;
     const long long* rec_lin;
     float* traces;
+    const float* trace_adj;          // adjoint sources dJ/dtraces (adjoint calls)
+    const float* init_prev;          // optional initial state
+    const float* init_cur;
+    float* gacc;                     // window-shaped gradient accumulator (adjoint calls)
     int variant;                     // shape * 8 + (M - 1)
     Weights w;
 };
+
+__device__ __forceinline__ const float* slot_ptr(const BatchShot& s, int slot) {
+    if (slot >= 0) return s.arena + (long long)slot * s.npts;
+    if (slot == SLOT_INIT_PREV) return s.init_prev;
+    if (slot == SLOT_INIT_CUR) return s.init_cur;
+    return nullptr;
+}
 
 struct BatchArgs {
     const BatchShot* shots;
     const int2* jobs;                // (shot, tile within the shot) per block
     int njobs;
-    int step;
+    int step;                        // forward: time step n (source sample, trace n-1)
+    int f_cur, f_prev, f_next;       // forward: u^n, u^{n-1}, u^{n+1} slots
+    int gather;                      // forward: write trace n-1 from u^n
     Sponge sp;
     float q;
 };
 
+struct BatchAdjArgs {
+    const BatchShot* shots;
+    const int2* jobs;
+    int njobs;
+    int f_pcur, f_pprev, f_pnext;    // psi^{k+1}, psi^{k+2}, psi^k slots
+    int f_ufwd;                      // u^k slot (gradient pairing)
+    int with_grad, with_update;
+    float gscale;                    // 2 dt / h
+    Sponge sp;
+};
+
+void launch_batch_adj2d(const BatchAdjArgs& a, hipStream_t s);
+// dst slot <- src slot for every shot (src SLOT_ZERO: fill with zeros; an
+// absent initial state also reads as zeros); also used for gacc when dst is
+// SLOT_GACC
+enum { SLOT_GACC = -4 };
+void launch_batch_copy(const BatchShot* shots, int nshots, long long max_npts, int dst, int src,
+                       hipStream_t s);
+// psi(x_r) += b v rho^{k-1}_r in slot f for every shot
+void launch_batch_inject(const BatchShot* shots, int nshots, int max_nrec, int f, int k, Sponge sp,
+                         hipStream_t s);
+// trace n of every shot from slot f
+void launch_batch_gather(const BatchShot* shots, int nshots, int max_nrec, int f, int n, hipStream_t s);
 void launch_batch2d(const BatchArgs& a, hipStream_t s);
 int batch_rows();
 
@@ -202,6 +244,8 @@ void launch_inject(float* psi, const long long* lin, int nrec, const float* rho,
                    long long ldv_y, long long ldv_z, Sponge sp, int nx, int ny, int nz,
                    hipStream_t s);
 void launch_check_finite(const float* p, long long n, int* flags, hipStream_t s);
+// g[z*ldg + x] += a[z*nx + x] over an nx x nz window
+void launch_accum2d(float* g, long long ldg, const float* a, int nx, int nz, hipStream_t s);
 
 // flags[] slots in the workspace
 enum { FLAG_BAD_REC = 0, FLAG_NONFINITE = 1, FLAG_BAD_VEL = 2, FLAG_COUNT = 4 };

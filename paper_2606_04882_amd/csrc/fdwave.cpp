@@ -218,21 +218,24 @@ bool get_stencil(int id, Stencil* out) {
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct ShotLayout {
-    size_t bufA, bufB, rec;   // forward ping-pong fields, receiver indices
+    size_t arena;       // nslots window-sized fields: slot 0 = A, slot 1 = B, ...
+    size_t rec;         // receiver indices
 };
 struct Layout {
     size_t flags, v;
     std::vector<ShotLayout> shots;
-    // adjoint scratch (shared by all shots, sized for the largest window)
+    int nslots;         // fields per shot arena
+    // single-shot adjoint scratch (shared by all shots, sized for the largest window)
     size_t psiA, psiB, ckpt, seg;
-    // batched forward: shot descriptors and the (shot, tile) work list
+    // batched calls: shot descriptors and the (shot, tile) work list
     size_t desc, jobs;
     long long njobs;
     size_t total;
 };
 
 bool use_batch(const fd_grid* g, int nshots, int mode) {
-    return mode == 0 && nshots > 1 && g->ndim == 2 && !(g->flags & FD_NO_BATCH);
+    (void)mode;
+    return nshots > 1 && g->ndim == 2 && !(g->flags & FD_NO_BATCH);
 }
 
 int shot_tiles2d(const fd_shot& s, int rows, int* tiles_x) {
@@ -245,6 +248,17 @@ long long window_points(const fd_shot& s, int ndim) {
     return s.extent[0] * (ndim == 3 ? s.extent[1] : 1) * s.extent[2];
 }
 
+// Slots of the batched adjoint arena (K = segment length, nseg segments).
+struct AdjSlots {
+    int nseg, K;
+    int ck(int j, int which) const { return 2 + 2 * j + which; }
+    int seg(int i) const { return 2 + 2 * nseg + i; }
+    int psiA() const { return 2 + 2 * nseg + K; }
+    int psiB() const { return psiA() + 1; }
+    int gacc() const { return psiA() + 2; }
+    int count() const { return psiA() + 3; }
+};
+
 Layout make_layout(const fd_grid* g, const fd_shot* shots, int nshots, int mode, int K) {
     Layout L;
     size_t off = 0;
@@ -253,32 +267,22 @@ Layout make_layout(const fd_grid* g, const fd_shot* shots, int nshots, int mode,
     const long long mpts = g->n[0] * (g->ndim == 3 ? g->n[1] : 1) * g->n[2];
     L.v = off;
     off = align256(off + sizeof(float) * (size_t)mpts);
+    const bool batch = use_batch(g, nshots, mode);
+    const int nseg = mode == 1 ? (g->nt + K - 1) / K : 0;
+    L.nslots = (batch && mode == 1) ? AdjSlots{nseg, K}.count() : 2;
     long long wmax = 0;
     for (int i = 0; i < nshots; ++i) {
         const long long wp = window_points(shots[i], g->ndim);
         wmax = std::max(wmax, wp);
-        ShotLayout s;
-        s.bufA = off;
-        off = align256(off + sizeof(float) * (size_t)wp);
-        s.bufB = off;
-        off = align256(off + sizeof(float) * (size_t)wp);
-        s.rec = off;
+        ShotLayout sl;
+        sl.arena = off;
+        off = align256(off + sizeof(float) * (size_t)wp * (size_t)L.nslots);
+        sl.rec = off;
         off = align256(off + sizeof(long long) * (size_t)std::max(shots[i].nrec, 0));
-        L.shots.push_back(s);
+        L.shots.push_back(sl);
     }
     L.psiA = L.psiB = L.ckpt = L.seg = 0;
-    L.desc = L.jobs = 0;
-    L.njobs = 0;
-    if (use_batch(g, nshots, mode)) {
-        int tx;
-        for (int i = 0; i < nshots; ++i) L.njobs += shot_tiles2d(shots[i], batch_rows(), &tx);
-        L.desc = off;
-        off = align256(off + sizeof(BatchShot) * (size_t)nshots);
-        L.jobs = off;
-        off = align256(off + sizeof(int2) * (size_t)L.njobs);
-    }
-    if (mode == 1) {
-        const int nseg = (g->nt + K - 1) / K;
+    if (mode == 1 && !batch) {
         L.psiA = off;
         off = align256(off + sizeof(float) * (size_t)wmax);
         L.psiB = off;
@@ -287,6 +291,16 @@ Layout make_layout(const fd_grid* g, const fd_shot* shots, int nshots, int mode,
         off = align256(off + sizeof(float) * (size_t)wmax * 2 * (size_t)nseg);
         L.seg = off;
         off = align256(off + sizeof(float) * (size_t)wmax * (size_t)K);
+    }
+    L.desc = L.jobs = 0;
+    L.njobs = 0;
+    if (batch) {
+        int tx;
+        for (int i = 0; i < nshots; ++i) L.njobs += shot_tiles2d(shots[i], batch_rows(), &tx);
+        L.desc = off;
+        off = align256(off + sizeof(BatchShot) * (size_t)nshots);
+        L.jobs = off;
+        off = align256(off + sizeof(int2) * (size_t)L.njobs);
     }
     L.total = off;
     return L;
@@ -654,49 +668,176 @@ int enqueue_adjoint_shot(const CallCtx& c, const ShotCtx& s, Recorder& R) {
 // Every 2D shot advanced by one batched launch per step.
 int enqueue_batched(const CallCtx& c, Recorder& R) {
     hipStream_t st = R.stream;
-    const int nt = c.g->nt;
+    const int nt = c.g->nt, ns = (int)c.shots.size();
+    const BatchShot* dshots = (const BatchShot*)(c.ws + c.L.desc);
+    long long maxn = 0;
+    int maxrec = 0;
     for (const ShotCtx& s : c.shots) {
-        if (s.s->init_prev) launch_copy(s.bufA, s.s->init_prev, s.npts, st); else launch_fill(s.bufA, s.npts, 0.f, st);
-        if (s.s->init_cur) launch_copy(s.bufB, s.s->init_cur, s.npts, st); else launch_fill(s.bufB, s.npts, 0.f, st);
+        maxn = std::max(maxn, s.npts);
+        maxrec = std::max(maxrec, s.s->nrec);
         launch_rec_index(s.s->rec, s.s->nrec, 2, s.nx, 1, s.nz, s.rec, c.flags, st);
-        R.launched(3);
+        R.launched();
     }
+    launch_batch_copy(dshots, ns, maxn, 0, SLOT_INIT_PREV, st);
+    launch_batch_copy(dshots, ns, maxn, 1, SLOT_INIT_CUR, st);
+    R.launched(2);
     BatchArgs a;
-    a.shots = (const BatchShot*)(c.ws + c.L.desc);
+    a.shots = dshots;
     a.jobs = (const int2*)(c.ws + c.L.jobs);
     a.njobs = (int)c.L.njobs;
     a.sp = c.sp;
     a.q = c.q;
+    a.gather = 1;
     for (int n = 0; n < nt; ++n) {
         a.step = n;
+        a.f_cur = (n + 1) & 1;      // step n reads u^n from slot (n+1)&1
+        a.f_prev = a.f_next = n & 1; // and writes u^{n+1} over u^{n-1}
         launch_batch2d(a, st);
         R.launched();
     }
+    const int last = (nt - 1) & 1, before = nt & 1;
+    launch_batch_gather(dshots, ns, maxrec, last, nt - 1, st);
+    R.launched();
     for (const ShotCtx& s : c.shots) {
-        float* last = (nt - 1) % 2 == 0 ? s.bufA : s.bufB;   // u^{nt} sits in buf[(nt-1)&1]
-        float* before = (nt - 1) % 2 == 0 ? s.bufB : s.bufA;
-        if (s.s->nrec > 0) launch_gather(last, s.rec, s.s->nrec, s.s->traces + (size_t)(nt - 1) * s.s->nrec, st);
-        if (s.s->final_prev) launch_copy(s.s->final_prev, before, s.npts, st);
-        if (s.s->final_cur) launch_copy(s.s->final_cur, last, s.npts, st);
+        if (s.s->final_prev) launch_copy(s.s->final_prev, s.bufA + before * s.npts, s.npts, st);
+        if (s.s->final_cur) launch_copy(s.s->final_cur, s.bufA + last * s.npts, s.npts, st);
         if (c.g->check_finite && s.s->nrec > 0)
             launch_check_finite(s.s->traces, (long long)nt * s.s->nrec, c.flags, st);
-        R.launched(4);
+        R.launched(3);
+    }
+    return R.err;
+}
+
+// Forward with checkpoints, then segment-wise recompute and adjoint, for
+// every 2D shot at once (one launch per step for all shots).  Each shot
+// accumulates its gradient in its own arena field; the per-shot gradients are
+// added into the model gradient at the end, shot after shot (deterministic).
+int enqueue_batched_adjoint(const CallCtx& c, Recorder& R) {
+    hipStream_t st = R.stream;
+    const int nt = c.g->nt, K = c.K, ns = (int)c.shots.size();
+    const int nseg = (nt + K - 1) / K;
+    const AdjSlots S{nseg, K};
+    const BatchShot* dshots = (const BatchShot*)(c.ws + c.L.desc);
+    long long maxn = 0;
+    int maxrec = 0;
+    bool any_init = false;
+    for (const ShotCtx& s : c.shots) {
+        maxn = std::max(maxn, s.npts);
+        maxrec = std::max(maxrec, s.s->nrec);
+        any_init = any_init || s.s->init_cur;
+        launch_rec_index(s.s->rec, s.s->nrec, 2, s.nx, 1, s.nz, s.rec, c.flags, st);
+        R.launched();
+    }
+    auto copy = [&](int dst, int src) {
+        launch_batch_copy(dshots, ns, maxn, dst, src, st);
+        R.launched();
+    };
+    copy(0, SLOT_INIT_PREV);
+    copy(1, SLOT_INIT_CUR);
+    copy(SLOT_GACC, SLOT_ZERO);
+    copy(S.ck(0, 0), 0);
+    copy(S.ck(0, 1), 1);
+    BatchArgs f;
+    f.shots = dshots;
+    f.jobs = (const int2*)(c.ws + c.L.jobs);
+    f.njobs = (int)c.L.njobs;
+    f.sp = c.sp;
+    f.q = c.q;
+    const int tail = ((nt - 1) / K) * K;
+    int cur = 1, prev = 0, last = 1;
+    for (int n = 0; n < nt; ++n) {
+        f.step = n;
+        f.gather = 1;
+        if (n < tail) {
+            f.f_cur = cur;
+            f.f_prev = f.f_next = prev;
+        } else {
+            const int i = n - tail;
+            f.f_cur = i == 0 ? cur : S.seg(i - 1);
+            f.f_prev = i == 0 ? prev : (i == 1 ? cur : S.seg(i - 2));
+            f.f_next = S.seg(i);
+        }
+        launch_batch2d(f, st);
+        R.launched();
+        last = f.f_next;
+        if (n < tail) {
+            std::swap(cur, prev);
+            if ((n + 1) % K == 0 && n + 1 < nt) {
+                copy(S.ck((n + 1) / K, 0), prev);
+                copy(S.ck((n + 1) / K, 1), cur);
+            }
+        }
+    }
+    launch_batch_gather(dshots, ns, maxrec, last, nt - 1, st);
+    R.launched();
+    R.cut();
+    copy(S.psiA(), SLOT_ZERO);
+    copy(S.psiB(), SLOT_ZERO);
+    int pcur = S.psiA(), pprev = S.psiB();
+    BatchAdjArgs a;
+    a.shots = dshots;
+    a.jobs = f.jobs;
+    a.njobs = f.njobs;
+    a.gscale = (float)(2.0 * c.g->dt / c.g->h);
+    a.sp = c.sp;
+    f.gather = 0;
+    for (int j = nseg - 1; j >= 0; --j) {
+        const int s0 = j * K, e0 = std::min(nt, s0 + K);
+        for (int step = s0; step < e0 && j < nseg - 1; ++step) {
+            const int i = step - s0;
+            f.step = step;
+            f.f_cur = i == 0 ? S.ck(j, 1) : S.seg(i - 1);
+            f.f_prev = i == 0 ? S.ck(j, 0) : (i == 1 ? S.ck(j, 1) : S.seg(i - 2));
+            f.f_next = S.seg(i);
+            launch_batch2d(f, st);
+            R.launched();
+        }
+        for (int k = e0; k > s0; --k) {
+            a.f_pcur = pcur;
+            a.f_pprev = a.f_pnext = pprev;
+            a.f_ufwd = S.seg(k - s0 - 1);
+            a.with_grad = k < nt;
+            a.with_update = 1;
+            launch_batch_adj2d(a, st);
+            launch_batch_inject(dshots, ns, maxrec, pprev, k, c.sp, st);
+            R.launched(2);
+            std::swap(pcur, pprev);
+        }
+        R.cut();
+    }
+    if (any_init) {
+        a.f_pcur = pcur;
+        a.f_pprev = pprev;
+        a.f_pnext = -1;
+        a.f_ufwd = SLOT_INIT_CUR;
+        a.with_grad = 1;
+        a.with_update = 0;
+        launch_batch_adj2d(a, st);
+        R.launched();
+    }
+    for (const ShotCtx& s : c.shots) {
+        launch_accum2d(c.grad + model_offset(c, *s.s), c.ldv_y, s.bufA + (long long)S.gacc() * s.npts,
+                       s.nx, s.nz, st);
+        if (c.g->check_finite && s.s->nrec > 0)
+            launch_check_finite(s.s->traces, (long long)nt * s.s->nrec, c.flags, st);
+        R.launched(2);
     }
     return R.err;
 }
 
 // Descriptors and work list of a batched call, built on the host.
-void build_batch_blob(CallCtx& c) {
+void build_batch_blob(CallCtx& c, int mode) {
     const int nshots = (int)c.shots.size();
     std::vector<BatchShot> desc(nshots);
     std::vector<int2> jobs;
     jobs.reserve((size_t)c.L.njobs);
+    const AdjSlots S{mode == 1 ? (c.g->nt + c.K - 1) / c.K : 0, c.K};
     for (int i = 0; i < nshots; ++i) {
         const ShotCtx& s = c.shots[i];
         BatchShot& d = desc[i];
         std::memset(&d, 0, sizeof d);
-        d.buf[0] = s.bufA;
-        d.buf[1] = s.bufB;
+        d.arena = s.bufA;
+        d.npts = s.npts;
         d.v = s.v;
         d.ldv = c.ldv_y;
         d.nx = s.nx;
@@ -707,6 +848,10 @@ void build_batch_blob(CallCtx& c) {
         d.nrec = s.s->nrec;
         d.rec_lin = s.rec;
         d.traces = s.s->traces;
+        d.trace_adj = s.s->trace_adj;
+        d.init_prev = s.s->init_prev;
+        d.init_cur = s.s->init_cur;
+        d.gacc = mode == 1 ? s.bufA + (long long)S.gacc() * s.npts : nullptr;
         d.variant = s.st.shape * 8 + s.st.M - 1;
         d.w = s.st.w32;
         for (int t = 0; t < d.ntiles; ++t) jobs.push_back(make_int2(i, t));
@@ -723,7 +868,8 @@ int enqueue_call(const CallCtx& c, int mode, Recorder& R) {
     const long long mpts = c.g->n[0] * (c.g->ndim == 3 ? c.g->n[1] : 1) * c.g->n[2];
     launch_vprep(c.vel, c.vfield, mpts, c.g->dt / c.g->h, c.flags, R.stream);
     R.launched(2);
-    if (use_batch(c.g, (int)c.shots.size(), mode)) return enqueue_batched(c, R);
+    if (use_batch(c.g, (int)c.shots.size(), mode))
+        return mode == 0 ? enqueue_batched(c, R) : enqueue_batched_adjoint(c, R);
     for (const ShotCtx& s : c.shots) {
         int rc = mode == 0 ? enqueue_forward_shot(c, s, nullptr, 0, nullptr, R)
                            : enqueue_adjoint_shot(c, s, R);
@@ -886,15 +1032,15 @@ int prepare(CallCtx& c, const fd_grid* g, const float* vel, const fd_shot* shots
         s.nz = (int)shots[i].extent[2];
         s.npts = window_points(shots[i], g->ndim);
         s.v = c.vfield + model_offset(c, shots[i]);
-        s.bufA = (float*)(c.ws + c.L.shots[i].bufA);
-        s.bufB = (float*)(c.ws + c.L.shots[i].bufB);
+        s.bufA = (float*)(c.ws + c.L.shots[i].arena);
+        s.bufB = s.bufA + s.npts;
         s.rec = (long long*)(c.ws + c.L.shots[i].rec);
         const int* p = shots[i].src;
         s.src = g->ndim == 2 ? (long long)p[2] * s.nx + p[0]
                              : ((long long)p[2] * s.ny + p[1]) * s.nx + p[0];
         c.shots.push_back(s);
     }
-    if (use_batch(g, nshots, mode)) build_batch_blob(c);
+    if (use_batch(g, nshots, mode)) build_batch_blob(c, mode);
     return FD_OK;
 }
 

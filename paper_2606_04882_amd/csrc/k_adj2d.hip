@@ -11,72 +11,34 @@
 //
 // Memory traffic per point: psi^{k+1}, u^k (plus halos), psi^{k+2}, v, the
 // gradient (read + write), psi^k (write): 28 B.
-#include "fd_kernels.h"
-#include "stencil2d.h"
+#include "adj2d_body.h"
 
 namespace fdw {
 
 template <int SHAPE, int M, int RY>
 __global__ __launch_bounds__(kBlock) void k_adj2d(AdjArgs p) {
-    constexpr int TY = 4 * RY, LW = kTileX + 2 * M, LH = TY + 2 * M;
-    __shared__ float tp[LH * LW];
-    __shared__ float tu[LH * LW];
-    const int tid = threadIdx.x, tx = tid & 63, ty = tid >> 6;
+    constexpr int N = tile2d_floats_adj<M, RY>();
+    __shared__ float tp[N];
+    __shared__ float tu[N];
     const int t = xcd_tile(blockIdx.x, p.ntiles);
     const int bz = t / p.tiles_x, bx = t - bz * p.tiles_x;
-    const int x0 = bx * kTileX, z0 = bz * TY;
-    const int gx = x0 + tx;
-    const bool colok = gx < p.nx;
-    float pp[RY], vv[RY], gg[RY];
-#pragma unroll
-    for (int j = 0; j < RY; ++j) {
-        const int gz = z0 + ty * RY + j;
-        pp[j] = 0.f;
-        vv[j] = 0.f;
-        gg[j] = 0.f;
-        if (colok && gz < p.nz) {
-            if (p.with_update) pp[j] = p.pprev[(long long)gz * p.nx + gx];
-            vv[j] = p.v[(long long)gz * p.ldv_y + gx];
-            if (p.with_grad) gg[j] = p.grad[(long long)gz * p.ldv_y + gx];
-        }
-    }
-    load_tile2d<M, RY>(tp, p.pcur, p.nx, p.nz, x0, z0);
-    if (p.with_grad) load_tile2d<M, RY>(tu, p.ufwd, p.nx, p.nz, x0, z0);
-    __syncthreads();
-
-    float pc[RY], lp[RY];
-    stencil2d<SHAPE, M, RY, LW>(tp, tx, ty, p.w, pc, lp);
-    float uc[RY], lu[RY];
-    if (p.with_grad) {
-        stencil2d<SHAPE, M, RY, LW>(tu, tx, ty, p.w, uc, lu);
-    } else {
-#pragma unroll
-        for (int j = 0; j < RY; ++j) lu[j] = 0.f;
-    }
-    if (!colok) return;
-
-    const int dxb = p.sp.nb > 0 ? band_depth(gx, p.nx, p.sp.nb) : 0;
-#pragma unroll
-    for (int j = 0; j < RY; ++j) {
-        const int gz = z0 + ty * RY + j;
-        if (gz >= p.nz) break;
-        if (p.with_grad)
-            p.grad[(long long)gz * p.ldv_y + gx] = fmaf(p.gscale * rsqrtf(vv[j]) * pc[j], lu[j], gg[j]);
-        if (!p.with_update) continue;
-        const long long k = (long long)gz * p.nx + gx;
-        const int dzb = p.sp.nb > 0 ? band_depth(gz, p.nz, p.sp.nb) : 0;
-        float r;
-        if ((dxb | dzb) == 0) {
-            r = fmaf(vv[j], lp[j], 2.f * pc[j] - pp[j]);
-        } else {
-            const float ex = dxb * p.sp.inv_nb, ez = dzb * p.sp.inv_nb;
-            const float e = p.sp.escale * fmaf(ex, ex, ez * ez);
-            r = fmaf(-(1.f - e), pp[j], 2.f * pc[j]);
-            r = fmaf(vv[j], lp[j], r);
-            r = r / (1.f + e);
-        }
-        p.pnext[k] = r;
-    }
+    AdjTile a;
+    a.pcur = p.pcur;
+    a.pprev = p.pprev;
+    a.pnext = p.pnext;
+    a.ufwd = p.ufwd;
+    a.v = p.v;
+    a.ldv = p.ldv_y;
+    a.grad = p.grad;
+    a.ldg = p.ldv_y;
+    a.gscale = p.gscale;
+    a.nx = p.nx;
+    a.nz = p.nz;
+    a.x0 = bx * kTileX;
+    a.z0 = bz * 4 * RY;
+    a.with_grad = p.with_grad;
+    a.with_update = p.with_update;
+    adj2d_tile<SHAPE, M, RY>(a, p.sp, p.w, tp, tu);
 }
 
 template <int SHAPE, int M, int RY>

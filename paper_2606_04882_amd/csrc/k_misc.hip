@@ -104,6 +104,20 @@ __global__ void k_check_finite(const float* __restrict__ p, long long n, int* __
     if (bad) atomicAdd(&flags[FLAG_NONFINITE], bad);
 }
 
+__global__ void k_accum2d(float* __restrict__ g, long long ldg, const float* __restrict__ a, int nx,
+                          long long n) {
+    for (long long i = blockIdx.x * (long long)kBlock + threadIdx.x; i < n;
+         i += (long long)gridDim.x * kBlock) {
+        const long long z = i / nx, x = i - z * nx;
+        g[z * ldg + x] += a[i];
+    }
+}
+
+void launch_accum2d(float* g, long long ldg, const float* a, int nx, int nz, hipStream_t s) {
+    const long long n = (long long)nx * nz;
+    if (n > 0) hipLaunchKernelGGL(k_accum2d, dim3(grid_for(n)), dim3(kBlock), 0, s, g, ldg, a, nx, n);
+}
+
 void launch_vprep(const float* vel, float* v, long long n, double dt_over_h, int* flags,
                   hipStream_t s) {
     hipLaunchKernelGGL(k_vprep, dim3(grid_for(n)), dim3(kBlock), 0, s, vel, v, n, dt_over_h, flags);

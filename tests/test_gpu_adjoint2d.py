@@ -86,3 +86,60 @@ def test_checkpoint_interval_does_not_matter(F, K):
 def test_initial_state_term(F):
     g, gref, _, _ = run_case(F, "taylor", "cross", 4, K=40, init=True)
     check(g, gref)
+
+
+def test_batched_multishot_gradient(F):
+    """Several shots with different windows and stencils in one adjoint call
+    (one launch per step for all shots): the summed gradient matches the
+    shot-after-shot path and the oracle's summed FP64 gradient."""
+    NZ, NX, h, nt, nb = 70, 160, 10.0, 140, 8
+    model = layered((NZ, NX), seed=6)
+    vmax = float(model.max())
+    dt = 0.5 * 0.45 * h / vmax
+    C = vmax * dt / h
+    eta = synth.sponge_eta_max(vmax, nb, h)
+    wav = synth.ricker(nt, dt, 30.0)
+    specs = [  # (origin x, origin z, extent x, extent z, scheme, shape, M, src, init)
+        (0, 0, 160, 70, "dispte", "cross", 4, (80, 12), False),
+        (20, 5, 100, 60, "specls", "square", 3, (50, 10), True),
+        (60, 0, 90, 64, "dispte", "rhombus", 5, (40, 14), False),
+    ]
+    rng = np.random.default_rng(9)
+    shots, refs = [], []
+    gref = np.zeros((NZ, NX))
+    for ox, oz, ex, ez, scheme, shape, M, src, init in specs:
+        wo = oracle_weights(2, scheme, shape, M, C)
+        sid = F.fd_weights_set(2, shape, M, wo)
+        rec = np.array([[x, 9] for x in range(2, ex - 2, 3)], dtype=np.int32)
+        rho = rng.standard_normal((nt, len(rec))).astype(np.float32)
+        sh = F.Shot(stencil_id=sid, src=src, wavelet=torch.tensor(wav.astype(np.float32), device=DEV),
+                    rec=torch.tensor(rec, device=DEV), traces=torch.zeros(nt, len(rec), device=DEV),
+                    trace_adj=torch.tensor(rho, device=DEV), origin=(ox, 0, oz), extent=(ex, 1, ez))
+        ini = None
+        if init:
+            x = np.arange(ex) - ex / 2
+            z = np.arange(ez) - ez / 2
+            bump = np.exp(-(z[:, None] ** 2 + x[None, :] ** 2) / 40.0).astype(np.float32)
+            ini = (0.8 * bump, bump)
+            sh.init = tuple(torch.tensor(a, device=DEV) for a in ini)
+        shots.append(sh)
+        crop = np.ascontiguousarray(model[oz:oz + ez, ox:ox + ex])
+        st = rounded_stencil(2, shape, M, wo)
+        gi, _ = S.adjoint_gradient(st, v32(crop, dt, h), crop.astype(np.float64), dt, nt, nb, eta, src,
+                                   q32(wav, dt, h, 2), rec, rho.astype(np.float64),
+                                   init=None if ini is None else tuple(a.astype(np.float64) for a in ini))
+        gref[oz:oz + ez, ox:ox + ex] += gi
+    vel = torch.tensor(model, device=DEV)
+    g = F.Grid(shape=model.shape, h=h, dt=dt, nt=nt, nb=nb, eta_max=eta, vmax=vmax)
+    gb = torch.zeros(model.shape, device=DEV)
+    F.fd_adjoint_gradient(g, vel, shots, 30, gb)
+    torch.cuda.synchronize()
+    tb = [s.traces.clone() for s in shots]
+    gs = torch.zeros(model.shape, device=DEV)
+    g1 = F.Grid(shape=model.shape, h=h, dt=dt, nt=nt, nb=nb, eta_max=eta, vmax=vmax, flags=F.FD_NO_BATCH)
+    F.fd_adjoint_gradient(g1, vel, shots, 30, gs)
+    torch.cuda.synchronize()
+    for a, s in zip(tb, shots):
+        assert torch.equal(a, s.traces)
+    assert rel_l2(gb.cpu().numpy(), gs.cpu().numpy()) <= 1e-5
+    check(gb.cpu().numpy(), gref)

@@ -4,20 +4,27 @@ forward path on one MI355X, plus the FWI gradient time per shot.
 A "step" is one pass of the whole forward hot path over the default workload:
 the 1001 x 1001 layered 2D model advanced 2000 time steps with each of the
 eight stencils (Taylor cross M=4,8; DispTE cross M=4,8; DispTE rhombus M=4,8;
-SpecLS square M=4,8), sources, damping band and 501 receivers included.
+SpecLS square M=4,8), sources, damping band and 501 receivers included, run
+as one batched call with one shot per stencil (one launch per time step and
+stencil variant; variants run concurrently on parallel graph branches).
 value = total grid-point updates / wall time (inputs resident in HBM).
 
 Also reported on the same line:
-  roofline      the kernel with the largest share of the step time, timed with
-                HIP events on the stream it runs on; algorithmic bytes or flops
-                per update times updates per launch, over the average launch
-                duration; HBM traffic from rocprofv3 counters when available
+  roofline      the kernel with the largest share of the work (the slowest
+                stencil), timed alone with HIP events on the calling stream;
+                algorithmic bytes or flops per update times updates per launch,
+                over the average launch duration; HBM traffic per launch from
+                the committed rocprofv3 counter record when it matches the
+                current kernel sources
+  step_roofline the timed step as a whole: algorithmic flops and 16 B/update
+                bytes over the step time
   cpu_baseline  the FP64 oracle on this host's cores, on a bounded sample of
                 the same workload (a few steps per stencil), in Gpt-updates/s
   fwi           FWI gradient (forward + checkpointed adjoint) seconds per shot
                 on the 601 x 301 workload, against the plain form (per-step
                 launches, full forward storage, shot after shot)
-  variants      per-stencil Gpt-updates/s
+  variants      per-stencil Gpt-updates/s, each stencil's call alone
+  vol3d, ragged 512^3 volume per stencil; 64 ragged shots batched vs plain
 """
 from __future__ import annotations
 
@@ -37,6 +44,13 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 FP32_PEAK_TFLOPS = 157.3
 BYTES_PER_UPDATE = 16.0  # read u^n, u^{n-1}, v; write u^{n+1}
+
+
+def bytes_per_point_launch(tsteps: int) -> float:
+    """Algorithmic HBM bytes per grid point of one launch: one step reads u^n,
+    u^{n-1}, v and writes u^{n+1} (16 B); two steps per launch read the same
+    three fields once and write u^{n+1}, u^{n+2} (20 B)."""
+    return 16.0 if tsteps == 1 else 20.0
 
 
 def flops_per_update(ndim: int, shape: str, M: int) -> float:
@@ -62,8 +76,10 @@ def parse():
     ap.add_argument("--vol3d-nt", type=int, default=1000)
     ap.add_argument("--ragged-nt", type=int, default=3000)
     ap.add_argument("--no-tune", action="store_true", help="skip the tile autotuner")
-    ap.add_argument("--only", choices=["vol3d", "ragged", "fwi", "copy"], default=None,
-                    help="run one secondary workload alone (for profiling); no value line")
+    ap.add_argument("--only", choices=["2d", "vol3d", "ragged", "fwi", "copy"], default=None,
+                    help="run one workload alone (for profiling); no value line")
+    ap.add_argument("--stencil", default=None,
+                    help="--only 2d: run this stencil alone (e.g. specls-square-M8)")
     ap.add_argument("--copy-mib", type=int, default=1024,
                     help="--only copy: size of a plain device-to-device copy (counter calibration)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -96,6 +112,8 @@ def main():
             torch.cuda.synchronize()
             ms = _event_time(torch, lambda: b.copy_(a), reps=5)
             res = {"copy_bytes": 4 * n, "ms": ms, "gbs_read_plus_write": 8 * n / (ms * 1e-3) / 1e9}
+        elif args.only == "2d":
+            res = only_2d(torch, F, autotune, configs, design, dev, args)
         elif args.only == "vol3d":
             res = vol3d_bench(torch, F, design, configs, dev, args.vol3d_nt, not args.no_tune)
         elif args.only == "ragged":
@@ -104,37 +122,18 @@ def main():
             res = fwi_bench(torch, F, design, configs, dev)
         print(json.dumps({"only": args.only, "result": res}))
         return
-    w = configs.large_2d(nt=args.nt)
-    vel_np = configs.large_2d_model(w)
-    vel = torch.tensor(vel_np, device=dev)
-    wav = torch.tensor(w.wavelet().astype(np.float32), device=dev)
-    rec = torch.tensor(w.rec.astype(np.int32), device=dev)
-    grid = F.Grid(shape=w.shape, h=w.h, dt=w.dt, nt=w.nt, nb=w.nb, eta_max=w.eta_max, vmax=w.c_max)
-    variants = []
-    log("registering stencils")
-    for scheme, shape, M in w.stencils:
-        wts = design.weights(2, scheme, shape, M, w.courant)
-        sid = F.fd_weights_set(2, shape, M, wts)
-        shot = F.Shot(stencil_id=sid, src=w.src, wavelet=wav, rec=rec,
-                      traces=torch.zeros(w.nt, len(w.rec), device=dev))
-        if not args.no_tune:
-            autotune.tune(sid, 2, shape, M, grid, vel, w.src, nt=40, reps=2)
-        nbytes = F.fd_workspace_bytes(grid, [shot])
-        ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
-        variants.append({"name": f"{scheme}-{shape}-M{M}", "shape": shape, "M": M, "sid": sid,
-                         "shot": shot, "ws": ws, "rows": F.fd_get_tile(sid)[0]})
+    w, vel_np, vel, grid, variants = setup_2d(torch, F, autotune, configs, design, dev, args)
 
     stream = torch.cuda.current_stream(dev)
     npts = int(np.prod(w.shape))
     updates_per_step = npts * w.nt * len(variants)
+    # the whole job: every stencil as one shot of a single batched call (one
+    # launch per time step and stencil variant, variants on parallel branches)
+    shots = [v["shot"] for v in variants]
+    ws_all = torch.empty(F.fd_workspace_bytes(grid, shots), dtype=torch.uint8, device=dev)
 
-    def one_step(events=None):
-        for i, v in enumerate(variants):
-            if events is not None:
-                events[i][0].record(stream)
-            F.fd_forward(grid, vel, [v["shot"]], ws=v["ws"])
-            if events is not None:
-                events[i][1].record(stream)
+    def one_step():
+        F.fd_forward(grid, vel, shots, ws=ws_all)
 
     log(f"setup done: {len(variants)} stencils, {npts} points, nt={w.nt}")
     for _ in range(max(args.warmup, 1)):
@@ -142,27 +141,43 @@ def main():
     torch.cuda.synchronize()
     log("warm-up done")
 
-    evs = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-            for _ in variants] for _ in range(args.steps)]
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    e0.record(stream)
     for k in range(args.steps):
-        one_step(evs[k])
+        one_step()
+    e1.record(stream)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     elapsed = t1 - t0
     value = updates_per_step * args.steps / elapsed
+    step_ms_events = e0.elapsed_time(e1) / args.steps
+    log(f"timed: {value / 1e9:.1f} Gupd/s")
 
+    # each stencil alone (its own call, its kernel chain alone on the GPU),
+    # timed with HIP events on the calling stream: per-kernel launch durations
     per_variant = []
-    for i, v in enumerate(variants):
-        ms = sum(evs[k][i][0].elapsed_time(evs[k][i][1]) for k in range(args.steps)) / args.steps
-        per_variant.append({"stencil": v["name"], "ms": round(ms, 4),
-                            "gupd_s": round(npts * w.nt / (ms * 1e-3) / 1e9, 2), "rows": v["rows"]})
-    dom = max(range(len(variants)), key=lambda i: per_variant[i]["ms"])
+    for v in variants:
+        F.fd_forward(grid, vel, [v["shot"]], ws=v["ws"])
+        ms = _event_time(torch, lambda: F.fd_forward(grid, vel, [v["shot"]], ws=v["ws"]), reps=2)
+        ts = v["tsteps"]
+        kname = (f"k_fwd2d_tb<{v['shape']},M={v['M']},rows={v['rows']}>" if ts == 2
+                 else f"k_fwd2d<{v['shape']},M={v['M']},rows={v['rows']}>")
+        per_variant.append({"stencil": v["name"], "ms_alone": round(ms, 4),
+                            "gupd_s_alone": round(npts * w.nt / (ms * 1e-3) / 1e9, 2), "rows": v["rows"],
+                            "tsteps": ts, "kernel": kname})
+    # dominant kernel: the stencil with the largest share of the work; its
+    # call is nt / tsteps launches of that kernel plus a few field fills and
+    # copies (under 1% of the call), so call time / launches is its average
+    # launch duration
+    dom = max(range(len(variants)), key=lambda i: per_variant[i]["ms_alone"])
     dv = variants[dom]
-    launch_ms = per_variant[dom]["ms"] / w.nt   # one kernel launch per time step
-    flops = flops_per_update(2, dv["shape"], dv["M"])
-    gbs = npts * BYTES_PER_UPDATE / (launch_ms * 1e-3) / 1e9
+    ts = dv["tsteps"]
+    nlaunch = w.nt // ts
+    launch_ms = per_variant[dom]["ms_alone"] / nlaunch
+    flops = flops_per_update(2, dv["shape"], dv["M"]) * ts
+    gbs = npts * bytes_per_point_launch(ts) / (launch_ms * 1e-3) / 1e9
     tfl = npts * flops / (launch_ms * 1e-3) / 1e12
     if gbs / HBM_PEAK_GBS >= tfl / FP32_PEAK_TFLOPS:
         roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -170,9 +185,22 @@ def main():
     else:
         roof = {"bound": "alu", "achieved": round(tfl, 2), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(tfl / FP32_PEAK_TFLOPS, 4)}
-    roof["kernel"] = f"k_fwd2d<{dv['shape']},M={dv['M']},rows={dv['rows']}>"
-    roof["traffic"] = None
+    roof["kernel"] = per_variant[dom]["kernel"]
+    roof["traffic"] = traffic_for(per_variant[dom]["kernel"], npts)
     roof["launch_us"] = round(launch_ms * 1e3, 3)
+    roof["timing"] = "that stencil's call alone, HIP events on the calling stream"
+    roof["per_launch"] = {"points": npts, "steps": ts, "algorithmic_bytes": npts * bytes_per_point_launch(ts),
+                          "algorithmic_flops": npts * flops}
+    # the timed step as a whole (all variants running concurrently)
+    step_flops = sum(flops_per_update(2, v["shape"], v["M"]) for v in variants) * npts * w.nt
+    step_bytes = BYTES_PER_UPDATE * updates_per_step
+    step_s = step_ms_events * 1e-3
+    step_roof = {"tflops": round(step_flops / step_s / 1e12, 2),
+                 "tflops_frac": round(step_flops / step_s / 1e12 / FP32_PEAK_TFLOPS, 4),
+                 "hbm_gbs_16B": round(step_bytes / step_s / 1e9, 1),
+                 "hbm_frac_16B": round(step_bytes / step_s / 1e9 / HBM_PEAK_GBS, 4),
+                 "ms_events": round(step_ms_events, 3),
+                 "sequential_ms_alone": round(sum(p["ms_alone"] for p in per_variant), 3)}
 
     line = {
         "metric": "Gpt-updates/s (forward, 2D 1001x1001, 8 stencils)",
@@ -188,13 +216,13 @@ def main():
         "dtype": "f32",
         "data": "synthetic (seeded layered model, Ricker source)",
         "config": {"workload": w.name, "grid": list(w.shape), "nt": w.nt, "stencils": len(variants),
-                   "updates_per_step": updates_per_step, "pct_hbm_effective":
-                   round(100 * value * BYTES_PER_UPDATE / (HBM_PEAK_GBS * 1e9), 2)},
+                   "call": "one batched fd_forward, one shot per stencil",
+                   "updates_per_step": updates_per_step},
         "roofline": roof,
+        "step_roofline": step_roof,
         "variants": per_variant,
     }
 
-    log(f"timed: {value / 1e9:.1f} Gupd/s")
     if not args.no_vol3d:
         line["vol3d"] = vol3d_bench(torch, F, design, configs, dev, args.vol3d_nt, not args.no_tune)
         log("vol3d done")
@@ -208,6 +236,75 @@ def main():
         line["cpu_baseline"] = cpu_baseline(w, vel_np, args.cpu_seconds)
         log("cpu baseline done")
     print(json.dumps(line))
+
+
+def setup_2d(torch, F, autotune, configs, design, dev, args, only=None):
+    """The 1001 x 1001 workload: model, grid and one registered, tuned stencil
+    per variant (each with its shot and workspace)."""
+    w = configs.large_2d(nt=args.nt)
+    vel_np = configs.large_2d_model(w)
+    vel = torch.tensor(vel_np, device=dev)
+    wav = torch.tensor(w.wavelet().astype(np.float32), device=dev)
+    rec = torch.tensor(w.rec.astype(np.int32), device=dev)
+    grid = F.Grid(shape=w.shape, h=w.h, dt=w.dt, nt=w.nt, nb=w.nb, eta_max=w.eta_max, vmax=w.c_max)
+    variants = []
+    log("registering stencils")
+    for scheme, shape, M in w.stencils:
+        name = f"{scheme}-{shape}-M{M}"
+        if only is not None and name != only:
+            continue
+        wts = design.weights(2, scheme, shape, M, w.courant)
+        sid = F.fd_weights_set(2, shape, M, wts)
+        shot = F.Shot(stencil_id=sid, src=w.src, wavelet=wav, rec=rec,
+                      traces=torch.zeros(w.nt, len(w.rec), device=dev))
+        if not args.no_tune:
+            autotune.tune(sid, 2, shape, M, grid, vel, w.src, nt=40, reps=2)
+        nbytes = F.fd_workspace_bytes(grid, [shot])
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        variants.append({"name": name, "shape": shape, "M": M, "sid": sid,
+                         "shot": shot, "ws": ws, "rows": F.fd_get_tile(sid)[0],
+                         "tsteps": F.fd_get_time_block(sid)})
+    if not variants:
+        raise SystemExit(f"unknown stencil {only!r}")
+    return w, vel_np, vel, grid, variants
+
+
+def only_2d(torch, F, autotune, configs, design, dev, args):
+    """Forward runs of the 2D workload (one stencil with --stencil), one warm-up
+    call and --steps timed calls, for profiling."""
+    w, _, vel, grid, variants = setup_2d(torch, F, autotune, configs, design, dev, args, only=args.stencil)
+    out = []
+    for v in variants:
+        F.fd_forward(grid, vel, [v["shot"]], ws=v["ws"])
+        torch.cuda.synchronize()
+        ms = _event_time(torch, lambda: F.fd_forward(grid, vel, [v["shot"]], ws=v["ws"]), reps=args.steps)
+        out.append({"stencil": v["name"], "rows": v["rows"], "tsteps": v["tsteps"], "nt": w.nt,
+                    "ms": round(ms, 4)})
+    return out
+
+
+def traffic_for(kernel: str, npts: int):
+    """HBM bytes per launch of `kernel` on an npts-point window, from the
+    rocprofv3 FETCH_SIZE / WRITE_SIZE record in profiles/traffic.txt, scaled by
+    the plain-copy calibration stored with it; None when there is no record
+    or the kernel's sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", "traffic.txt")
+    try:
+        lines = open(path).read().splitlines()
+    except OSError:
+        return None
+    from paper_2606_04882_amd.profsum import kernel_sources_sha
+    sha = kernel_sources_sha(kernel)
+    for ln in lines:
+        if not ln.strip() or ln.startswith("#"):
+            continue
+        f = ln.split("\t")
+        if len(f) < 7 or f[0] != kernel or f[1] != sha or int(f[2]) != npts:
+            continue
+        fetch = float(f[3]) * 1024 * float(f[5])
+        write = float(f[4]) * 1024 * float(f[6])
+        return round(fetch + write)
+    return None
 
 
 def _event_time(torch, fn, reps=1):

@@ -193,6 +193,17 @@ size_t fd_workspace_bytes(const fd_grid* g, const fd_shot* shots, int nshots, in
 int fd_set_tile(int stencil_id, int rows, int zchunk);
 int fd_get_tile(int stencil_id, int* rows, int* zchunk);
 
+/*
+ * Time steps per kernel launch of the single-shot 2D forward (1 or 2).  With
+ * 2, one launch advances two steps on a tile staged with a 2M halo (fields
+ * written out of place), halving launches and HBM passes; results are
+ * bit-identical to 1.  Compiled for cross stencils with rows 2 or 4
+ * (FD_EUNSUPPORTED otherwise); the default is 2 where compiled.  Calls with
+ * checkpoints (the adjoint) and batched calls always use one step per launch.
+ */
+int fd_set_time_block(int stencil_id, int steps);
+int fd_get_time_block(int stencil_id, int* steps);
+
 /* Message for the last non-OK return on this thread ("" if none). */
 const char* fd_last_error(void);
 

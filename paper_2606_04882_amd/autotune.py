@@ -1,12 +1,15 @@
 """Tile autotuner for the forward kernels.
 
 For a stencil on a given grid, times a short forward run for every compiled
-tile configuration (2D: rows per thread 2, 4, 8; 3D: rows 1, 2, 4 times
-z-chunk 16, 32, 64, 128) and installs the fastest with fd_set_tile.  Results
-are cached in a JSON file keyed by device, dimension, stencil and grid size,
-so a tuned configuration is reused by later runs.  The tile choice never
-changes results: every configuration evaluates each point with the same
-arithmetic in the same order.
+configuration (2D: rows per thread 2, 4, 8, and for crosses also one or two
+time steps per launch; 3D: rows 1, 2, 4 times z-chunk 16, 32, 64, 128) and
+installs the fastest with fd_set_tile / fd_set_time_block.  Results are
+cached in a JSON file keyed by device, dimension, stencil and grid size, so a
+tuned configuration is reused by later runs; configurations tuned on MI355X
+for the standard workloads ship with the package (tuned_mi355x.json) and are
+used when the user cache has no entry.  The choice never changes results:
+every configuration evaluates each point with the same arithmetic in the same
+order.
 """
 from __future__ import annotations
 
@@ -22,23 +25,42 @@ from . import fdwave as F
 
 CACHE = os.environ.get("FDWAVE_TUNE_CACHE",
                        os.path.join(os.path.expanduser("~"), ".cache", "fdwave", "tiles.json"))
+PACKAGED = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned_mi355x.json")
 
 
-def candidates(ndim: int, shape: str, M: int) -> List[Tuple[int, int]]:
+def candidates(ndim: int, shape: str, M: int) -> List[Tuple[int, int, int]]:
+    """(rows, zchunk, time steps per launch) configurations to time."""
     if ndim == 2:
-        return [(r, 64) for r in (2, 4, 8)]
+        c = [(r, 64, 1) for r in (2, 4, 8)]
+        if shape == "cross":
+            c += [(r, 64, 2) for r in (2, 4)]
+        return c
     rows = (1, 2, 4) if shape == "cross" else ((1, 2) if M <= 4 else (1,))
-    return [(r, z) for r in rows for z in (16, 32, 64, 128)]
+    return [(r, z, 1) for r in rows for z in (16, 32, 64, 128)]
+
+
+def device_tag() -> str:
+    """Architecture and compute-unit count of GPU 0 (e.g. gfx950-256cu)."""
+    if not torch.cuda.is_available():
+        return "none"
+    p = torch.cuda.get_device_properties(0)
+    arch = getattr(p, "gcnArchName", "") or torch.cuda.get_device_name(0)
+    return f"{arch.split(':')[0]}-{p.multi_processor_count}cu"
 
 
 def _key(ndim, shape, M, grid_shape) -> str:
-    name = torch.cuda.get_device_name(0) if torch.cuda.is_available() else "none"
-    return f"{name}|{ndim}|{shape}|{M}|{'x'.join(str(int(n)) for n in grid_shape)}"
+    return f"v2|{device_tag()}|{ndim}|{shape}|{M}|{'x'.join(str(int(n)) for n in grid_shape)}"
 
 
-def _load() -> Dict:
+def _install(stencil_id: int, ndim: int, rows: int, zc: int, ts: int):
+    F.fd_set_tile(stencil_id, rows, zc)
+    if ndim == 2:
+        F.fd_set_time_block(stencil_id, ts)
+
+
+def _load(path: str = "") -> Dict:
     try:
-        with open(CACHE) as f:
+        with open(path or CACHE) as f:
             return json.load(f)
     except (OSError, ValueError):
         return {}
@@ -58,13 +80,17 @@ def _store(db: Dict):
 def tune(stencil_id: int, ndim: int, shape: str, M: int, grid: F.Grid, vel: torch.Tensor,
          src: Sequence[int], nt: int = 40, reps: int = 3, use_cache: bool = True) -> Dict:
     """Pick and install the fastest tile configuration for `stencil_id` on
-    this grid; returns {"rows", "zchunk", "ms": {config: time}, "cached"}."""
+    this grid; returns {"rows", "zchunk", "tsteps", "ms": {config: time},
+    "cached"}."""
     key = _key(ndim, shape, M, grid.shape)
-    db = _load() if use_cache else {}
+    db = {}
+    if use_cache:
+        db = _load(PACKAGED)
+        db.update(_load())
     if key in db:
-        r, z = db[key]["rows"], db[key]["zchunk"]
-        F.fd_set_tile(stencil_id, r, z)
-        return dict(db[key], cached=True)
+        e = db[key]
+        _install(stencil_id, ndim, e["rows"], e["zchunk"], e.get("tsteps", 1))
+        return dict(e, cached=True)
     dev = vel.device
     g = F.Grid(shape=grid.shape, h=grid.h, dt=grid.dt, nt=nt, nb=grid.nb, eta_max=grid.eta_max,
                vmax=grid.vmax)
@@ -72,9 +98,9 @@ def tune(stencil_id: int, ndim: int, shape: str, M: int, grid: F.Grid, vel: torc
     wav[0] = 1.0
     shot = F.Shot(stencil_id=stencil_id, src=tuple(src), wavelet=wav)
     times = {}
-    for rows, zc in candidates(ndim, shape, M):
+    for rows, zc, ts in candidates(ndim, shape, M):
         try:
-            F.fd_set_tile(stencil_id, rows, zc)
+            _install(stencil_id, ndim, rows, zc, ts)
         except F.FdError:
             continue
         F.fd_forward(g, vel, [shot])          # capture / warm-up
@@ -87,13 +113,13 @@ def tune(stencil_id: int, ndim: int, shape: str, M: int, grid: F.Grid, vel: torc
             e1.record()
             torch.cuda.synchronize()
             best = min(best, e0.elapsed_time(e1))
-        times[f"{rows}x{zc}"] = best
+        times[f"{rows}x{zc}x{ts}"] = best
     if not times:
         raise RuntimeError("no tile configuration could run")
     win = min(times, key=times.get)
-    rows, zc = (int(x) for x in win.split("x"))
-    F.fd_set_tile(stencil_id, rows, zc)
-    rec = {"rows": rows, "zchunk": zc, "ms": times}
+    rows, zc, ts = (int(x) for x in win.split("x"))
+    _install(stencil_id, ndim, rows, zc, ts)
+    rec = {"rows": rows, "zchunk": zc, "tsteps": ts, "ms": times}
     if use_cache:
         db = _load()
         db[key] = rec

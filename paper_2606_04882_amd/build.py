@@ -3,7 +3,9 @@
 Every translation unit under csrc/ is compiled in parallel to an object file
 under _build/, then linked into paper_2606_04882_amd/libfdwave.so.
 Packed FP32 instructions are disabled for all device code
-(-target-feature -packed-fp32-ops).
+(-target-feature -packed-fp32-ops), and floating-point contraction is off
+(-ffp-contract=off): fused multiply-adds appear only where the sources call
+fmaf, so every kernel rounds the same expression the same way.
 """
 from __future__ import annotations
 
@@ -20,7 +22,7 @@ LIB = os.path.join(HERE, "libfdwave.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("FDWAVE_ARCH", "gfx950")
 
-FLAGS = ["-O3", f"--offload-arch={ARCH}", "-std=c++17", "-fPIC",
+FLAGS = ["-O3", f"--offload-arch={ARCH}", "-std=c++17", "-fPIC", "-ffp-contract=off",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 

@@ -9,7 +9,7 @@ Time steps.  The paper picks tau from the maximum velocity for stability
 among its velocity-independent stencils:
     dt = 0.5 * min C_lim * h / c_max,   C_lim = 2 / sqrt(max_k -S(k)),
 and builds its dispersion-optimised (DispTE) weights at the resulting Courant
-number C = c_max dt / h ("weights from the maximum velocity", Sec. 6.1).  The
+number C = c_max dt / h (weights built from the maximum velocity, Sec. 6.1).  The
 literals below were computed that way; a CPU test recomputes them.
 
   small 2D     Taylor cross M=4 limit 0.554632479665589

@@ -204,7 +204,8 @@ struct BatchAdjArgs {
     Sponge sp;
 };
 
-void launch_batch_adj2d(const BatchAdjArgs& a, hipStream_t s);
+// one launch over the jobs of one stencil variant (false: not compiled)
+bool launch_batch_adj2d(const BatchAdjArgs& a, int shape, int M, hipStream_t s);
 // dst slot <- src slot for every shot (src SLOT_ZERO: fill with zeros; an
 // absent initial state also reads as zeros); also used for gacc when dst is
 // SLOT_GACC
@@ -216,8 +217,33 @@ void launch_batch_inject(const BatchShot* shots, int nshots, int max_nrec, int f
                          hipStream_t s);
 // trace n of every shot from slot f
 void launch_batch_gather(const BatchShot* shots, int nshots, int max_nrec, int f, int n, hipStream_t s);
-void launch_batch2d(const BatchArgs& a, hipStream_t s);
+bool launch_batch2d(const BatchArgs& a, int shape, int M, hipStream_t s);
 int batch_rows();
+
+// Two-steps-per-launch 2D forward (out of place: u^{n-1}, u^n -> u^{n+1}, u^{n+2}).
+struct TbArgs {
+    const float* __restrict__ uprev;   // u^{n-1}
+    const float* __restrict__ ucur;    // u^n
+    float* __restrict__ out1;          // u^{n+1}
+    float* __restrict__ out2;          // u^{n+2}
+    const float* __restrict__ v;
+    long long ldv;
+    int nx, nz;
+    int tiles_x, ntiles;
+    Sponge sp;
+    long long src;
+    float q;                           // dt^2 / h^2
+    const float* __restrict__ wavelet;
+    int step;                          // n
+    int nrec;
+    const long long* __restrict__ rec_lin;
+    float* __restrict__ trace_a;       // trace n-2 <- u^{n-1}, or nullptr
+    float* __restrict__ trace_b;       // trace n-1 <- u^n, or nullptr
+    Weights w;
+};
+
+bool launch_fwd2d_tb(const TbArgs& a, int shape, int M, int rows, hipStream_t s);
+bool have_fwd2d_tb(int shape, int M, int rows);
 
 // Launchers (one per translation unit).  Return false when the requested
 // (shape, M, rows) combination was not compiled.

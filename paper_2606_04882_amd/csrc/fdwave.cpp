@@ -194,6 +194,7 @@ struct Stencil {
     Weights w32;
     double cfl;
     int rows, zchunk;
+    int tsteps;   // 2D single-shot forward: time steps per launch (1 or 2)
 };
 
 std::mutex g_mu;
@@ -269,7 +270,9 @@ Layout make_layout(const fd_grid* g, const fd_shot* shots, int nshots, int mode,
     off = align256(off + sizeof(float) * (size_t)mpts);
     const bool batch = use_batch(g, nshots, mode);
     const int nseg = mode == 1 ? (g->nt + K - 1) / K : 0;
-    L.nslots = (batch && mode == 1) ? AdjSlots{nseg, K}.count() : 2;
+    // 2D single-shot forward keeps four fields so that two-steps-per-launch
+    // kernels can write out of place
+    L.nslots = (batch && mode == 1) ? AdjSlots{nseg, K}.count() : ((g->ndim == 2 && !batch && mode == 0) ? 4 : 2);
     long long wmax = 0;
     for (int i = 0; i < nshots; ++i) {
         const long long wp = window_points(shots[i], g->ndim);
@@ -389,27 +392,89 @@ void key_push(std::vector<uint64_t>& k, const void* p, size_t n) {
     }
 }
 
+// Streams and events for independent work that may run concurrently
+// (per device, library-owned, default priority).  Captured into a graph, the
+// fork / join dependencies become graph edges and the branches run on
+// separate hardware queues; without capture they are real cross-stream waits.
+constexpr int kBranches = 4;
+
+struct Branches {
+    hipStream_t s[kBranches];
+    hipEvent_t fork;
+    hipEvent_t join[kBranches];
+};
+std::map<int, Branches> g_branches;
+std::mutex g_branch_mu;   // held while a call enqueues its work
+
+// Created outside any capture (called before a capture begins).
+int get_branches(Branches** out) {
+    std::lock_guard<std::mutex> lk(g_branch_mu);
+    int dev = 0;
+    HIP_OK(hipGetDevice(&dev));
+    auto it = g_branches.find(dev);
+    if (it == g_branches.end()) {
+        Branches b;
+        for (int i = 0; i < kBranches; ++i) {
+            HIP_OK(hipStreamCreateWithFlags(&b.s[i], hipStreamNonBlocking));
+            HIP_OK(hipEventCreateWithFlags(&b.join[i], hipEventDisableTiming));
+        }
+        HIP_OK(hipEventCreateWithFlags(&b.fork, hipEventDisableTiming));
+        it = g_branches.emplace(dev, b).first;
+    }
+    *out = &it->second;
+    return FD_OK;
+}
+
 // Splits captured work into graphs of bounded size: HIP graph capture and
 // instantiation cost grow with the node count, and a multi-shot adjoint
 // would otherwise become one graph of ~10^5 nodes.  In direct mode (no
-// capture) cuts do nothing.
+// capture) cuts do nothing.  Work may be forked onto up to kBranches branch
+// streams (on(b)); a cut joins the branches, ends the graph and forks again.
 struct Recorder {
     bool capturing = false;
     hipStream_t stream = nullptr;
     std::vector<hipGraphExec_t> execs;
     int nodes = 0;
     int err = FD_OK;
+    Branches* br = nullptr;
+    int nbr = 0;          // forked branches (0: everything on `stream`)
     static constexpr int kMaxNodes = 2048;
 
+    int active = -1;      // branch that per-shot enqueue functions use (-1: `stream`)
+
+    hipStream_t on(int b) const { return nbr > 0 ? br->s[b % nbr] : stream; }
+    hipStream_t cur() const { return active >= 0 ? on(active) : stream; }
     void launched(int n = 1) {
         nodes += n;
         if (nodes >= kMaxNodes) cut();
+    }
+    void check(hipError_t e) {
+        if (e != hipSuccess && err == FD_OK) err = fail(FD_EDEVICE, "stream fork/join failed: %s", hipGetErrorString(e));
+    }
+    // branches 0..n-1 start after everything queued so far on `stream`
+    void fork(int n) {
+        n = std::min(n, kBranches);
+        if (n <= 1 || !br) return;
+        check(hipEventRecord(br->fork, stream));
+        for (int b = 0; b < n; ++b) check(hipStreamWaitEvent(br->s[b], br->fork, 0));
+        nbr = n;
+    }
+    // `stream` continues after everything queued on the branches
+    void join() {
+        if (nbr == 0) return;
+        for (int b = 0; b < nbr; ++b) {
+            check(hipEventRecord(br->join[b], br->s[b]));
+            check(hipStreamWaitEvent(stream, br->join[b], 0));
+        }
+        nbr = 0;
     }
     // End the current capture, keep its graph, and start capturing again.
     // After a failure the remaining work is still captured (and later
     // discarded) so that nothing runs outside the caller's stream order.
     void cut() {
         if (!capturing || nodes == 0) return;
+        const int forked = nbr;
+        join();
         hipGraph_t graph = nullptr;
         hipError_t e = hipStreamEndCapture(stream, &graph);
         hipGraphExec_t exec = nullptr;
@@ -423,7 +488,9 @@ struct Recorder {
         if (e != hipSuccess) {
             if (err == FD_OK) err = fail(FD_EDEVICE, "graph capture failed: %s", hipGetErrorString(e));
             capturing = false;
+            return;
         }
+        fork(forked);
     }
 };
 
@@ -460,6 +527,18 @@ struct CallCtx {
     // host-built data uploaded to the workspace before the work runs
     std::vector<unsigned char> blob;
     size_t blob_off = 0;
+    // batched calls: shots grouped by stencil variant (contiguous in the
+    // descriptor array and in the work list), each group on a branch
+    struct Group {
+        int shape, M;
+        int d0, dn;               // descriptor range
+        long long job0, njobs;    // work-list range
+        long long maxn;           // largest window of the group
+        int maxrec;
+        int branch;
+    };
+    std::vector<Group> groups;
+    int nbranch = 1;
 };
 
 // offset of a window origin in model-sized arrays
@@ -508,13 +587,88 @@ bool launch_step(const CallCtx& c, const ShotCtx& s, const StepArgs& a, hipStrea
     return launch_fwd3d(a, s.st.shape, s.st.M, s.st.rows, st);
 }
 
+// Two steps per launch (2D, no checkpoints): four buffers rotate; traces
+// n-2 and n-1 are gathered from the inputs of the launch covering n, n+1.
+int enqueue_forward_tb(const CallCtx& c, const ShotCtx& s, Recorder& R) {
+    hipStream_t st = R.cur();
+    const long long n = s.npts;
+    const int nt = c.g->nt, nrec = s.s->nrec;
+    float* prev = s.bufA;
+    float* cur = s.bufA + n;
+    float* f1 = s.bufA + 2 * n;
+    float* f2 = s.bufA + 3 * n;
+    if (s.s->init_prev) launch_copy(prev, s.s->init_prev, n, st); else launch_fill(prev, n, 0.f, st);
+    if (s.s->init_cur) launch_copy(cur, s.s->init_cur, n, st); else launch_fill(cur, n, 0.f, st);
+    launch_rec_index(s.s->rec, nrec, 2, s.nx, 1, s.nz, s.rec, c.flags, st);
+    R.launched(3);
+    TbArgs t;
+    std::memset(&t, 0, sizeof t);
+    t.v = s.v;
+    t.ldv = c.ldv_y;
+    t.nx = s.nx;
+    t.nz = s.nz;
+    t.tiles_x = (s.nx + kTileX - 1) / kTileX;
+    t.ntiles = t.tiles_x * ((s.nz + 4 * s.st.rows - 1) / (4 * s.st.rows));
+    t.sp = c.sp;
+    t.src = s.src;
+    t.q = c.q;
+    t.wavelet = s.s->wavelet;
+    t.nrec = nrec;
+    t.rec_lin = s.rec;
+    t.w = s.st.w32;
+    float* tr = s.s->traces;
+    int step = 0;
+    for (; step + 2 <= nt; step += 2) {
+        t.uprev = prev;
+        t.ucur = cur;
+        t.out1 = f1;
+        t.out2 = f2;
+        t.step = step;
+        t.trace_a = (nrec > 0 && step >= 2) ? tr + (size_t)(step - 2) * nrec : nullptr;
+        t.trace_b = (nrec > 0 && step >= 1) ? tr + (size_t)(step - 1) * nrec : nullptr;
+        if (!launch_fwd2d_tb(t, s.st.shape, s.st.M, s.st.rows, st))
+            return fail(FD_EUNSUPPORTED, "two-step kernel not compiled");
+        R.launched();
+        std::swap(prev, f1);
+        std::swap(cur, f2);
+    }
+    // prev = u^{step-1}, cur = u^step; traces step-2 and step-1 are pending
+    if (nrec > 0 && step >= 2) {
+        launch_gather(prev, s.rec, nrec, tr + (size_t)(step - 2) * nrec, st);
+        R.launched();
+    }
+    if (step < nt) {   // odd nt: one single-step launch
+        StepArgs a = base_step(c, s);
+        a.ucur = cur;
+        a.uprev = prev;
+        a.unext = prev;
+        a.step = step;
+        a.trace_out = (nrec > 0 && step >= 1) ? tr + (size_t)(step - 1) * nrec : nullptr;
+        if (!launch_step(c, s, a, st)) return fail(FD_EUNSUPPORTED, "kernel not compiled");
+        R.launched();
+        std::swap(prev, cur);
+    }
+    if (nrec > 0) {   // trace nt-1 <- u^nt
+        launch_gather(cur, s.rec, nrec, tr + (size_t)(nt - 1) * nrec, st);
+        R.launched();
+    }
+    if (s.s->final_prev) launch_copy(s.s->final_prev, prev, n, st);
+    if (s.s->final_cur) launch_copy(s.s->final_cur, cur, n, st);
+    if (c.g->check_finite && nrec > 0) launch_check_finite(tr, (long long)nt * nrec, c.flags, st);
+    R.launched(3);
+    return R.err;
+}
+
 // forward run of one shot.  With ckpt != nullptr, slot j receives
 // (u^{jK-1}, u^{jK}) for every segment start jK, and the steps of the last
 // segment [tail, nt) write u^{n+1} out of place into seg[n - tail] (so the
 // adjoint needs no recompute for that segment).
 int enqueue_forward_shot(const CallCtx& c, const ShotCtx& s, float* ckpt, int K, float* seg,
                          Recorder& R) {
-    hipStream_t st = R.stream;
+    if (!ckpt && c.g->ndim == 2 && s.st.tsteps == 2 && c.L.nslots >= 4 &&
+        have_fwd2d_tb(s.st.shape, s.st.M, s.st.rows))
+        return enqueue_forward_tb(c, s, R);
+    hipStream_t st = R.cur();
     const long long n = s.npts;
     const int nt = c.g->nt;
     float* prev = s.bufA;
@@ -665,11 +819,13 @@ int enqueue_adjoint_shot(const CallCtx& c, const ShotCtx& s, Recorder& R) {
     return R.err;
 }
 
-// Every 2D shot advanced by one batched launch per step.
+// Every 2D shot advanced by one batched launch per step and stencil variant;
+// variant groups run on parallel branches.
 int enqueue_batched(const CallCtx& c, Recorder& R) {
     hipStream_t st = R.stream;
     const int nt = c.g->nt, ns = (int)c.shots.size();
     const BatchShot* dshots = (const BatchShot*)(c.ws + c.L.desc);
+    const int2* jobs = (const int2*)(c.ws + c.L.jobs);
     long long maxn = 0;
     int maxrec = 0;
     for (const ShotCtx& s : c.shots) {
@@ -683,18 +839,24 @@ int enqueue_batched(const CallCtx& c, Recorder& R) {
     R.launched(2);
     BatchArgs a;
     a.shots = dshots;
-    a.jobs = (const int2*)(c.ws + c.L.jobs);
-    a.njobs = (int)c.L.njobs;
     a.sp = c.sp;
     a.q = c.q;
     a.gather = 1;
-    for (int n = 0; n < nt; ++n) {
+    R.fork(c.nbranch);
+    bool ok = true;
+    for (int n = 0; n < nt && ok; ++n) {
         a.step = n;
         a.f_cur = (n + 1) & 1;      // step n reads u^n from slot (n+1)&1
         a.f_prev = a.f_next = n & 1; // and writes u^{n+1} over u^{n-1}
-        launch_batch2d(a, st);
-        R.launched();
+        for (const CallCtx::Group& g : c.groups) {
+            a.jobs = jobs + g.job0;
+            a.njobs = (int)g.njobs;
+            ok = ok && launch_batch2d(a, g.shape, g.M, R.on(g.branch));
+        }
+        R.launched((int)c.groups.size());
     }
+    R.join();
+    if (!ok) return fail(FD_EUNSUPPORTED, "batched kernel not compiled");
     const int last = (nt - 1) & 1, before = nt & 1;
     launch_batch_gather(dshots, ns, maxrec, last, nt - 1, st);
     R.launched();
@@ -709,43 +871,72 @@ int enqueue_batched(const CallCtx& c, Recorder& R) {
 }
 
 // Forward with checkpoints, then segment-wise recompute and adjoint, for
-// every 2D shot at once (one launch per step for all shots).  Each shot
-// accumulates its gradient in its own arena field; the per-shot gradients are
-// added into the model gradient at the end, shot after shot (deterministic).
+// every 2D shot at once (one launch per step and stencil variant, variant
+// groups on parallel branches).  Each shot accumulates its gradient in its
+// own arena field; the per-shot gradients are added into the model gradient
+// at the end, shot after shot (deterministic).
 int enqueue_batched_adjoint(const CallCtx& c, Recorder& R) {
     hipStream_t st = R.stream;
     const int nt = c.g->nt, K = c.K, ns = (int)c.shots.size();
     const int nseg = (nt + K - 1) / K;
     const AdjSlots S{nseg, K};
     const BatchShot* dshots = (const BatchShot*)(c.ws + c.L.desc);
+    const int2* jobs = (const int2*)(c.ws + c.L.jobs);
     long long maxn = 0;
-    int maxrec = 0;
     bool any_init = false;
     for (const ShotCtx& s : c.shots) {
         maxn = std::max(maxn, s.npts);
-        maxrec = std::max(maxrec, s.s->nrec);
         any_init = any_init || s.s->init_cur;
         launch_rec_index(s.s->rec, s.s->nrec, 2, s.nx, 1, s.nz, s.rec, c.flags, st);
         R.launched();
     }
-    auto copy = [&](int dst, int src) {
+    auto copy_all = [&](int dst, int src) {
         launch_batch_copy(dshots, ns, maxn, dst, src, st);
         R.launched();
     };
-    copy(0, SLOT_INIT_PREV);
-    copy(1, SLOT_INIT_CUR);
-    copy(SLOT_GACC, SLOT_ZERO);
-    copy(S.ck(0, 0), 0);
-    copy(S.ck(0, 1), 1);
+    copy_all(0, SLOT_INIT_PREV);
+    copy_all(1, SLOT_INIT_CUR);
+    copy_all(SLOT_GACC, SLOT_ZERO);
+    copy_all(S.ck(0, 0), 0);
+    copy_all(S.ck(0, 1), 1);
+    // per-group helpers, each on the group's branch
+    auto copy = [&](int dst, int src) {
+        for (const CallCtx::Group& g : c.groups)
+            launch_batch_copy(dshots + g.d0, g.dn, g.maxn, dst, src, R.on(g.branch));
+        R.launched((int)c.groups.size());
+    };
+    bool ok = true;
     BatchArgs f;
     f.shots = dshots;
-    f.jobs = (const int2*)(c.ws + c.L.jobs);
-    f.njobs = (int)c.L.njobs;
     f.sp = c.sp;
     f.q = c.q;
+    auto fwd = [&]() {
+        for (const CallCtx::Group& g : c.groups) {
+            f.jobs = jobs + g.job0;
+            f.njobs = (int)g.njobs;
+            ok = ok && launch_batch2d(f, g.shape, g.M, R.on(g.branch));
+        }
+        R.launched((int)c.groups.size());
+    };
+    BatchAdjArgs a;
+    a.shots = dshots;
+    a.gscale = (float)(2.0 * c.g->dt / c.g->h);
+    a.sp = c.sp;
+    auto adj = [&](bool inject, int k) {
+        for (const CallCtx::Group& g : c.groups) {
+            a.jobs = jobs + g.job0;
+            a.njobs = (int)g.njobs;
+            hipStream_t bs = R.on(g.branch);
+            ok = ok && launch_batch_adj2d(a, g.shape, g.M, bs);
+            if (inject) launch_batch_inject(dshots + g.d0, g.dn, g.maxrec, a.f_pprev, k, c.sp, bs);
+        }
+        R.launched((int)c.groups.size() * (inject ? 2 : 1));
+    };
+
+    R.fork(c.nbranch);
     const int tail = ((nt - 1) / K) * K;
     int cur = 1, prev = 0, last = 1;
-    for (int n = 0; n < nt; ++n) {
+    for (int n = 0; n < nt && ok; ++n) {
         f.step = n;
         f.gather = 1;
         if (n < tail) {
@@ -757,8 +948,7 @@ int enqueue_batched_adjoint(const CallCtx& c, Recorder& R) {
             f.f_prev = i == 0 ? prev : (i == 1 ? cur : S.seg(i - 2));
             f.f_next = S.seg(i);
         }
-        launch_batch2d(f, st);
-        R.launched();
+        fwd();
         last = f.f_next;
         if (n < tail) {
             std::swap(cur, prev);
@@ -768,20 +958,15 @@ int enqueue_batched_adjoint(const CallCtx& c, Recorder& R) {
             }
         }
     }
-    launch_batch_gather(dshots, ns, maxrec, last, nt - 1, st);
-    R.launched();
+    for (const CallCtx::Group& g : c.groups)
+        launch_batch_gather(dshots + g.d0, g.dn, g.maxrec, last, nt - 1, R.on(g.branch));
+    R.launched((int)c.groups.size());
     R.cut();
     copy(S.psiA(), SLOT_ZERO);
     copy(S.psiB(), SLOT_ZERO);
     int pcur = S.psiA(), pprev = S.psiB();
-    BatchAdjArgs a;
-    a.shots = dshots;
-    a.jobs = f.jobs;
-    a.njobs = f.njobs;
-    a.gscale = (float)(2.0 * c.g->dt / c.g->h);
-    a.sp = c.sp;
     f.gather = 0;
-    for (int j = nseg - 1; j >= 0; --j) {
+    for (int j = nseg - 1; j >= 0 && ok; --j) {
         const int s0 = j * K, e0 = std::min(nt, s0 + K);
         for (int step = s0; step < e0 && j < nseg - 1; ++step) {
             const int i = step - s0;
@@ -789,8 +974,7 @@ int enqueue_batched_adjoint(const CallCtx& c, Recorder& R) {
             f.f_cur = i == 0 ? S.ck(j, 1) : S.seg(i - 1);
             f.f_prev = i == 0 ? S.ck(j, 0) : (i == 1 ? S.ck(j, 1) : S.seg(i - 2));
             f.f_next = S.seg(i);
-            launch_batch2d(f, st);
-            R.launched();
+            fwd();
         }
         for (int k = e0; k > s0; --k) {
             a.f_pcur = pcur;
@@ -798,9 +982,7 @@ int enqueue_batched_adjoint(const CallCtx& c, Recorder& R) {
             a.f_ufwd = S.seg(k - s0 - 1);
             a.with_grad = k < nt;
             a.with_update = 1;
-            launch_batch_adj2d(a, st);
-            launch_batch_inject(dshots, ns, maxrec, pprev, k, c.sp, st);
-            R.launched(2);
+            adj(true, k);
             std::swap(pcur, pprev);
         }
         R.cut();
@@ -812,9 +994,10 @@ int enqueue_batched_adjoint(const CallCtx& c, Recorder& R) {
         a.f_ufwd = SLOT_INIT_CUR;
         a.with_grad = 1;
         a.with_update = 0;
-        launch_batch_adj2d(a, st);
-        R.launched();
+        adj(false, 0);
     }
+    R.join();
+    if (!ok) return fail(FD_EUNSUPPORTED, "batched kernel not compiled");
     for (const ShotCtx& s : c.shots) {
         launch_accum2d(c.grad + model_offset(c, *s.s), c.ldv_y, s.bufA + (long long)S.gacc() * s.npts,
                        s.nx, s.nz, st);
@@ -825,16 +1008,48 @@ int enqueue_batched_adjoint(const CallCtx& c, Recorder& R) {
     return R.err;
 }
 
-// Descriptors and work list of a batched call, built on the host.
+// Relative cost of one update with stencil (shape, M): stencil points plus
+// a fixed part for the loads, the update and the store.
+double update_cost(int shape, int M) {
+    const int P = shape == FD_CROSS ? 4 * M + 1 : (shape == FD_RHOMBUS ? 2 * M * M + 2 * M + 1
+                                                                       : (2 * M + 1) * (2 * M + 1));
+    return P + 24.0;
+}
+
+// Descriptors and work list of a batched call, built on the host: shots
+// sorted by stencil variant, one contiguous descriptor and job range per
+// variant, groups spread over the branches by decreasing cost (each to the
+// least loaded branch).
 void build_batch_blob(CallCtx& c, int mode) {
     const int nshots = (int)c.shots.size();
+    std::vector<int> order(nshots);
+    for (int i = 0; i < nshots; ++i) order[i] = i;
+    auto variant = [&](int i) { return c.shots[i].st.shape * 8 + c.shots[i].st.M - 1; };
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return variant(x) < variant(y); });
     std::vector<BatchShot> desc(nshots);
     std::vector<int2> jobs;
     jobs.reserve((size_t)c.L.njobs);
     const AdjSlots S{mode == 1 ? (c.g->nt + c.K - 1) / c.K : 0, c.K};
-    for (int i = 0; i < nshots; ++i) {
-        const ShotCtx& s = c.shots[i];
-        BatchShot& d = desc[i];
+    c.groups.clear();
+    std::vector<double> gcost;
+    for (int k = 0; k < nshots; ++k) {
+        const ShotCtx& s = c.shots[order[k]];
+        if (c.groups.empty() || variant(order[k]) != variant(order[k - 1])) {
+            CallCtx::Group g;
+            g.shape = s.st.shape;
+            g.M = s.st.M;
+            g.d0 = k;
+            g.dn = 0;
+            g.job0 = (long long)jobs.size();
+            g.njobs = 0;
+            g.maxn = 0;
+            g.maxrec = 0;
+            g.branch = 0;
+            c.groups.push_back(g);
+            gcost.push_back(0.0);
+        }
+        CallCtx::Group& g = c.groups.back();
+        BatchShot& d = desc[k];
         std::memset(&d, 0, sizeof d);
         d.arena = s.bufA;
         d.npts = s.npts;
@@ -852,9 +1067,25 @@ void build_batch_blob(CallCtx& c, int mode) {
         d.init_prev = s.s->init_prev;
         d.init_cur = s.s->init_cur;
         d.gacc = mode == 1 ? s.bufA + (long long)S.gacc() * s.npts : nullptr;
-        d.variant = s.st.shape * 8 + s.st.M - 1;
+        d.variant = variant(order[k]);
         d.w = s.st.w32;
-        for (int t = 0; t < d.ntiles; ++t) jobs.push_back(make_int2(i, t));
+        for (int t = 0; t < d.ntiles; ++t) jobs.push_back(make_int2(k, t));
+        g.dn++;
+        g.njobs += d.ntiles;
+        g.maxn = std::max(g.maxn, s.npts);
+        g.maxrec = std::max(g.maxrec, s.s->nrec);
+        gcost.back() += (double)s.npts * update_cost(s.st.shape, s.st.M);
+    }
+    const int ng = (int)c.groups.size();
+    c.nbranch = std::min(ng, kBranches);
+    std::vector<int> by_cost(ng);
+    for (int i = 0; i < ng; ++i) by_cost[i] = i;
+    std::stable_sort(by_cost.begin(), by_cost.end(), [&](int x, int y) { return gcost[x] > gcost[y]; });
+    std::vector<double> load(c.nbranch, 0.0);
+    for (int gi : by_cost) {
+        const int b = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        c.groups[gi].branch = b;
+        load[b] += gcost[gi];
     }
     c.blob_off = c.L.desc;
     const size_t jobs_rel = c.L.jobs - c.L.desc;
@@ -864,18 +1095,29 @@ void build_batch_blob(CallCtx& c, int mode) {
 }
 
 int enqueue_call(const CallCtx& c, int mode, Recorder& R) {
+    std::lock_guard<std::mutex> lk(g_branch_mu);   // the branches' events are shared
+    int rc = FD_OK;
     launch_fill_i32(c.flags, FLAG_COUNT, 0, R.stream);
     const long long mpts = c.g->n[0] * (c.g->ndim == 3 ? c.g->n[1] : 1) * c.g->n[2];
     launch_vprep(c.vel, c.vfield, mpts, c.g->dt / c.g->h, c.flags, R.stream);
     R.launched(2);
     if (use_batch(c.g, (int)c.shots.size(), mode))
         return mode == 0 ? enqueue_batched(c, R) : enqueue_batched_adjoint(c, R);
-    for (const ShotCtx& s : c.shots) {
-        int rc = mode == 0 ? enqueue_forward_shot(c, s, nullptr, 0, nullptr, R)
-                           : enqueue_adjoint_shot(c, s, R);
-        if (rc) return rc;
+    // forward shots own their fields: unless FD_NO_BATCH asks for shot after
+    // shot, they run on parallel branches (adjoint shots share the checkpoint
+    // and adjoint fields and the gradient, so they stay in sequence)
+    const int ns = (int)c.shots.size();
+    const bool par = mode == 0 && ns > 1 && !(c.g->flags & FD_NO_BATCH);
+    if (par) R.fork(ns);
+    for (int i = 0; i < ns; ++i) {
+        if (par) R.active = i;
+        rc = mode == 0 ? enqueue_forward_shot(c, c.shots[i], nullptr, 0, nullptr, R)
+                       : enqueue_adjoint_shot(c, c.shots[i], R);
+        if (rc) break;
     }
-    return R.err;
+    R.active = -1;
+    R.join();
+    return rc ? rc : R.err;
 }
 
 int get_capture_stream(int dev, hipStream_t* out) {
@@ -898,7 +1140,9 @@ int run_direct(CallCtx& c, int mode, hipStream_t user) {
     }
     Recorder R;
     R.stream = user;
-    int rc = enqueue_call(c, mode, R);
+    int rc = get_branches(&R.br);
+    if (rc) return rc;
+    rc = enqueue_call(c, mode, R);
     if (rc) return rc;
     HIP_OK(hipGetLastError());
     return FD_OK;
@@ -919,6 +1163,7 @@ int run_call(CallCtx& c, int mode, hipStream_t user) {
     for (const ShotCtx& s : c.shots) {
         key_push(key, s.s, sizeof(fd_shot));
         key.push_back(((uint64_t)s.st.rows << 32) | (uint32_t)s.st.zchunk);
+        key.push_back((uint64_t)s.st.tsteps);
     }
     std::lock_guard<std::mutex> lk(g_graphs.mu);
     GraphCache::Entry* entry = nullptr;
@@ -936,6 +1181,8 @@ int run_call(CallCtx& c, int mode, hipStream_t user) {
         Recorder R;
         R.stream = cs;
         R.capturing = true;
+        rc = get_branches(&R.br);
+        if (rc) return rc;
         HIP_OK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
         rc = enqueue_call(c, mode, R);
         if (R.capturing) {
@@ -1105,6 +1352,7 @@ int fd_weights_set(int ndim, int shape, int M, const double* w, int nw, int* ste
     st.cfl = 2.0 / std::sqrt(mneg);
     st.rows = default_rows(ndim, shape, M);
     st.zchunk = 64;
+    st.tsteps = (ndim == 2 && have_fwd2d_tb(shape, M, st.rows)) ? 2 : 1;
     std::lock_guard<std::mutex> lk(g_mu);
     for (size_t i = 0; i < g_stencils.size(); ++i) {
         const Stencil& e = g_stencils[i];
@@ -1137,6 +1385,26 @@ int fd_set_tile(int stencil_id, int rows, int zchunk) {
     if (!have) return fail(FD_EUNSUPPORTED, "no kernel compiled for rows = %d", rows);
     s.rows = rows;
     s.zchunk = zchunk;
+    if (s.tsteps == 2 && !have_fwd2d_tb(s.shape, s.M, rows)) s.tsteps = 1;
+    return FD_OK;
+}
+
+int fd_set_time_block(int stencil_id, int steps) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (stencil_id < 0 || stencil_id >= (int)g_stencils.size()) return fail(FD_EINVAL, "unknown stencil id");
+    if (steps != 1 && steps != 2) return fail(FD_EINVAL, "steps must be 1 or 2");
+    Stencil& s = g_stencils[stencil_id];
+    if (steps == 2 && (s.ndim != 2 || !have_fwd2d_tb(s.shape, s.M, s.rows)))
+        return fail(FD_EUNSUPPORTED, "no two-step kernel for this stencil and tile height");
+    s.tsteps = steps;
+    return FD_OK;
+}
+
+int fd_get_time_block(int stencil_id, int* steps) {
+    Stencil st;
+    if (!steps) return fail(FD_EINVAL, "steps is NULL");
+    if (!get_stencil(stencil_id, &st)) return fail(FD_EINVAL, "unknown stencil id");
+    *steps = st.tsteps;
     return FD_OK;
 }
 

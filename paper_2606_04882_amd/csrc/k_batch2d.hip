@@ -2,13 +2,14 @@
 //
 // Many shots, each a window of its own size into one velocity model with its
 // own stencil (shape, M), source and receivers, advance one time step in a
-// single launch: the host flattens every shot's tiles into one work list and
-// each block looks up its (shot, tile) pair, then runs the same tile body as
-// the single-shot kernels with that shot's parameters.  The stencil branch is
-// uniform per block.  Tiles are 64 x 16 (4 rows per thread) for every shot.
-// Fields are named by slot in each shot's arena (see BatchShot), so forward,
-// checkpoint, recompute and adjoint phases of all shots share one launch per
-// step.
+// single launch per stencil variant: the host sorts the shots by variant and
+// flattens each variant group's tiles into one work list; each block looks up
+// its (shot, tile) pair and runs the same tile body as the single-shot
+// kernels with that shot's parameters.  Kernels are compiled per variant, so
+// each group runs at its own register and LDS budget.  Tiles are 64 x 16 (4
+// rows per thread) for every shot.  Fields are named by slot in each shot's
+// arena (see BatchShot), so forward, checkpoint, recompute and adjoint phases
+// of all shots of a group share one launch per step.
 #include "adj2d_body.h"
 #include "fwd2d_body.h"
 
@@ -24,8 +25,9 @@ constexpr int kBatchRows = 4;
     CASE(SH_SQUARE, 2) CASE(SH_SQUARE, 3) CASE(SH_SQUARE, 4) CASE(SH_SQUARE, 5)                 \
     CASE(SH_SQUARE, 6) CASE(SH_SQUARE, 7) CASE(SH_SQUARE, 8)
 
+template <int SH, int MM>
 __global__ __launch_bounds__(kBlock) void k_batch2d(BatchArgs p) {
-    __shared__ float tile[tile2d_floats<SH_SQUARE, 8, kBatchRows>()];
+    __shared__ float tile[tile2d_floats<SH, MM, kBatchRows>()];
     const int job = xcd_tile(blockIdx.x, p.njobs);
     const int2 jb = p.jobs[job];
     const BatchShot& s = p.shots[jb.x];
@@ -52,17 +54,12 @@ __global__ __launch_bounds__(kBlock) void k_batch2d(BatchArgs p) {
     tl.z0 = tz * 4 * kBatchRows;
     tl.src = s.src;
     tl.qs = s.src >= 0 ? p.q * s.wavelet[n] : 0.f;
-    switch (s.variant) {
-#define FDW_CASE(SH, MM) \
-    case SH * 8 + MM - 1: fwd2d_tile<SH, MM, kBatchRows>(tl, p.sp, s.w, tile); break;
-        FDW_SWITCH(FDW_CASE)
-#undef FDW_CASE
-        default: break;
-    }
+    fwd2d_tile<SH, MM, kBatchRows>(tl, p.sp, s.w, tile);
 }
 
+template <int SH, int MM>
 __global__ __launch_bounds__(kBlock) void k_batch_adj2d(BatchAdjArgs p) {
-    constexpr int N = tile2d_floats_adj<8, kBatchRows>();
+    constexpr int N = tile2d_floats_adj<MM, kBatchRows>();
     __shared__ float tp[N];
     __shared__ float tu[N];
     const int job = xcd_tile(blockIdx.x, p.njobs);
@@ -86,13 +83,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_adj2d(BatchAdjArgs p) {
     a.z0 = tz * 4 * kBatchRows;
     a.with_grad = p.with_grad && a.ufwd != nullptr;
     a.with_update = p.with_update;
-    switch (s.variant) {
-#define FDW_CASE(SH, MM) \
-    case SH * 8 + MM - 1: adj2d_tile<SH, MM, kBatchRows>(a, p.sp, s.w, tp, tu); break;
-        FDW_SWITCH(FDW_CASE)
-#undef FDW_CASE
-        default: break;
-    }
+    adj2d_tile<SH, MM, kBatchRows>(a, p.sp, s.w, tp, tu);
 }
 
 // dst <- src per shot; blockIdx.y = shot
@@ -135,12 +126,30 @@ __global__ void k_batch_gather(const BatchShot* __restrict__ shots, int f, int n
 
 int batch_rows() { return kBatchRows; }
 
-void launch_batch2d(const BatchArgs& a, hipStream_t s) {
-    hipLaunchKernelGGL(k_batch2d, dim3(a.njobs), dim3(kBlock), 0, s, a);
+bool launch_batch2d(const BatchArgs& a, int shape, int M, hipStream_t s) {
+    if (a.njobs <= 0) return true;
+    switch (shape * 8 + M - 1) {
+#define FDW_CASE(SH, MM)                                                                  \
+    case SH * 8 + MM - 1:                                                                 \
+        hipLaunchKernelGGL((k_batch2d<SH, MM>), dim3(a.njobs), dim3(kBlock), 0, s, a);    \
+        return true;
+        FDW_SWITCH(FDW_CASE)
+#undef FDW_CASE
+        default: return false;
+    }
 }
 
-void launch_batch_adj2d(const BatchAdjArgs& a, hipStream_t s) {
-    hipLaunchKernelGGL(k_batch_adj2d, dim3(a.njobs), dim3(kBlock), 0, s, a);
+bool launch_batch_adj2d(const BatchAdjArgs& a, int shape, int M, hipStream_t s) {
+    if (a.njobs <= 0) return true;
+    switch (shape * 8 + M - 1) {
+#define FDW_CASE(SH, MM)                                                                      \
+    case SH * 8 + MM - 1:                                                                     \
+        hipLaunchKernelGGL((k_batch_adj2d<SH, MM>), dim3(a.njobs), dim3(kBlock), 0, s, a);    \
+        return true;
+        FDW_SWITCH(FDW_CASE)
+#undef FDW_CASE
+        default: return false;
+    }
 }
 
 void launch_batch_copy(const BatchShot* shots, int nshots, long long max_npts, int dst, int src,

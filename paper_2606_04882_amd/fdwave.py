@@ -8,7 +8,7 @@ raises immediately - there is no CPU fallback.
 
 Names follow the C entry points: fd_orbits, fd_weights_set, fd_cfl_limit,
 fd_forward, fd_adjoint_gradient, fd_workspace_bytes, fd_set_tile,
-fd_get_tile, fd_last_error.
+fd_get_tile, fd_set_time_block, fd_get_time_block, fd_last_error.
 """
 from __future__ import annotations
 
@@ -65,6 +65,8 @@ def _load() -> ctypes.CDLL:
     lib.fd_cfl_limit.argtypes = [ctypes.c_int, P(ctypes.c_double)]
     lib.fd_set_tile.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int]
     lib.fd_get_tile.argtypes = [ctypes.c_int, P(ctypes.c_int), P(ctypes.c_int)]
+    lib.fd_set_time_block.argtypes = [ctypes.c_int, ctypes.c_int]
+    lib.fd_get_time_block.argtypes = [ctypes.c_int, P(ctypes.c_int)]
     lib.fd_workspace_bytes.restype = ctypes.c_size_t
     lib.fd_workspace_bytes.argtypes = [P(FdGrid), P(FdShot), ctypes.c_int, ctypes.c_int, ctypes.c_int]
     lib.fd_forward.argtypes = [P(FdGrid), ctypes.c_void_p, P(FdShot), ctypes.c_int, ctypes.c_void_p,
@@ -120,6 +122,16 @@ def fd_get_tile(stencil_id: int) -> Tuple[int, int]:
     r, z = ctypes.c_int(), ctypes.c_int()
     _check(_lib.fd_get_tile(stencil_id, ctypes.byref(r), ctypes.byref(z)))
     return r.value, z.value
+
+
+def fd_set_time_block(stencil_id: int, steps: int):
+    _check(_lib.fd_set_time_block(stencil_id, steps))
+
+
+def fd_get_time_block(stencil_id: int) -> int:
+    n = ctypes.c_int()
+    _check(_lib.fd_get_time_block(stencil_id, ctypes.byref(n)))
+    return n.value
 
 
 def fd_last_error() -> str:

@@ -1,0 +1,145 @@
+"""The C ABI library on the CPU: it loads, exports every entry point that
+include/fdwave.h declares, and its host-only calls (stencil registry, orbit
+enumeration, CFL limit, tile and time-block controls, workspace sizing,
+argument checks) behave as documented.  No call here launches a kernel.
+"""
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+from oracle import weights as W
+from tests.fdcase import oracle_weights
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fdwave.h")
+
+
+@pytest.fixture(scope="module")
+def F():
+    from paper_2606_04882_amd import fdwave
+    return fdwave
+
+
+def declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\**\s*(fd_\w+)\s*\(", text, flags=re.M)))
+
+
+def test_header_declares_the_entry_points():
+    names = declared()
+    for n in ["fd_orbits", "fd_weights_set", "fd_cfl_limit", "fd_forward", "fd_adjoint_gradient",
+              "fd_workspace_bytes", "fd_set_tile", "fd_get_tile", "fd_set_time_block",
+              "fd_get_time_block", "fd_last_error"]:
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(F):
+    out = subprocess.run(["nm", "-D", "--defined-only", F.LIB_PATH], capture_output=True, text=True,
+                         check=True).stdout
+    exported = {ln.split()[-1] for ln in out.splitlines() if " T " in ln}
+    missing = [n for n in declared() if n not in exported]
+    assert not missing, missing
+    for n in declared():
+        assert getattr(F._lib, n) is not None
+
+
+@pytest.mark.parametrize("ndim,shape,M", [(2, "cross", 4), (2, "rhombus", 5), (2, "square", 3),
+                                          (3, "cross", 8), (3, "rhombus", 4), (3, "square", 2)])
+def test_orbits_match_the_oracle_enumeration(F, ndim, shape, M):
+    reps, counts = F.fd_orbits(ndim, shape, M)
+    orbs = W.orbits(ndim, shape, M)
+    assert len(reps) == len(orbs)
+    for r, c, (rep, pts) in zip(reps, counts, orbs):
+        assert tuple(int(x) for x in r) == tuple(rep)
+        assert int(c) == len(pts)
+
+
+@pytest.mark.parametrize("ndim,scheme,shape,M", [(2, "taylor", "cross", 4), (2, "dispte", "rhombus", 4),
+                                                 (2, "specls", "square", 3), (3, "taylor", "cross", 2)])
+def test_cfl_limit_matches_the_oracle(F, ndim, scheme, shape, M):
+    w = oracle_weights(ndim, scheme, shape, M, 0.3)
+    sid = F.fd_weights_set(ndim, shape, M, w)
+    ref = W.cfl_limit(ndim, shape, M, w)
+    assert abs(F.fd_cfl_limit(sid) - ref) <= 1e-4 * ref
+
+
+def test_weights_are_validated(F):
+    _, counts = F.fd_orbits(2, "cross", 4)
+    with pytest.raises(F.FdError) as e:
+        F.fd_weights_set(2, "cross", 4, [1.0] * len(counts))       # violates sum count*w = 0
+    assert e.value.code == F.FD_EINVAL
+    w = oracle_weights(2, "taylor", "cross", 4)
+    with pytest.raises(F.FdError) as e:
+        F.fd_weights_set(2, "cross", 4, w[:-1])                    # one weight missing
+    assert e.value.code == F.FD_EINVAL
+    with pytest.raises(F.FdError) as e:
+        F.fd_weights_set(2, "cross", 9, [0.0] * 10)                # radius above FD_MAX_RADIUS
+    assert e.value.code == F.FD_EINVAL
+    assert F.fd_last_error()
+
+
+def test_time_block_controls(F):
+    sid = F.fd_weights_set(2, "cross", 4, oracle_weights(2, "taylor", "cross", 4))
+    F.fd_set_tile(sid, 4)
+    F.fd_set_time_block(sid, 2)
+    assert F.fd_get_time_block(sid) == 2
+    F.fd_set_time_block(sid, 1)
+    assert F.fd_get_time_block(sid) == 1
+    with pytest.raises(F.FdError) as e:
+        F.fd_set_time_block(sid, 3)
+    assert e.value.code == F.FD_EINVAL
+    F.fd_set_time_block(sid, 2)
+    F.fd_set_tile(sid, 8)                      # no two-step kernel at 8 rows: falls back to 1
+    assert F.fd_get_tile(sid)[0] == 8 and F.fd_get_time_block(sid) == 1
+    with pytest.raises(F.FdError) as e:
+        F.fd_set_time_block(sid, 2)
+    assert e.value.code == F.FD_EUNSUPPORTED
+    sq = F.fd_weights_set(2, "square", 2, oracle_weights(2, "specls", "square", 2))
+    assert F.fd_get_time_block(sq) == 1
+    with pytest.raises(F.FdError) as e:
+        F.fd_set_time_block(sq, 2)
+    assert e.value.code == F.FD_EUNSUPPORTED
+    s3 = F.fd_weights_set(3, "cross", 2, oracle_weights(3, "taylor", "cross", 2))
+    with pytest.raises(F.FdError) as e:
+        F.fd_set_time_block(s3, 2)
+    assert e.value.code == F.FD_EUNSUPPORTED
+    with pytest.raises(F.FdError):
+        F.fd_set_time_block(10 ** 6, 1)
+
+
+def test_tile_controls_reject_unknown_configurations(F):
+    sid = F.fd_weights_set(2, "cross", 2, oracle_weights(2, "taylor", "cross", 2))
+    with pytest.raises(F.FdError) as e:
+        F.fd_set_tile(sid, 3)
+    assert e.value.code == F.FD_EINVAL
+
+
+def _ws_bytes(F, shape, mode, K, sid, wav):
+    """fd_workspace_bytes on hand-built structs (sizing reads no buffer)."""
+    import ctypes
+    g = F.Grid(shape=shape, h=10.0, dt=1e-3, nt=100, nb=10, eta_max=1.0, vmax=3000.0).c()
+    s = F.FdShot()
+    s.stencil_id = sid
+    s.src[0], s.src[1], s.src[2] = 20, 0, 20
+    s.extent[0], s.extent[1], s.extent[2] = shape[1], 1, shape[0]
+    s.wavelet = wav.ctypes.data
+    arr = (F.FdShot * 1)(s)
+    return int(F._lib.fd_workspace_bytes(ctypes.byref(g), arr, 1, mode, K))
+
+
+def test_workspace_grows_with_window_and_checkpoints(F):
+    sid = F.fd_weights_set(2, "cross", 4, oracle_weights(2, "taylor", "cross", 4))
+    wav = np.zeros(100, np.float32)
+    fwd = _ws_bytes(F, (300, 400), 0, 1, sid, wav)
+    assert fwd >= 3 * 300 * 400 * 4          # v = (c dt/h)^2 and at least two wavefields
+    assert _ws_bytes(F, (100, 400), 0, 1, sid, wav) < fwd
+    adj10 = _ws_bytes(F, (300, 400), 1, 10, sid, wav)
+    adj50 = _ws_bytes(F, (300, 400), 1, 50, sid, wav)
+    # checkpoint pairs every K steps plus a K-step segment store: 10 pairs and
+    # 10 fields at K = 10, 2 pairs and 50 fields at K = 50
+    assert adj50 > adj10 > fwd
+    assert _ws_bytes(F, (300, 400), 1, 0, sid, wav) == 0      # ckpt_every < 1 is invalid

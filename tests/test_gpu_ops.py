@@ -51,6 +51,8 @@ def test_autotuner_picks_a_config_and_results_do_not_change(F, ndim, shape, M, t
     before = run()
     res = autotune.tune(sid, ndim, shape, M, grid, vt, src, nt=20, reps=2)
     assert (res["rows"], res["zchunk"]) == F.fd_get_tile(sid)
+    if ndim == 2:
+        assert res["tsteps"] == F.fd_get_time_block(sid)
     assert len(res["ms"]) >= 2 and not res["cached"]
     assert torch.equal(before, run())
     again = autotune.tune(sid, ndim, shape, M, grid, vt, src, nt=20, reps=2)

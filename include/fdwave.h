@@ -117,11 +117,13 @@ typedef struct {
     int flags;             /* FD_NO_GRAPH | FD_NO_BATCH, 0 for the default path */
 } fd_grid;
 
-/* fd_grid.flags: the plain execution forms, kept as baselines.
+/* fd_grid.flags: the plain execution forms, kept as baselines (results are
+ * identical across forms; any other bit is rejected with FD_EINVAL).
  * FD_NO_GRAPH: queue every kernel launch directly instead of replaying a
  *              cached HIP graph of the whole call.
  * FD_NO_BATCH: run the shots of a multi-shot call one after the other with
- *              the single-shot kernels instead of one batched launch per step. */
+ *              the single-shot kernels instead of batched launches on
+ *              concurrent branches. */
 #define FD_NO_GRAPH 1
 #define FD_NO_BATCH 2
 

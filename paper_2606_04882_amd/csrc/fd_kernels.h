@@ -16,10 +16,14 @@ constexpr int kTileX = 64;    // tile width along x = one wave
 // never read: the kernels use the centre-free difference form).  wd is the
 // same weights laid out densely by 2D offset group: wd[dx*(M+1) + dz] is the
 // weight of (dx, dz) (0 outside the shape), used by the dense 2D kernels.
+// wc[dz] (dz = 1..M) is the weight the dense 2D kernels give the centre
+// column's z difference u(z+dz) + u(z-dz) - 2u: w(0, dz) + 2 sum_dx w(dx, dz),
+// formed in FP64 from the FP32 weights and rounded once.
 constexpr int kMaxDense = 81;
 struct Weights {
     float w[kMaxOrbits];
     float wd[kMaxDense];
+    float wc[9];
 };
 
 // ---------------------------------------------------------------------------

@@ -235,7 +235,6 @@ struct Layout {
 };
 
 bool use_batch(const fd_grid* g, int nshots, int mode) {
-    (void)mode;
     return nshots > 1 && g->ndim == 2 && !(g->flags & FD_NO_BATCH);
 }
 
@@ -316,6 +315,8 @@ int check_grid(const fd_grid* g) {
     if (!g) return fail(FD_EINVAL, "grid is NULL");
     if (g->ndim != 2 && g->ndim != 3) return fail(FD_EINVAL, "ndim must be 2 or 3 (got %d)", g->ndim);
     if (g->nt < 1) return fail(FD_EINVAL, "nt must be >= 1 (got %d)", g->nt);
+    if (g->flags & ~(FD_NO_GRAPH | FD_NO_BATCH))
+        return fail(FD_EINVAL, "unknown flags 0x%x", (unsigned)g->flags);
     if (g->n[0] < 1 || g->n[2] < 1 || (g->ndim == 3 && g->n[1] < 1))
         return fail(FD_EINVAL, "model extents must be >= 1");
     if (g->ndim == 2 && g->n[1] != 1) return fail(FD_EINVAL, "2D models need n[1] == 1");
@@ -1348,6 +1349,11 @@ int fd_weights_set(int ndim, int shape, int M, const double* w, int nw, int* ste
                 for (int i = 0; i < nw; ++i)
                     if (o[i].rep[0] == a && o[i].rep[1] == b) st.w32.wd[dx * (M + 1) + dz] = (float)w[i];
             }
+        for (int dz = 1; dz <= M; ++dz) {
+            double acc = st.w32.wd[dz];
+            for (int dx = 1; dx <= M; ++dx) acc += 2.0 * (double)st.w32.wd[dx * (M + 1) + dz];
+            st.w32.wc[dz] = (float)acc;
+        }
     }
     st.cfl = 2.0 / std::sqrt(mneg);
     st.rows = default_rows(ndim, shape, M);

@@ -15,33 +15,23 @@
 
 namespace fdw {
 
-// Stencil sum at LDS position (r, c) of a tile of width LW, in the order of
-// stencil2d(): z pairs of the centre column, then x-mirror column pairs.
-template <int SHAPE, int M, int LW>
-__device__ __forceinline__ float point_stencil(const float* t, int r, int c, const Weights& W,
-                                               float& uc) {
+// Cross stencil sum at LDS position (r, c) of a tile of width LW, in the
+// order of stencil2d(): z pairs of the centre column, then x-mirror pairs.
+template <int M, int LW>
+__device__ __forceinline__ float point_cross(const float* t, int r, int c, const Weights& W, float& uc) {
     const float* p = t + r * LW + c;
     const float u = p[0];
     uc = u;
     float acc = 0.f;
 #pragma unroll
     for (int dz = 1; dz <= M; ++dz) {
-        const float w = W.w[orbit2(SHAPE, M, dz, 0)];
+        const float w = W.w[orbit2(SH_CROSS, M, dz, 0)];
         acc = fmaf(w, fmaf(-2.f, u, p[dz * LW] + p[-dz * LW]), acc);
     }
 #pragma unroll
     for (int dx = 1; dx <= M; ++dx) {
-        const int mz = maxdz2(SHAPE, M, dx);
-        const float w0 = SHAPE == SH_CROSS ? W.w[orbit2(SHAPE, M, dx, 0)] : W.wd[dx * (M + 1)];
-        acc = fmaf(w0, fmaf(-2.f, u, p[-dx] + p[dx]), acc);
-#pragma unroll
-        for (int dz = 1; dz <= M; ++dz) {
-            if (dz <= mz) {
-                const float w = W.wd[dx * (M + 1) + dz];
-                const float s = (p[dz * LW - dx] + p[dz * LW + dx]) + (p[-dz * LW - dx] + p[-dz * LW + dx]);
-                acc = fmaf(w, fmaf(-4.f, u, s), acc);
-            }
-        }
+        const float w = W.w[orbit2(SH_CROSS, M, dx, 0)];
+        acc = fmaf(w, fmaf(-2.f, u, p[-dx] + p[dx]), acc);
     }
     return acc;
 }
@@ -67,6 +57,7 @@ __device__ __forceinline__ float leapfrog(float uc, float up, float vv, float L,
 
 template <int SHAPE, int M, int RY>
 __global__ __launch_bounds__(kBlock) void k_fwd2d_tb(TbArgs p) {
+    static_assert(SHAPE == SH_CROSS, "two-step kernel is compiled for cross stencils");
     constexpr int TY = 4 * RY;
     constexpr int W0 = kTileX + 4 * M, H0 = TY + 4 * M, N0 = W0 * H0;   // u^n
     constexpr int W1 = kTileX + 2 * M, H1 = TY + 2 * M, N1 = W1 * H1;   // u^{n+1}
@@ -138,7 +129,7 @@ __global__ __launch_bounds__(kBlock) void k_fwd2d_tb(TbArgs p) {
             float out = 0.f;
             if ((unsigned)gz < (unsigned)p.nz && (unsigned)gxx < (unsigned)p.nx) {
                 float uc;
-                const float L = point_stencil<SHAPE, M, W0>(U0, r + M, c + M, p.w, uc);
+                const float L = point_cross<M, W0>(U0, r + M, c + M, p.w, uc);
                 const long long kk = (long long)gz * p.nx + gxx;
                 out = leapfrog(uc, up1[k], vv1[k], L, gxx, gz, p.nx, p.nz, p.sp, kk == p.src, qs0);
             }

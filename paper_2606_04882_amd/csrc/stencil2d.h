@@ -67,38 +67,44 @@ __device__ __forceinline__ void s2_dx(const float* tile, int tx, int ty, const f
     }
 }
 
-// Dense shapes (rhombus, square): the column offset dx runs as a real loop,
+// Dense shapes (rhombus, square).  For each column offset dx the x second
+// difference d(z) = u(x-dx, z) + u(x+dx, z) - 2 u(x, z) is formed once per
+// row; the group (dx, dz) then contributes
+//     w (d(z+dz) + d(z-dz)) + 2 w (u(x, z+dz) + u(x, z-dz) - 2 u(x, z)),
+// and the second part, summed over dx, is folded into the centre column's
+// weight wc[dz].  Every term stays a small difference of nearby values, at
+// two operations per group instead of three.  dx runs as a real loop,
 // uniform across the wave, so only one column group of LDS values is live at
 // a time (a fully unrolled form lets the compiler hoist every group's reads
-// and exhausts the register file).  W.wd holds the weight of group (dx, dz)
-// at wd[dx*(M+1) + dz]; the group extent along z for a given dx is
+// and exhausts the register file); the centre value of each row is read from
+// LDS again rather than kept in registers.  W.wd holds the weight of group
+// (dx, dz) at wd[dx*(M+1) + dz]; the group extent along z for a given dx is
 // maxdz2(SHAPE, M, dx), a wave-uniform value.
 template <int SHAPE, int M, int RY, int LW>
-__device__ __forceinline__ void s2_dense_dx(const float* tile, int tx, int ty, const float* uc,
-                                            float* acc, const Weights& W) {
+__device__ __forceinline__ void s2_dense_dx(const float* tile, int tx, int ty, float* acc,
+                                            const Weights& W) {
 #pragma unroll 1
     for (int dx = 1; dx <= M; ++dx) {
         const int mz = SHAPE == SH_RHOMBUS ? M - dx : M;
         const float* wrow = W.wd + dx * (M + 1);
-        float cs[RY + 2 * M];
+        float d[RY + 2 * M];
 #pragma unroll
         for (int j = 0; j < RY + 2 * M; ++j) {
-            cs[j] = 0.f;
+            d[j] = 0.f;
             if (j >= M - mz && j < M + RY + mz) {
                 const float* row = tile + (ty * RY + j) * LW + tx + M;
-                cs[j] = row[-dx] + row[dx];
+                d[j] = fmaf(-2.f, row[0], row[-dx] + row[dx]);
             }
         }
         const float w0 = wrow[0];
 #pragma unroll
-        for (int j = 0; j < RY; ++j) acc[j] = fmaf(w0, fmaf(-2.f, uc[j], cs[j + M]), acc[j]);
+        for (int j = 0; j < RY; ++j) acc[j] = fmaf(w0, d[j + M], acc[j]);
 #pragma unroll
         for (int dz = 1; dz <= M; ++dz) {
             if (dz <= mz) {
                 const float w = wrow[dz];
 #pragma unroll
-                for (int j = 0; j < RY; ++j)
-                    acc[j] = fmaf(w, fmaf(-4.f, uc[j], cs[j + M + dz] + cs[j + M - dz]), acc[j]);
+                for (int j = 0; j < RY; ++j) acc[j] = fmaf(w, d[j + M + dz] + d[j + M - dz], acc[j]);
             }
         }
     }
@@ -116,11 +122,19 @@ __device__ __forceinline__ void stencil2d(const float* tile, int tx, int ty, con
         uc[j] = col[j + M];
         acc[j] = 0.f;
     }
-    s2_col0<SHAPE, M, RY, LW, 1>(col, uc, acc, W);
-    if constexpr (SHAPE == SH_CROSS)
+    if constexpr (SHAPE == SH_CROSS) {
+        s2_col0<SHAPE, M, RY, LW, 1>(col, uc, acc, W);
         s2_dx<SHAPE, M, RY, LW, 1>(tile, tx, ty, uc, acc, W);
-    else
-        s2_dense_dx<SHAPE, M, RY, LW>(tile, tx, ty, uc, acc, W);
+    } else {
+#pragma unroll
+        for (int dz = 1; dz <= M; ++dz) {
+            const float w = W.wc[dz];
+#pragma unroll
+            for (int j = 0; j < RY; ++j)
+                acc[j] = fmaf(w, fmaf(-2.f, uc[j], col[j + M + dz] + col[j + M - dz]), acc[j]);
+        }
+        s2_dense_dx<SHAPE, M, RY, LW>(tile, tx, ty, acc, W);
+    }
 }
 
 // Cooperative load of the (4*RY + 2M) x (64 + 2M) tile of field f (window

@@ -143,3 +143,19 @@ def test_workspace_grows_with_window_and_checkpoints(F):
     # 10 fields at K = 10, 2 pairs and 50 fields at K = 50
     assert adj50 > adj10 > fwd
     assert _ws_bytes(F, (300, 400), 1, 0, sid, wav) == 0      # ckpt_every < 1 is invalid
+
+
+def test_unknown_flags_are_rejected(F):
+    import ctypes
+    sid = F.fd_weights_set(2, "cross", 2, oracle_weights(2, "taylor", "cross", 2))
+    g = F.Grid(shape=(40, 50), h=10.0, dt=1e-3, nt=10, nb=0, vmax=3000.0, flags=8).c()
+    s = F.FdShot()
+    s.stencil_id = sid
+    s.extent[0], s.extent[1], s.extent[2] = 50, 1, 40
+    wav = np.zeros(10, np.float32)
+    s.wavelet = wav.ctypes.data
+    arr = (F.FdShot * 1)(s)
+    # validation runs before any device work: a null velocity and workspace
+    # would be reported only after the flags
+    rc = F._lib.fd_forward(ctypes.byref(g), ctypes.c_void_p(16), arr, 1, None, 0, None)
+    assert rc == F.FD_EINVAL and "flags" in F.fd_last_error()

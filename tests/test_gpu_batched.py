@@ -170,3 +170,38 @@ def test_3d_shots_on_branches_equal_shot_after_shot(F):
     for (a, fa), (b, fb), (c, fc) in zip(par, seq, direct):
         assert torch.equal(a, b) and torch.equal(fa, fb) and torch.equal(a, c) and torch.equal(fa, fc)
         assert fa.abs().max() > 0
+
+
+@pytest.mark.parametrize("nshots", [16, 17, 23])
+def test_large_variant_group_equals_shot_after_shot(F, nshots):
+    """One stencil variant over many small shots (up to 16 the block-to-shot
+    map travels in the kernel arguments, beyond that in the work list):
+    traces equal the shot-after-shot path bitwise."""
+    from tests.fdcase import layered
+    NZ, NX, h, nt, nb = 50, 260, 10.0, 50, 6
+    model = layered((NZ, NX), seed=21)
+    vmax = float(model.max())
+    dt = 0.5 * 0.45 * h / vmax
+    sid = F.fd_weights_set(2, "cross", 3, oracle_weights(2, "taylor", "cross", 3))
+    wav = torch.tensor(synth.ricker(nt, dt, 30.0).astype(np.float32), device=DEV)
+    shots = []
+    for k in range(nshots):
+        ex, ez = 40 + (k * 37) % 150, 20 + (k * 11) % 30
+        ox = (k * 53) % (NX - ex)
+        rec = np.array([[x, 3] for x in range(0, ex, 4)], dtype=np.int32)
+        shots.append(F.Shot(stencil_id=sid, src=(ex // 2, ez // 2), wavelet=wav,
+                            rec=torch.tensor(rec, device=DEV), traces=torch.zeros(nt, len(rec), device=DEV),
+                            origin=(ox, 0, NZ - ez), extent=(ex, 1, ez)))
+    vel = torch.tensor(model, device=DEV)
+    g = F.Grid(shape=model.shape, h=h, dt=dt, nt=nt, nb=nb, eta_max=synth.sponge_eta_max(vmax, nb, h),
+               vmax=vmax)
+    F.fd_forward(g, vel, shots)
+    torch.cuda.synchronize()
+    batched = [s.traces.clone() for s in shots]
+    g1 = F.Grid(shape=model.shape, h=h, dt=dt, nt=nt, nb=nb, eta_max=synth.sponge_eta_max(vmax, nb, h),
+                vmax=vmax, flags=F.FD_NO_BATCH)
+    F.fd_forward(g1, vel, shots)
+    torch.cuda.synchronize()
+    for b, s in zip(batched, shots):
+        assert torch.equal(b, s.traces)
+        assert b.abs().max() > 0

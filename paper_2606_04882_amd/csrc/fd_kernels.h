@@ -11,6 +11,9 @@ enum { SH_CROSS = 0, SH_RHOMBUS = 1, SH_SQUARE = 2 };
 constexpr int kMaxOrbits = 64;
 constexpr int kBlock = 256;   // threads per block: 4 waves of 64
 constexpr int kTileX = 64;    // tile width along x = one wave
+// 3D kernels: waves per block; a block's tile is 64 x kWaves3 * rows in xy
+constexpr int kWaves3 = 8;
+constexpr int kBlock3 = 64 * kWaves3;
 
 // FP32 weights, one per orbit in canonical order (orbit 0, the centre, is
 // never read: the kernels use the centre-free difference form).  wd is the

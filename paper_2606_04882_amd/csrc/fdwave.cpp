@@ -200,10 +200,12 @@ struct Stencil {
 std::mutex g_mu;
 std::vector<Stencil> g_stencils;
 
+// Untuned defaults (the autotuner installs measured choices): 2D tiles of
+// 64 x 16; 3D tiles of 64 x 8 (64 x 16 for crosses with M > 4).
 int default_rows(int ndim, int shape, int M) {
     if (ndim == 2) return 4;
-    if (shape == FD_CROSS) return 2;
-    return M <= 4 ? 2 : 1;
+    if (shape == FD_CROSS) return M <= 4 ? 1 : 2;
+    return 1;
 }
 
 bool get_stencil(int id, Stencil* out) {
@@ -556,7 +558,7 @@ void fill_tiles(StepArgs& a, int ndim, int rows, int zchunk) {
         a.zchunk = 0;
     } else {
         a.tiles_x = (a.nx + kTileX - 1) / kTileX;
-        a.tiles_y = (a.ny + 4 * rows - 1) / (4 * rows);
+        a.tiles_y = (a.ny + kWaves3 * rows - 1) / (kWaves3 * rows);
         const int tz = (a.nz + zchunk - 1) / zchunk;
         a.ntiles = a.tiles_x * a.tiles_y * tz;
         a.zchunk = zchunk;
@@ -1357,7 +1359,7 @@ int fd_weights_set(int ndim, int shape, int M, const double* w, int nw, int* ste
     }
     st.cfl = 2.0 / std::sqrt(mneg);
     st.rows = default_rows(ndim, shape, M);
-    st.zchunk = 64;
+    st.zchunk = (ndim == 3 && shape == FD_CROSS) ? 128 : 64;
     st.tsteps = (ndim == 2 && have_fwd2d_tb(shape, M, st.rows)) ? 2 : 1;
     std::lock_guard<std::mutex> lk(g_mu);
     for (size_t i = 0; i < g_stencils.size(); ++i) {

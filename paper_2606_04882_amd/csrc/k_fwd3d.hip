@@ -1,8 +1,9 @@
 // 3D forward and adjoint steps.
 //
 // Same update as the 2D kernels (Sec. 3.1-3.2, the 3D extension noted at the
-// end of Sec. 3.1), on [nz][ny][nx] windows.  A block owns a 64 (x) by 4*RY (y)
-// column of the grid and marches along z through `zchunk` planes:
+// end of Sec. 3.1), on [nz][ny][nx] windows.  A block of kWaves3 waves owns a
+// 64 (x) by kWaves3*RY (y) column of the grid and marches along z through
+// `zchunk` planes:
 //
 //  * cross stencils keep the 2M+1 values of u along z for each of the thread's
 //    RY points in registers (a queue shifted once per plane) and stage only the
@@ -27,7 +28,7 @@ namespace {
 template <int M, int RY>
 struct Geo3 {
     static constexpr int LW = kTileX + 2 * M;
-    static constexpr int LH = 4 * RY + 2 * M;
+    static constexpr int LH = kWaves3 * RY + 2 * M;
     static constexpr int PLANE = LH * LW;
 };
 
@@ -52,8 +53,8 @@ __device__ __forceinline__ float damp_e(const Sponge& sp, int gx, int gy, int gz
 template <int M, int RY>
 struct Halo {
     static constexpr int LW = Geo3<M, RY>::LW;
-    static constexpr int TOPN = M * LW, SIDEN = 4 * RY * M, H = 2 * TOPN + 2 * SIDEN;
-    static constexpr int NL = (H + kBlock - 1) / kBlock;
+    static constexpr int TOPN = M * LW, SIDEN = kWaves3 * RY * M, H = 2 * TOPN + 2 * SIDEN;
+    static constexpr int NL = (H + kBlock3 - 1) / kBlock3;
     float val[NL];
 
     __device__ __forceinline__ static int pos(int i, int& r, int& c) {
@@ -62,7 +63,7 @@ struct Halo {
             c = i - r * LW;
         } else if (i < 2 * TOPN) {
             const int q = i - TOPN;
-            r = M + 4 * RY + q / LW;
+            r = M + kWaves3 * RY + q / LW;
             c = q % LW;
         } else {
             int q = i - 2 * TOPN;
@@ -78,7 +79,7 @@ struct Halo {
         const bool zok = (unsigned)z < (unsigned)nz;
 #pragma unroll
         for (int k = 0; k < NL; ++k) {
-            const int i = threadIdx.x + k * kBlock;
+            const int i = threadIdx.x + k * kBlock3;
             int r, c;
             pos(i, r, c);
             const int gy = y0 - M + r, gx = x0 - M + c;
@@ -90,7 +91,7 @@ struct Halo {
     __device__ __forceinline__ void store(float* tile) const {
 #pragma unroll
         for (int k = 0; k < NL; ++k) {
-            const int i = threadIdx.x + k * kBlock;
+            const int i = threadIdx.x + k * kBlock3;
             int r, c;
             const int at = pos(i, r, c);
             if (i < H) tile[at] = val[k];
@@ -111,12 +112,12 @@ template <int M, int RY>
 __device__ __forceinline__ void load_plane(float* tile, const float* __restrict__ f, int nx, int ny,
                                            int nz, int x0, int y0, int z) {
     using G = Geo3<M, RY>;
-    constexpr int NL = (G::PLANE + kBlock - 1) / kBlock;
+    constexpr int NL = (G::PLANE + kBlock3 - 1) / kBlock3;
     const bool zok = (unsigned)z < (unsigned)nz;
     float val[NL];
 #pragma unroll
     for (int k = 0; k < NL; ++k) {
-        const int i = threadIdx.x + k * kBlock;
+        const int i = threadIdx.x + k * kBlock3;
         const int r = i / G::LW, c = i - r * G::LW;
         const int gy = y0 - M + r, gx = x0 - M + c;
         val[k] = 0.f;
@@ -125,7 +126,7 @@ __device__ __forceinline__ void load_plane(float* tile, const float* __restrict_
     }
 #pragma unroll
     for (int k = 0; k < NL; ++k) {
-        const int i = threadIdx.x + k * kBlock;
+        const int i = threadIdx.x + k * kBlock3;
         if (i < G::PLANE) tile[i] = val[k];
     }
 }
@@ -143,7 +144,7 @@ __device__ __forceinline__ Pos3 block_pos(int ntiles, int tiles_x, int tiles_y, 
     const int bx = t % tiles_x, t2 = t / tiles_x;
     const int by = t2 % tiles_y, bz = t2 / tiles_y;
     q.x0 = bx * kTileX;
-    q.y0 = by * 4 * RY;
+    q.y0 = by * kWaves3 * RY;
     q.zs = bz * zchunk;
     q.ze = min(q.zs + zchunk, nz);
     q.gx = q.x0 + q.tx;
@@ -175,12 +176,12 @@ __device__ __forceinline__ float cross_sum(const float* tile, const float* q, in
 // rewritten only after every thread has passed the barrier of the plane in
 // between).
 template <int M, int RY>
-__global__ __launch_bounds__(kBlock) void k_fwd3d_cross(StepArgs p) {
+__global__ __launch_bounds__(kBlock3) void k_fwd3d_cross(StepArgs p) {
     using G = Geo3<M, RY>;
     constexpr int NQ = 2 * M + 1;
     __shared__ float tiles[2][G::PLANE];
     if (p.trace_out) {
-        for (int r = blockIdx.x * kBlock + threadIdx.x; r < p.nrec; r += gridDim.x * kBlock) {
+        for (int r = blockIdx.x * kBlock3 + threadIdx.x; r < p.nrec; r += gridDim.x * kBlock3) {
             const long long i = p.rec_lin[r];
             p.trace_out[r] = i >= 0 ? p.ucur[i] : 0.f;
         }
@@ -211,8 +212,8 @@ __global__ __launch_bounds__(kBlock) void k_fwd3d_cross(StepArgs p) {
             const int zz = z + M;
             const bool in = ok[j] && z < b.ze;
             front[j] = (in && zz < p.nz) ? p.ucur[zz * plane + col[j]] : 0.f;
-            up[j] = in ? p.uprev[z * plane + col[j]] : 0.f;
-            vv[j] = in ? p.v[(long long)z * p.ldv_z + vcol[j]] : 0.f;
+            up[j] = in ? __builtin_nontemporal_load(p.uprev + z * plane + col[j]) : 0.f;
+            vv[j] = in ? __builtin_nontemporal_load(p.v + (long long)z * p.ldv_z + vcol[j]) : 0.f;
         }
         if (z < b.ze) halo.fetch(p.ucur, p.nx, p.ny, p.nz, b.x0, b.y0, z);
     };
@@ -250,7 +251,7 @@ __global__ __launch_bounds__(kBlock) void k_fwd3d_cross(StepArgs p) {
                     if (k == p.src) r += p.q * p.wavelet[p.step];
                     r = r / (1.f + e);
                 }
-                p.unext[k] = r;
+                __builtin_nontemporal_store(r, p.unext + k);
             }
         }
 #pragma unroll
@@ -262,7 +263,7 @@ __global__ __launch_bounds__(kBlock) void k_fwd3d_cross(StepArgs p) {
 }
 
 template <int M, int RY>
-__global__ __launch_bounds__(kBlock) void k_adj3d_cross(AdjArgs p) {
+__global__ __launch_bounds__(kBlock3) void k_adj3d_cross(AdjArgs p) {
     using G = Geo3<M, RY>;
     constexpr int NQ = 2 * M + 1;
     __shared__ float tp[G::PLANE];
@@ -411,14 +412,14 @@ struct RingLDS {
 template <int M, int RY>
 struct PlaneRegs {
     static constexpr int N = Geo3<M, RY>::PLANE, LW = Geo3<M, RY>::LW;
-    static constexpr int NL = (N + kBlock - 1) / kBlock;
+    static constexpr int NL = (N + kBlock3 - 1) / kBlock3;
     float val[NL];
     __device__ __forceinline__ void fetch(const float* __restrict__ f, int nx, int ny, int nz, int x0,
                                           int y0, int z) {
         const bool zok = (unsigned)z < (unsigned)nz;
 #pragma unroll
         for (int k = 0; k < NL; ++k) {
-            const int i = threadIdx.x + k * kBlock;
+            const int i = threadIdx.x + k * kBlock3;
             const int r = i / LW, c = i - r * LW;
             const int gy = y0 - M + r, gx = x0 - M + c;
             val[k] = 0.f;
@@ -429,7 +430,7 @@ struct PlaneRegs {
     __device__ __forceinline__ void store(float* tile) const {
 #pragma unroll
         for (int k = 0; k < NL; ++k) {
-            const int i = threadIdx.x + k * kBlock;
+            const int i = threadIdx.x + k * kBlock3;
             if (i < N) tile[i] = val[k];
         }
     }
@@ -441,12 +442,12 @@ struct PlaneRegs {
 // passed; so one barrier per plane suffices, and the global loads of plane
 // z+M+2 are in flight during the computation.
 template <int SHAPE, int M, int RY>
-__global__ __launch_bounds__(kBlock) void k_fwd3d_gen(StepArgs p) {
+__global__ __launch_bounds__(kBlock3) void k_fwd3d_gen(StepArgs p) {
     using G = Geo3<M, RY>;
     constexpr int NR = 2 * M + 2;
     __shared__ float ring[NR * G::PLANE];
     if (p.trace_out) {
-        for (int r = blockIdx.x * kBlock + threadIdx.x; r < p.nrec; r += gridDim.x * kBlock) {
+        for (int r = blockIdx.x * kBlock3 + threadIdx.x; r < p.nrec; r += gridDim.x * kBlock3) {
             const long long i = p.rec_lin[r];
             p.trace_out[r] = i >= 0 ? p.ucur[i] : 0.f;
         }
@@ -512,7 +513,7 @@ __global__ __launch_bounds__(kBlock) void k_fwd3d_gen(StepArgs p) {
 }
 
 template <int SHAPE, int M, int RY>
-__global__ __launch_bounds__(kBlock) void k_adj3d_gen(AdjArgs p) {
+__global__ __launch_bounds__(kBlock3) void k_adj3d_gen(AdjArgs p) {
     using G = Geo3<M, RY>;
     constexpr int NP = 2 * M + 1;
     __shared__ RingLDS<SHAPE, M, RY, 2> L;
@@ -597,19 +598,19 @@ bool have_fwd3d(int shape, int M, int rows) {
 
 template <int M, int RY>
 static void run_cross(const StepArgs& a, hipStream_t s) {
-    hipLaunchKernelGGL((k_fwd3d_cross<M, RY>), dim3(a.ntiles), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL((k_fwd3d_cross<M, RY>), dim3(a.ntiles), dim3(kBlock3), 0, s, a);
 }
 template <int M, int RY>
 static void run_cross_adj(const AdjArgs& a, hipStream_t s) {
-    hipLaunchKernelGGL((k_adj3d_cross<M, RY>), dim3(a.ntiles), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL((k_adj3d_cross<M, RY>), dim3(a.ntiles), dim3(kBlock3), 0, s, a);
 }
 template <int SHAPE, int M, int RY>
 static void run_gen(const StepArgs& a, hipStream_t s) {
-    hipLaunchKernelGGL((k_fwd3d_gen<SHAPE, M, RY>), dim3(a.ntiles), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL((k_fwd3d_gen<SHAPE, M, RY>), dim3(a.ntiles), dim3(kBlock3), 0, s, a);
 }
 template <int SHAPE, int M, int RY>
 static void run_gen_adj(const AdjArgs& a, hipStream_t s) {
-    hipLaunchKernelGGL((k_adj3d_gen<SHAPE, M, RY>), dim3(a.ntiles), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL((k_adj3d_gen<SHAPE, M, RY>), dim3(a.ntiles), dim3(kBlock3), 0, s, a);
 }
 
 template <int M>

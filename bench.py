@@ -437,14 +437,36 @@ def fwi_bench(torch, F, design, configs, dev):
             "speedup_vs_plain": round(t_plain / t_fast, 3), "grad_rel_diff_vs_plain": diff}
 
 
+def _gomp():
+    """libgomp, as loaded by the oracle's shared library (thread controls)."""
+    import ctypes
+    try:
+        return ctypes.CDLL("libgomp.so.1")
+    except OSError:
+        return None
+
+
+def _cpu_model() -> str:
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(w, vel_np, budget_s):
     """The FP64 oracle (plain C, OpenMP over the slowest axis) on this host:
     each of the eight stencils advanced a few steps on the full 1001 x 1001
-    model; rate in Gpt-updates/s.  Bounded to about budget_s seconds."""
+    model with every host thread, then one stencil on one thread; rates in
+    Gpt-updates/s.  Bounded to about budget_s seconds."""
     from oracle import stepper as S
     from oracle import weights as W
     from fractions import Fraction
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    S.build(force=False)
+    gomp = _gomp()
+    cores = int(gomp.omp_get_max_threads()) if gomp else int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     v = S.v_from_c(vel_np.astype(np.float64), w.dt, w.h)
     q = S.source_term(w.wavelet(), w.dt, w.h, 2)
     sts = []
@@ -468,9 +490,23 @@ def cpu_baseline(w, vel_np, budget_s):
         S.forward(st, v, w.dt, nsteps, w.nb, w.eta_max, w.src, q[:nsteps], w.rec)
     el = time.perf_counter() - t0
     rate = len(sts) * nsteps * int(np.prod(w.shape)) / el
-    return {"value": round(rate / 1e9, 5), "unit": "Gpt-updates/s", "cores": cores, "kind": "oracle",
-            "sample": f"8 stencils x {nsteps} steps on the full {w.shape[1]}x{w.shape[0]} model, FP64",
-            "seconds": round(el, 2)}
+    out = {"value": round(rate / 1e9, 5), "unit": "Gpt-updates/s", "cores": cores, "kind": "oracle",
+           "sample": f"8 stencils x {nsteps} steps on the full {w.shape[1]}x{w.shape[0]} model, FP64",
+           "seconds": round(el, 2), "cpu": _cpu_model()}
+    if gomp:
+        gomp.omp_set_num_threads(1)
+        try:
+            st = sts[0]
+            n1 = max(1, min(20, int(0.25 * budget_s / max(one / len(sts) * cores, 1e-3))))
+            t0 = time.perf_counter()
+            S.forward(st, v, w.dt, n1, w.nb, w.eta_max, w.src, q[:n1], w.rec)
+            el1 = time.perf_counter() - t0
+            out["single_thread"] = {"value": round(n1 * int(np.prod(w.shape)) / el1 / 1e9, 5),
+                                    "sample": f"{w.stencils[0][0]} {w.stencils[0][1]} M={w.stencils[0][2]} x {n1} steps",
+                                    "seconds": round(el1, 2)}
+        finally:
+            gomp.omp_set_num_threads(cores)
+    return out
 
 
 if __name__ == "__main__":

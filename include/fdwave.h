@@ -59,7 +59,13 @@ typedef enum {
     FD_CROSS = 0,    /* |d_i| <= M on one axis only (Sec. 4.1, P = Q = 0) */
     FD_RHOMBUS = 1,  /* sum |d_i| <= M (Sec. 4.1: Q = floor(M/2), P0(q) = q,
                         P(q) = M - q); in 3D the L1 ball */
-    FD_SQUARE = 2    /* max |d_i| <= M (Sec. 4.1: Q = M, P0(q) = q, P(q) = M) */
+    FD_SQUARE = 2,   /* max |d_i| <= M (Sec. 4.1: Q = M, P0(q) = q, P(q) = M) */
+    FD_CROSS_RHOMBUS = 3,  /* 2D: the cross of radius M plus the rhombus
+                              |x| + |z| <= N, 0 <= N <= M (Sec. 4.1:
+                              Q = floor(N/2), P0(q) = q, P(q) = N - q) */
+    FD_CROSS_SQUARE = 4    /* 2D: max(|x|, |z|) <= M and min(|x|, |z|) <= N,
+                              0 <= N <= M, a cross with arms N cells thick
+                              (Sec. 4.1: Q = N, P0(q) = q, P(q) = M) */
 } fd_shape;
 
 #define FD_MAX_RADIUS 8      /* largest M with compiled kernels */
@@ -81,6 +87,14 @@ typedef enum {
 int fd_orbits(int ndim, int shape, int M, int* reps, int* counts, int* nw);
 
 /*
+ * fd_orbits for shapes with an inner size N (FD_CROSS_RHOMBUS,
+ * FD_CROSS_SQUARE: 2D only, 0 <= N <= M); the basic shapes take N = 0, and
+ * fd_orbits(...) is fd_orbits_n(..., N = 0, ...).  Errors: FD_EINVAL for a bad
+ * combination of ndim, shape, M and N.
+ */
+int fd_orbits_n(int ndim, int shape, int M, int N, int* reps, int* counts, int* nw);
+
+/*
  * Register a stencil: one FP64 weight per orbit, in fd_orbits order, scaled
  * so that h^2 lap(u)(x) ~ sum_d w_d u(x + d) (Sec. 3.2).  Checks
  *   - nw matches fd_orbits (else FD_EINVAL);
@@ -96,6 +110,14 @@ int fd_orbits(int ndim, int shape, int M, int* reps, int* counts, int* nw);
  * Thread-safe.  Registering identical weights again returns the same id.
  */
 int fd_weights_set(int ndim, int shape, int M, const double* w, int nw, int* stencil_id);
+
+/*
+ * fd_weights_set for shapes with an inner size N (see fd_orbits_n); weights in
+ * fd_orbits_n order.  Same checks, errors and handle.  N-shapes without
+ * off-axis points (cross-rhombus N <= 1, cross-square N = 0) run the cross
+ * kernels; the others run the dense 2D kernels.
+ */
+int fd_weights_set_n(int ndim, int shape, int M, int N, const double* w, int nw, int* stencil_id);
 
 /* FP64 stability limit of a registered stencil ([host, out] c_lim). */
 int fd_cfl_limit(int stencil_id, double* c_lim);

@@ -44,6 +44,10 @@ Schemes:
           k = beta (cos theta, sin theta).  The centre weight follows from
           r = 0 (eq. taylor_system_r0_spec).  Floating point; parity unpinned
           (the paper prints neither the band b nor any weight values).
+  DispLS  Sec. 3.4.3, cosine form eq. displs_cont_linsys: as SpecLS with the
+          denominator Psi_2 = (2 - 2 cos(C beta)) / C^2 instead of beta^2.
+  SpecTE-theta / DispTE-theta  Sec. 3.3.2 / 3.4.2: the cross systems in
+          polar wavenumbers at one angle theta (the paper uses pi/8).
 """
 from __future__ import annotations
 
@@ -151,14 +155,17 @@ def moment_lhs(alpha: Tuple[int, ...], pts: Sequence[Offset]) -> int:
     return sum(math.prod(d[i] ** (2 * alpha[i]) for i in range(len(alpha))) for d in pts)
 
 
-def moment_system(ndim: int, shape: str, M: int, C, N: int = 0, mixed: bool = True):
-    """Rows (alpha, [lhs per non-centre orbit], rhs) of the DispTE system."""
+def moment_system(ndim: int, shape: str, M: int, C, N: int = 0, mixed: bool = True, mixed_max: int = 0):
+    """Rows (alpha, [lhs per non-centre orbit], rhs) of the DispTE system;
+    mixed-derivative rows (more than one non-zero alpha_i) only for orders
+    r <= mixed_max when mixed_max > 0."""
     C = Fraction(C)
     orbs = orbits(ndim, shape, M, N)[1:]
     rows = []
     for r in range(1, M + 1):
         for alpha in _partitions(r, ndim):
-            if not mixed and sum(1 for a in alpha if a) > 1:
+            is_mixed = sum(1 for a in alpha if a) > 1
+            if is_mixed and (not mixed or (mixed_max > 0 and r > mixed_max)):
                 continue
             rows.append((alpha, [moment_lhs(alpha, pts) for _, pts in orbs], moment_rhs(alpha, C)))
     return rows
@@ -171,9 +178,17 @@ def _with_centre(ndim, shape, M, w_rest: List[Fraction], N: int = 0) -> List[Fra
 
 
 def dispte(ndim: int, shape: str, M: int, C, N: int = 0) -> List[Fraction]:
-    """DispTE weights per orbit (exact). C = 0 gives SpatTE/SpecTE."""
+    """DispTE weights per orbit (exact). C = 0 gives SpatTE/SpecTE.
+
+    Cross-rhombus(M, N) (Sec. 4.2 states its system is square): the main
+    equations for r = 1..M and the mixed ones for 2 <= r <= N, i.e.
+    sum_{r<=N} floor(r/2) = floor(N^2/4) mixed rows for as many off-axis
+    weights.  N <= 1 gives the cross system, N = M the rhombus system."""
     mixed = shape != "cross"
-    rows = moment_system(ndim, shape, M, C, N, mixed=mixed)
+    mixed_max = N if shape == "cross_rhombus" else 0
+    if shape == "cross_rhombus" and N <= 1:
+        mixed = False
+    rows = moment_system(ndim, shape, M, C, N, mixed=mixed, mixed_max=mixed_max)
     A = [[Fraction(x) for x in lhs] for _, lhs, _ in rows]
     b = [rhs for _, _, rhs in rows]
     if len(A) != len(A[0]):
@@ -221,6 +236,84 @@ def specls(ndim: int, shape: str, M: int, band: float = math.pi, nbeta: int = 96
     rest = [float(x) for x in sol]
     centre = -sum(len(pts) * w for (_, pts), w in zip(orbs, rest))
     return [centre] + rest
+
+
+def displs(ndim: int, shape: str, M: int, C: float, band: float = math.pi, nbeta: int = 96,
+           ntheta: int = 96, N: int = 0) -> List[float]:
+    """DispLS weights per orbit (2D), the cosine form of Sec. 3.4.3
+    (eq. displs_cont_linsys): least squares of sum_o w_o Phi_o - 1 with the
+    orbit symbol deficit divided by Psi_2(beta) = (2 - 2 cos(C beta)) / C^2
+    (the printed Psi_2 drops a factor 2 on the cosine; with it, Psi_2 -> beta^2
+    as C -> 0 and DispLS reduces to SpecLS).  Same quadrature as specls.
+    Parity unpinned (no printed band or values)."""
+    if ndim != 2:
+        raise ValueError("DispLS is defined for 2D stencils")
+    if not C > 0:
+        return specls(ndim, shape, M, band, nbeta, ntheta, N)
+    orbs = orbits(ndim, shape, M, N)[1:]
+    xg, wg = np.polynomial.legendre.leggauss(nbeta)
+    beta = 0.5 * band * (xg + 1.0)
+    wb = 0.5 * band * wg
+    theta = (np.arange(ntheta) + 0.5) * (2.0 * math.pi / ntheta)
+    wt = np.full(ntheta, 2.0 * math.pi / ntheta)
+    B, T = np.meshgrid(beta, theta, indexing="ij")
+    Wq = np.sqrt(np.outer(wb, wt)).ravel()
+    kx = (B * np.cos(T)).ravel()
+    kz = (B * np.sin(T)).ravel()
+    psi2 = (4.0 * np.sin(0.5 * C * B) ** 2 / (C * C)).ravel()   # (2 - 2 cos(C beta)) / C^2
+    cols = []
+    for _, pts in orbs:
+        s = np.zeros_like(kx)
+        for d in pts:
+            s += 1.0 - np.cos(kx * d[0] + kz * d[1])
+        cols.append(s / psi2)
+    A = np.stack(cols, axis=1) * Wq[:, None]
+    sol, *_ = np.linalg.lstsq(A, Wq.copy(), rcond=None)
+    rest = [float(x) for x in sol]
+    centre = -sum(len(pts) * w for (_, pts), w in zip(orbs, rest))
+    return [centre] + rest
+
+
+def _cos_decimal(x, prec: int = 60):
+    """cos(x) to `prec` digits (Taylor series in decimal arithmetic)."""
+    import decimal
+    with decimal.localcontext() as ctx:
+        ctx.prec = prec + 10
+        x = decimal.Decimal(x)
+        term, total, n = decimal.Decimal(1), decimal.Decimal(1), 0
+        eps = decimal.Decimal(10) ** (-(prec + 5))
+        while abs(term) > eps:
+            n += 2
+            term = -term * x * x / (n * (n - 1))
+            total += term
+        return +total
+
+
+def dispte_theta(M: int, C, theta) -> List[Fraction]:
+    """DispTE-theta cross weights (Sec. 3.4.2, eqs. taylor_system_r1_disp_theta
+    and taylor_system_r_s0_disp_theta): for r = 1..M,
+        sum_m m^(2r) (cos^(2r) theta + sin^(2r) theta) a_m = C^(2r-2)
+    (r = 1 reads 1), solved exactly over the rationals with cos^2 theta to 60
+    digits; the centre follows from r = 0.  C = 0 gives SpecTE-theta, theta = 0
+    the plain DispTE / SpatTE cross.  `theta` is a float or a Decimal."""
+    import decimal
+    C = Fraction(C)
+    c = _cos_decimal(theta)
+    c2 = Fraction(c * c)
+    s2 = 1 - c2
+    A, b = [], []
+    for r in range(1, M + 1):
+        f = c2 ** r + s2 ** r
+        A.append([Fraction(m) ** (2 * r) * f for m in range(1, M + 1)])
+        b.append(C ** (2 * r - 2))
+    a = solve_exact(A, b)
+    return [-4 * sum(a)] + a
+
+
+def specte_theta(M: int, theta) -> List[Fraction]:
+    """SpecTE-theta cross weights (Sec. 3.3.2, eqs. taylor_system_r1_spec and
+    taylor_system_r_s0_spec): DispTE-theta with C = 0."""
+    return dispte_theta(M, 0, theta)
 
 
 # --------------------------------------------------------------------------

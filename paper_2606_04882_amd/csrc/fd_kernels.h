@@ -21,12 +21,16 @@ constexpr int kBlock3 = 64 * kWaves3;
 // weight of (dx, dz) (0 outside the shape), used by the dense 2D kernels.
 // wc[dz] (dz = 1..M) is the weight the dense 2D kernels give the centre
 // column's z difference u(z+dz) + u(z-dz) - 2u: w(0, dz) + 2 sum_dx w(dx, dz),
-// formed in FP64 from the FP32 weights and rounded once.
+// formed in FP64 from the FP32 weights and rounded once.  mz[dx] (dx = 1..M)
+// is the z extent of the dense 2D kernels' offset group at column dx: the
+// shape holds (dx, dz) exactly for dz = 0..mz[dx].  For the cross kernels,
+// w[m] is the weight of the axis offset m.
 constexpr int kMaxDense = 81;
 struct Weights {
     float w[kMaxOrbits];
     float wd[kMaxDense];
     float wc[9];
+    int mz[9];
 };
 
 // ---------------------------------------------------------------------------

@@ -55,23 +55,28 @@ struct Orbit {
     int count;
 };
 
-bool in_shape(int ndim, int shape, int M, int a, int b, int c) {
-    // a >= b >= c >= 0 (c = 0 in 2D)
+// Point sets of Sec. 4.1 (a >= b >= c >= 0 the sorted absolute offsets, c = 0
+// in 2D): cross, rhombus (|x|+|z| <= M), square (max <= M), cross-rhombus
+// (the cross of radius M plus the rhombus of size N) and cross-square (max
+// <= M with the smaller offset <= N: a cross with arms N thick).
+bool in_shape(int ndim, int shape, int M, int N, int a, int b, int c) {
     (void)ndim;
     switch (shape) {
         case FD_CROSS: return b == 0 && c == 0 && a <= M;
         case FD_RHOMBUS: return a + b + c <= M;
         case FD_SQUARE: return a <= M;
+        case FD_CROSS_RHOMBUS: return (b == 0 && c == 0 && a <= M) || a + b + c <= N;
+        case FD_CROSS_SQUARE: return a <= M && b <= N && c <= N;
     }
     return false;
 }
 
-std::vector<Orbit> make_orbits(int ndim, int shape, int M) {
+std::vector<Orbit> make_orbits(int ndim, int shape, int M, int N) {
     std::vector<Orbit> out;
     for (int a = 0; a <= M; ++a)
         for (int b = 0; b <= a; ++b)
             for (int c = 0; c <= (ndim == 3 ? b : 0); ++c) {
-                if (!in_shape(ndim, shape, M, a, b, c)) continue;
+                if (!in_shape(ndim, shape, M, N, a, b, c)) continue;
                 Orbit o{{a, b, c}, 0};
                 out.push_back(o);
             }
@@ -93,9 +98,26 @@ std::vector<Orbit> make_orbits(int ndim, int shape, int M) {
     return out;
 }
 
-bool valid_shape(int ndim, int shape, int M) {
-    return (ndim == 2 || ndim == 3) && shape >= FD_CROSS && shape <= FD_SQUARE && M >= 1 &&
-           M <= FD_MAX_RADIUS;
+// N-shapes are 2D (Sec. 4.1 defines them in 2D) with 0 <= N <= M; the basic
+// shapes take N = 0.
+bool valid_shape(int ndim, int shape, int M, int N) {
+    if (!(ndim == 2 || ndim == 3) || M < 1 || M > FD_MAX_RADIUS) return false;
+    if (shape >= FD_CROSS && shape <= FD_SQUARE) return N == 0;
+    if (shape == FD_CROSS_RHOMBUS || shape == FD_CROSS_SQUARE) return ndim == 2 && N >= 0 && N <= M;
+    return false;
+}
+
+// Kernel family of a shape: N-shapes without off-axis points are crosses;
+// the others run the dense 2D kernels, which take each column's extent from
+// the stencil's mz table.
+int kernel_shape(int shape, int N) {
+    switch (shape) {
+        case FD_CROSS: return SH_CROSS;
+        case FD_RHOMBUS: return SH_RHOMBUS;
+        case FD_CROSS_RHOMBUS: return N <= 1 ? SH_CROSS : SH_SQUARE;
+        case FD_CROSS_SQUARE: return N == 0 ? SH_CROSS : SH_SQUARE;
+        default: return SH_SQUARE;
+    }
 }
 
 // S(k) = sum_d w_d cos(k.d).  Summing an orbit over sign flips turns
@@ -125,7 +147,7 @@ struct Symbol {
     }
 };
 
-Symbol make_symbol(int ndim, int shape, int M, const std::vector<Orbit>& orbs,
+Symbol make_symbol(int ndim, int shape, int M, int N, const std::vector<Orbit>& orbs,
                    const double* w) {
     Symbol S{ndim, M, {}};
     const int n = M + 1;
@@ -137,7 +159,7 @@ Symbol make_symbol(int ndim, int shape, int M, const std::vector<Orbit>& orbs,
                 if (ndim == 2) { v[1] = c; v[2] = 0; }
                 int s[3] = {v[0], v[1], v[2]};
                 std::sort(s, s + 3, [](int p, int q) { return p > q; });
-                if (!in_shape(ndim, shape, M, s[0], s[1], s[2])) continue;
+                if (!in_shape(ndim, shape, M, N, s[0], s[1], s[2])) continue;
                 int oi = -1;
                 for (size_t i = 0; i < orbs.size(); ++i)
                     if (orbs[i].rep[0] == s[0] && orbs[i].rep[1] == s[1] && orbs[i].rep[2] == s[2])
@@ -189,7 +211,8 @@ void symbol_extrema(const Symbol& S, double* max_neg, double* max_pos) {
 // stencil registry
 // ---------------------------------------------------------------------------
 struct Stencil {
-    int ndim, shape, M, nw;
+    int ndim, shape, M, nw;   // shape: kernel family (SH_CROSS / SH_RHOMBUS / SH_SQUARE)
+    int ushape, N;            // the caller's shape and inner size
     std::vector<double> w64;
     Weights w32;
     double cfl;
@@ -1303,10 +1326,11 @@ extern "C" {
 
 const char* fd_last_error(void) { return g_err.c_str(); }
 
-int fd_orbits(int ndim, int shape, int M, int* reps, int* counts, int* nw) {
+int fd_orbits_n(int ndim, int shape, int M, int N, int* reps, int* counts, int* nw) {
     if (!nw) return fail(FD_EINVAL, "nw is NULL");
-    if (!valid_shape(ndim, shape, M)) return fail(FD_EINVAL, "invalid ndim/shape/M (%d, %d, %d)", ndim, shape, M);
-    std::vector<Orbit> o = make_orbits(ndim, shape, M);
+    if (!valid_shape(ndim, shape, M, N))
+        return fail(FD_EINVAL, "invalid ndim/shape/M/N (%d, %d, %d, %d)", ndim, shape, M, N);
+    std::vector<Orbit> o = make_orbits(ndim, shape, M, N);
     *nw = (int)o.size();
     for (size_t i = 0; i < o.size(); ++i) {
         if (reps)
@@ -1316,10 +1340,15 @@ int fd_orbits(int ndim, int shape, int M, int* reps, int* counts, int* nw) {
     return FD_OK;
 }
 
-int fd_weights_set(int ndim, int shape, int M, const double* w, int nw, int* stencil_id) {
+int fd_orbits(int ndim, int shape, int M, int* reps, int* counts, int* nw) {
+    return fd_orbits_n(ndim, shape, M, 0, reps, counts, nw);
+}
+
+int fd_weights_set_n(int ndim, int shape, int M, int N, const double* w, int nw, int* stencil_id) {
     if (!stencil_id || !w) return fail(FD_EINVAL, "NULL argument");
-    if (!valid_shape(ndim, shape, M)) return fail(FD_EINVAL, "invalid ndim/shape/M (%d, %d, %d)", ndim, shape, M);
-    std::vector<Orbit> o = make_orbits(ndim, shape, M);
+    if (!valid_shape(ndim, shape, M, N))
+        return fail(FD_EINVAL, "invalid ndim/shape/M/N (%d, %d, %d, %d)", ndim, shape, M, N);
+    std::vector<Orbit> o = make_orbits(ndim, shape, M, N);
     if (nw != (int)o.size()) return fail(FD_EINVAL, "expected %zu weights, got %d", o.size(), nw);
     if ((int)o.size() > kMaxOrbits) return fail(FD_EUNSUPPORTED, "too many orbits (%zu)", o.size());
     double sum = 0.0, asum = 0.0;
@@ -1331,19 +1360,28 @@ int fd_weights_set(int ndim, int shape, int M, const double* w, int nw, int* ste
     if (!(asum > 0)) return fail(FD_EINVAL, "all weights are zero");
     if (std::fabs(sum) > 1e-9 * asum)
         return fail(FD_EINVAL, "weights violate the zero-sum condition: sum count*w = %.3g", sum);
-    Symbol S = make_symbol(ndim, shape, M, o, w);
+    Symbol S = make_symbol(ndim, shape, M, N, o, w);
     double mneg, mpos;
     symbol_extrema(S, &mneg, &mpos);
     if (mpos > 1e-9 * asum) return fail(FD_EUNSTABLE, "stencil symbol is positive (%.3g): unstable for every dt", mpos);
     if (!(mneg > 0)) return fail(FD_EINVAL, "stencil symbol is identically zero");
+    const int ks = kernel_shape(shape, N);
     Stencil st;
     st.ndim = ndim;
-    st.shape = shape;
+    st.shape = ks;
+    st.ushape = shape;
+    st.N = N;
     st.M = M;
     st.nw = nw;
     st.w64.assign(w, w + nw);
     std::memset(&st.w32, 0, sizeof st.w32);
-    for (int i = 0; i < nw; ++i) st.w32.w[i] = (float)w[i];
+    if (ks == SH_CROSS) {
+        // cross kernels index weights by cross orbit (the axis offsets 0..M)
+        for (int i = 0; i < nw; ++i)
+            if (o[i].rep[1] == 0 && o[i].rep[2] == 0) st.w32.w[o[i].rep[0]] = (float)w[i];
+    } else {
+        for (int i = 0; i < nw; ++i) st.w32.w[i] = (float)w[i];
+    }
     if (ndim == 2) {
         for (int dx = 0; dx <= M; ++dx)
             for (int dz = 0; dz <= M; ++dz) {
@@ -1356,15 +1394,25 @@ int fd_weights_set(int ndim, int shape, int M, const double* w, int nw, int* ste
             for (int dx = 1; dx <= M; ++dx) acc += 2.0 * (double)st.w32.wd[dx * (M + 1) + dz];
             st.w32.wc[dz] = (float)acc;
         }
+        // z extent of the offset group of each column dx >= 1 (the set of dz
+        // with (dx, dz) in the shape is 0..mz for every shape here)
+        for (int dx = 1; dx <= M; ++dx) {
+            int mz = 0;
+            for (int dz = 1; dz <= M; ++dz) {
+                const int a = std::max(dx, dz), b = std::min(dx, dz);
+                if (in_shape(2, shape, M, N, a, b, 0)) mz = dz;
+            }
+            st.w32.mz[dx] = mz;
+        }
     }
     st.cfl = 2.0 / std::sqrt(mneg);
-    st.rows = default_rows(ndim, shape, M);
-    st.zchunk = (ndim == 3 && shape == FD_CROSS) ? 128 : 64;
-    st.tsteps = (ndim == 2 && have_fwd2d_tb(shape, M, st.rows)) ? 2 : 1;
+    st.rows = default_rows(ndim, ks, M);
+    st.zchunk = (ndim == 3 && ks == SH_CROSS) ? 128 : 64;
+    st.tsteps = (ndim == 2 && have_fwd2d_tb(ks, M, st.rows)) ? 2 : 1;
     std::lock_guard<std::mutex> lk(g_mu);
     for (size_t i = 0; i < g_stencils.size(); ++i) {
         const Stencil& e = g_stencils[i];
-        if (e.ndim == ndim && e.shape == shape && e.M == M && e.w64 == st.w64) {
+        if (e.ndim == ndim && e.ushape == shape && e.N == N && e.M == M && e.w64 == st.w64) {
             *stencil_id = (int)i;
             return FD_OK;
         }
@@ -1373,6 +1421,10 @@ int fd_weights_set(int ndim, int shape, int M, const double* w, int nw, int* ste
     g_stencils.push_back(st);
     *stencil_id = (int)g_stencils.size() - 1;
     return FD_OK;
+}
+
+int fd_weights_set(int ndim, int shape, int M, const double* w, int nw, int* stencil_id) {
+    return fd_weights_set_n(ndim, shape, M, 0, w, nw, stencil_id);
 }
 
 int fd_cfl_limit(int stencil_id, double* c_lim) {

@@ -79,13 +79,14 @@ __device__ __forceinline__ void s2_dx(const float* tile, int tx, int ty, const f
 // and exhausts the register file); the centre value of each row is read from
 // LDS again rather than kept in registers.  W.wd holds the weight of group
 // (dx, dz) at wd[dx*(M+1) + dz]; the group extent along z for a given dx is
-// maxdz2(SHAPE, M, dx), a wave-uniform value.
+// W.mz[dx], a wave-uniform value (so one kernel serves every dense shape:
+// rhombus, square, cross-rhombus, cross-square).
 template <int SHAPE, int M, int RY, int LW>
 __device__ __forceinline__ void s2_dense_dx(const float* tile, int tx, int ty, float* acc,
                                             const Weights& W) {
 #pragma unroll 1
     for (int dx = 1; dx <= M; ++dx) {
-        const int mz = SHAPE == SH_RHOMBUS ? M - dx : M;
+        const int mz = W.mz[dx];
         const float* wrow = W.wd + dx * (M + 1);
         float d[RY + 2 * M];
 #pragma unroll

@@ -8,7 +8,9 @@ raises immediately - there is no CPU fallback.
 
 Names follow the C entry points: fd_orbits, fd_weights_set, fd_cfl_limit,
 fd_forward, fd_adjoint_gradient, fd_workspace_bytes, fd_set_tile,
-fd_get_tile, fd_set_time_block, fd_get_time_block, fd_last_error.
+fd_get_tile, fd_set_time_block, fd_get_time_block, fd_last_error
+(fd_orbits and fd_weights_set take the inner size N of the cross-rhombus and
+cross-square shapes as a keyword and call fd_orbits_n / fd_weights_set_n).
 """
 from __future__ import annotations
 
@@ -26,7 +28,9 @@ LIB_PATH = os.path.join(_HERE, "libfdwave.so")
 FD_OK, FD_EINVAL, FD_EUNSTABLE, FD_ENOMEM, FD_EDEVICE, FD_ENONFINITE, FD_EUNSUPPORTED = range(7)
 FD_CROSS, FD_RHOMBUS, FD_SQUARE = 0, 1, 2
 FD_NO_GRAPH, FD_NO_BATCH = 1, 2
-SHAPES = {"cross": FD_CROSS, "rhombus": FD_RHOMBUS, "square": FD_SQUARE}
+FD_CROSS_RHOMBUS, FD_CROSS_SQUARE = 3, 4
+SHAPES = {"cross": FD_CROSS, "rhombus": FD_RHOMBUS, "square": FD_SQUARE,
+          "cross_rhombus": FD_CROSS_RHOMBUS, "cross_square": FD_CROSS_SQUARE}
 _STATUS = {1: "EINVAL", 2: "EUNSTABLE", 3: "ENOMEM", 4: "EDEVICE", 5: "ENONFINITE", 6: "EUNSUPPORTED"}
 
 
@@ -62,6 +66,10 @@ def _load() -> ctypes.CDLL:
                               P(ctypes.c_int)]
     lib.fd_weights_set.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, P(ctypes.c_double),
                                    ctypes.c_int, P(ctypes.c_int)]
+    lib.fd_orbits_n.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, P(ctypes.c_int),
+                                P(ctypes.c_int), P(ctypes.c_int)]
+    lib.fd_weights_set_n.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                     P(ctypes.c_double), ctypes.c_int, P(ctypes.c_int)]
     lib.fd_cfl_limit.argtypes = [ctypes.c_int, P(ctypes.c_double)]
     lib.fd_set_tile.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int]
     lib.fd_get_tile.argtypes = [ctypes.c_int, P(ctypes.c_int), P(ctypes.c_int)]
@@ -87,24 +95,24 @@ def _check(rc: int):
 # ---------------------------------------------------------------------------
 # stencils
 # ---------------------------------------------------------------------------
-def fd_orbits(ndim: int, shape, M: int) -> Tuple[np.ndarray, np.ndarray]:
+def fd_orbits(ndim: int, shape, M: int, N: int = 0) -> Tuple[np.ndarray, np.ndarray]:
     """(representatives [nw, ndim], point counts [nw]) in canonical order."""
     shape = SHAPES.get(shape, shape)
     nw = ctypes.c_int()
-    _check(_lib.fd_orbits(ndim, shape, M, None, None, ctypes.byref(nw)))
+    _check(_lib.fd_orbits_n(ndim, shape, M, N, None, None, ctypes.byref(nw)))
     reps = np.zeros(nw.value * ndim, dtype=np.int32)
     counts = np.zeros(nw.value, dtype=np.int32)
-    _check(_lib.fd_orbits(ndim, shape, M, reps.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
-                          counts.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), ctypes.byref(nw)))
+    _check(_lib.fd_orbits_n(ndim, shape, M, N, reps.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                            counts.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), ctypes.byref(nw)))
     return reps.reshape(nw.value, ndim), counts
 
 
-def fd_weights_set(ndim: int, shape, M: int, w: Sequence[float]) -> int:
+def fd_weights_set(ndim: int, shape, M: int, w: Sequence[float], N: int = 0) -> int:
     shape = SHAPES.get(shape, shape)
     arr = np.ascontiguousarray(np.asarray(w, dtype=np.float64))
     sid = ctypes.c_int()
-    _check(_lib.fd_weights_set(ndim, shape, M, arr.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
-                               len(arr), ctypes.byref(sid)))
+    _check(_lib.fd_weights_set_n(ndim, shape, M, N, arr.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                 len(arr), ctypes.byref(sid)))
     return sid.value
 
 

@@ -159,3 +159,46 @@ def test_unknown_flags_are_rejected(F):
     # would be reported only after the flags
     rc = F._lib.fd_forward(ctypes.byref(g), ctypes.c_void_p(16), arr, 1, None, 0, None)
     assert rc == F.FD_EINVAL and "flags" in F.fd_last_error()
+
+
+@pytest.mark.parametrize("M", [1, 2, 3, 4, 5, 8])
+def test_n_shape_weight_counts_follow_the_paper(F, M):
+    """Unique weights of the cross-rhombus and cross-square stencils (Sec. 4.1):
+    M + 1 + floor(N^2/4) (the printed (N^2 + 4M + 4)/4, N even, and
+    (N^2 + 4M + 3)/4, N odd) and (N + 1)(2M - N + 2)/2; both reduce to the
+    cross at N = 0, and to the rhombus / square at N = M."""
+    for N in range(0, M + 1):
+        reps, counts = F.fd_orbits(2, "cross_rhombus", M, N=N)
+        assert len(reps) == M + 1 + (N * N) // 4
+        reps, counts = F.fd_orbits(2, "cross_square", M, N=N)
+        assert len(reps) == (N + 1) * (2 * M - N + 2) // 2
+    assert len(F.fd_orbits(2, "cross_rhombus", M, N=M)[0]) == len(F.fd_orbits(2, "rhombus", M)[0])
+    assert len(F.fd_orbits(2, "cross_square", M, N=M)[0]) == len(F.fd_orbits(2, "square", M)[0])
+    assert len(F.fd_orbits(2, "cross_square", M, N=0)[0]) == M + 1
+
+
+@pytest.mark.parametrize("shape,M,N", [("cross_rhombus", 4, 2), ("cross_rhombus", 8, 5), ("cross_square", 4, 2),
+                                       ("cross_square", 6, 1), ("cross_square", 8, 3)])
+def test_n_shape_orbits_match_the_oracle(F, shape, M, N):
+    reps, counts = F.fd_orbits(2, shape, M, N=N)
+    orbs = W.orbits(2, shape, M, N)
+    assert [tuple(int(x) for x in r) for r in reps] == [tuple(rep) for rep, _ in orbs]
+    assert [int(c) for c in counts] == [len(p) for _, p in orbs]
+
+
+def test_n_shapes_are_validated(F):
+    with pytest.raises(F.FdError):
+        F.fd_orbits(2, "cross_rhombus", 4, N=5)          # N > M
+    with pytest.raises(F.FdError):
+        F.fd_orbits(3, "cross_square", 4, N=2)           # 2D only
+    with pytest.raises(F.FdError):
+        F.fd_orbits(2, "square", 4, N=1)                 # basic shapes take N = 0
+
+
+@pytest.mark.parametrize("shape,M,N", [("cross_rhombus", 4, 3), ("cross_rhombus", 6, 4)])
+def test_n_shape_cfl_matches_the_oracle(F, shape, M, N):
+    from fractions import Fraction
+    w = W.to_float(W.dispte(2, shape, M, Fraction(3, 10), N))
+    sid = F.fd_weights_set(2, shape, M, w, N=N)
+    ref = W.cfl_limit(2, shape, M, w, N)
+    assert abs(F.fd_cfl_limit(sid) - ref) <= 1e-4 * ref

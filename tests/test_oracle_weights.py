@@ -5,6 +5,7 @@ hand-solved instances of the paper's printed systems, weight-count formulas
 printed in Sec. 4.1, and exactness on polynomials.
 """
 import math
+from fractions import Fraction
 from fractions import Fraction as F
 
 import numpy as np
@@ -205,3 +206,111 @@ def test_specls_square_internal_consistency():
         mneg, smax = W.max_neg_symbol(2, "square", M, w)
         assert smax <= 1e-12
     assert W.cfl_limit(2, "square", 6, W.specls(2, "square", 6)) == pytest.approx(0.478934384230554, rel=1e-9)
+
+
+# --------------------------------------------------------------------------
+# cross-rhombus / cross-square schemes, DispLS, theta schemes (Sec. 3.3-3.4,
+# Sec. 4.2)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("M", [2, 3, 4, 6, 8])
+def test_dispte_cross_rhombus_system_is_square_and_reduces(M):
+    """Sec. 4.2: the DispTE-CrossRb(M, N) system has as many equations as
+    weights; N = 1 gives DispTE-Cross(M) and N = M DispTE-Rhombus(M)."""
+    C = Fraction(27, 100)
+    for N in range(0, M + 1):
+        w = W.dispte(2, "cross_rhombus", M, C, N)
+        assert len(w) == len(W.orbits(2, "cross_rhombus", M, N))
+    wc = W.dispte(2, "cross", M, C)
+    assert W.dispte(2, "cross_rhombus", M, C, 1) == wc
+    assert W.dispte(2, "cross_rhombus", M, C, M) == W.dispte(2, "rhombus", M, C)
+
+
+def test_dispte_cross_rhombus_satisfies_its_equations():
+    """Residual of the printed equations (r = 0 .. M main, mixed r <= N),
+    re-evaluated point by point from the weights in exact arithmetic."""
+    M, N, C = 6, 4, Fraction(3, 10)
+    w = W.dispte(2, "cross_rhombus", M, C, N)
+    offs, ws = W.expand(2, "cross_rhombus", M, w, N)
+    assert sum(ws) == 0
+    for r in range(1, M + 1):
+        for s in range(0, r // 2 + 1):
+            if s > 0 and r > N:
+                continue
+            lhs = sum(wd * Fraction(int(d[0])) ** (2 * r - 2 * s) * Fraction(int(d[1])) ** (2 * s)
+                      for d, wd in zip(offs, ws))
+            # sum_d w_d x^(2(r-s)) z^(2s) = 2 C^(2r-2) r!/((r-s)! s!) (2r-2s)!(2s)!/(2r)!
+            rhs = 2 * C ** (2 * r - 2) * Fraction(math.factorial(r), math.factorial(r - s) * math.factorial(s)) \
+                * Fraction(math.factorial(2 * r - 2 * s) * math.factorial(2 * s), math.factorial(2 * r))
+            assert lhs == rhs, (r, s)
+
+
+def test_dispte_cross_square_is_not_a_square_system():
+    """Sec. 4.2: DispTE-CrossSq(M, N) has fewer equations than weights."""
+    with pytest.raises(ValueError):
+        W.dispte(2, "cross_square", 4, Fraction(1, 4), 2)
+
+
+@pytest.mark.parametrize("M", [2, 4, 8])
+def test_specte_theta_cross_is_spatte(M):
+    """By the printed system, every r > 1 equation of SpecTE-theta-Cross has
+    right-hand side 0 and its angular factor scales the whole row, so the
+    weights are the SpatTE cross weights for every theta."""
+    for theta in (0.0, math.pi / 8, 0.3, 1.0):
+        assert W.specte_theta(M, theta) == W.taylor(2, M)
+
+
+@pytest.mark.parametrize("M", [2, 4, 8])
+def test_dispte_theta_reductions(M):
+    C = Fraction(27, 100)
+    assert W.dispte_theta(M, C, 0.0) == W.dispte(2, "cross", M, C)
+    a = W.to_float(W.dispte_theta(M, C, math.pi / 8))
+    b = W.to_float(W.dispte_theta(M, C, math.pi / 2 - math.pi / 8))
+    assert max(abs(x - y) for x, y in zip(a, b)) <= 1e-13 * max(abs(x) for x in a)
+    assert W.to_float(W.dispte_theta(M, 0, 0.7)) == W.to_float(W.taylor(2, M))
+
+
+def test_dispte_theta_matches_the_dispersion_relation_along_theta():
+    """Along the design angle the scheme's dispersion relation
+    cos(w dt) = 1 + C^2 S(k)/2 (eq. full_disp) agrees with cos(C |k|) to
+    O(|k|^(2M+2)): halving |k| divides the mismatch by ~2^(2M+2).  Off that
+    angle the agreement is only O(|k|^4)."""
+    M, C, th = 2, 0.3, math.pi / 8
+    w = W.to_float(W.dispte_theta(M, Fraction(C), th))
+
+    def mismatch(beta, ang):
+        k = beta * np.array([math.cos(ang), math.sin(ang)])
+        S = float(W.symbol(2, "cross", M, w, k))
+        return abs((1 + C * C * S / 2) - math.cos(C * beta))
+
+    r_on = mismatch(0.2, th) / mismatch(0.1, th)
+    r_off = mismatch(0.2, 0.0) / mismatch(0.1, 0.0)
+    assert r_on > 0.7 * 2 ** (2 * M + 2)
+    assert 0.7 * 16 < r_off < 1.5 * 16
+
+
+def _ls_objective(shape, M, N, w, C, band=math.pi, nb=64, nt=64):
+    """Quadrature of the relative dispersion objective of Sec. 3.3.3 / 3.4.3:
+    (sum_o w_o deficit_o(k) / Psi - 1)^2 over beta in [0, band], theta in
+    [0, 2 pi); Psi = beta^2 (SpecLS) or (2 - 2 cos(C beta)) / C^2 (DispLS)."""
+    beta = (np.arange(nb) + 0.5) * band / nb
+    theta = (np.arange(nt) + 0.5) * 2 * math.pi / nt
+    Bm, Tm = np.meshgrid(beta, theta, indexing="ij")
+    k = np.stack([Bm * np.cos(Tm), Bm * np.sin(Tm)], axis=-1)
+    deficit = -(W.symbol(2, shape, M, w, k, N))   # sum_d w_d (1 - cos) = -S (zero-sum weights)
+    psi = Bm ** 2 if C == 0 else (2 - 2 * np.cos(C * Bm)) / C ** 2
+    return float(np.sum((deficit / psi - 1) ** 2))
+
+
+def test_displs_reduces_to_specls_and_is_stable():
+    w0 = W.specls(2, "cross_rhombus", 4, N=2)
+    w1 = W.displs(2, "cross_rhombus", 4, 1e-3, N=2)
+    assert max(abs(x - y) for x, y in zip(w0, w1)) <= 1e-4 * max(abs(x) for x in w0)
+    for shape, M, N in (("cross_rhombus", 4, 2), ("cross_square", 6, 2), ("cross", 8, 0)):
+        C = 0.28
+        wd = W.displs(2, shape, M, C, N=N)
+        ws = W.specls(2, shape, M, N=N)
+        mneg, mpos = W.max_neg_symbol(2, shape, M, wd, N=N)
+        assert mneg > 0 and mpos <= 1e-9 * sum(abs(x) for x in wd)
+        # each least-squares solution minimises its own objective
+        assert _ls_objective(shape, M, N, wd, C) < _ls_objective(shape, M, N, ws, C)
+        assert _ls_objective(shape, M, N, ws, 0) < _ls_objective(shape, M, N, wd, 0)

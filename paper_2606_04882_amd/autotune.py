@@ -48,8 +48,9 @@ def device_tag() -> str:
     return f"{arch.split(':')[0]}-{p.multi_processor_count}cu"
 
 
-def _key(ndim, shape, M, grid_shape) -> str:
-    return f"v2|{device_tag()}|{ndim}|{shape}|{M}|{'x'.join(str(int(n)) for n in grid_shape)}"
+def _key(ndim, shape, M, grid_shape, N: int = 0) -> str:
+    sh = shape if N == 0 else f"{shape}{N}"
+    return f"v2|{device_tag()}|{ndim}|{sh}|{M}|{'x'.join(str(int(n)) for n in grid_shape)}"
 
 
 def _install(stencil_id: int, ndim: int, rows: int, zc: int, ts: int):
@@ -78,11 +79,11 @@ def _store(db: Dict):
 
 
 def tune(stencil_id: int, ndim: int, shape: str, M: int, grid: F.Grid, vel: torch.Tensor,
-         src: Sequence[int], nt: int = 40, reps: int = 3, use_cache: bool = True) -> Dict:
+         src: Sequence[int], nt: int = 40, reps: int = 3, use_cache: bool = True, N: int = 0) -> Dict:
     """Pick and install the fastest tile configuration for `stencil_id` on
     this grid; returns {"rows", "zchunk", "tsteps", "ms": {config: time},
     "cached"}."""
-    key = _key(ndim, shape, M, grid.shape)
+    key = _key(ndim, shape, M, grid.shape, N)
     db = {}
     if use_cache:
         db = _load(PACKAGED)

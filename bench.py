@@ -73,6 +73,7 @@ def parse():
     ap.add_argument("--no-fwi", action="store_true")
     ap.add_argument("--no-vol3d", action="store_true")
     ap.add_argument("--no-ragged", action="store_true")
+    ap.add_argument("--no-dispersion", action="store_true")
     ap.add_argument("--vol3d-nt", type=int, default=1000)
     ap.add_argument("--ragged-nt", type=int, default=3000)
     ap.add_argument("--no-tune", action="store_true", help="skip the tile autotuner")
@@ -232,6 +233,9 @@ def main():
     if not args.no_fwi:
         line["fwi"] = fwi_bench(torch, F, design, configs, dev)
         log("fwi done")
+    if not args.no_dispersion:
+        line["dispersion"] = dispersion_bench(torch, F, variants, w)
+        log("dispersion done")
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(w, vel_np, args.cpu_seconds)
         log("cpu baseline done")
@@ -435,6 +439,35 @@ def fwi_bench(torch, F, design, configs, dev):
     return {"workload": w.name, "shots": len(shots), "nt": w.nt, "ckpt_every": K,
             "s_per_shot": round(t_fast, 5), "plain_s_per_shot": round(t_plain, 5),
             "speedup_vs_plain": round(t_plain / t_fast, 3), "grad_rel_diff_vs_plain": diff}
+
+
+def dispersion_bench(torch, F, variants, w, nscale=64):
+    """Appendix A metrics of the 1001^2 workload's traces (501 receivers x
+    2000 samples): Taylor cross M=4 against DispTE cross M=8, gamma^F and the
+    64-scale Morlet gamma^W per receiver; GPU call time (events) against the
+    FP64 oracle on a few receivers (scaled to all)."""
+    by = {v["name"]: v for v in variants}
+    num = by["taylor-cross-M4"]["shot"].traces
+    ref = by["dispte-cross-M8"]["shot"].traces
+    nt, nrec = int(num.shape[0]), int(num.shape[1])
+    out = F.fd_dispersion(num, ref, w.dt, nscale)      # plans and warm-up
+    torch.cuda.synchronize()
+    ms = _event_time(torch, lambda: F.fd_dispersion(num, ref, w.dt, nscale), reps=3)
+    from oracle import dispersion as OD
+    a = num.cpu().numpy().astype(np.float64)
+    b = ref.cpu().numpy().astype(np.float64)
+    sample = 4
+    t0 = time.perf_counter()
+    for r in range(sample):
+        OD.gamma_dft(a[:, r], b[:, r])
+        OD.gamma_cwt(a[:, r], b[:, r], w.dt, nscale)
+    cpu_s = (time.perf_counter() - t0) / sample * nrec
+    nd = out["norm_dft"].cpu().numpy()
+    nc = out["norm_cwt"].cpu().numpy()
+    return {"traces": [nt, nrec], "nscale": nscale, "gpu_ms": round(ms, 3),
+            "oracle_s_all_receivers": round(cpu_s, 2), "speedup_vs_oracle": round(cpu_s * 1e3 / ms, 1),
+            "norm_dft_avg": float(nd.mean()), "norm_dft_max": float(nd.max()),
+            "norm_cwt_avg": float(nc.mean()), "norm_cwt_max": float(nc.max())}
 
 
 def _gomp():

@@ -231,6 +231,38 @@ int fd_get_time_block(int stencil_id, int* steps);
 /* Message for the last non-OK return on this thread ("" if none). */
 const char* fd_last_error(void);
 
+/*
+ * Dispersion metrics of Appendix A between numerical and reference traces
+ * (e.g. a coarse run and a fine-grid or analytic reference at the same
+ * receivers), per receiver:
+ *   gamma^F_k = (wrap(phi(A_k) - phi(A'_k)) / pi) |A_k| / max_k |A_k|,
+ *     A_k = sum_n u_n exp(-2 pi i k n / nt), k = 0..nt-1 (eq. gammadft);
+ *   ||gamma^F||_2 = sqrt(1/nt sum_k gamma_k^2) (eq. norm2gammastdft);
+ *   ||gamma^W||_2 of the Morlet CWT measure (eqs. cwt1-cwt3, gammacwt,
+ *     norm2gammastcwt) over nscale scales, one per DFT frequency
+ *     f_j = j / (nt dt), j = 1..nscale, s_j = (w0 + sqrt(2 + w0^2)) / (4 pi f_j).
+ * Amplitudes are sqrt(Re^2 + Im^2); phases atan2(Im, Re) in (-pi, pi]; the
+ * phase difference is moved into (-pi, pi] by +-2 pi.  Transforms in FP64.
+ *   num, ref    [dev] nt*nrec traces, num[n*nrec + r] (the fd_shot.traces layout)
+ *   dt          sample interval (s); used by the CWT
+ *   nscale      number of CWT scales (0: no CWT), <= nt/2
+ *   omega0      Morlet centre frequency (the usual choice is 6)
+ *   gamma_dft   [dev, out, may be NULL] nrec*nt: gamma^F of receiver r at r*nt + k
+ *   norm_dft    [dev, out] nrec per-receiver ||gamma^F||_2
+ *   norm_cwt    [dev, out, may be NULL] nrec per-receiver ||gamma^W||_2
+ *   workspace   [dev] >= fd_dispersion_workspace_bytes(nt, nrec, norm_cwt ? nscale : 0),
+ *               256-byte aligned
+ * The average and maximum over receivers (eqs. norm2gammarecdftavg ..
+ * norm2gammareccwtmax) are reductions of norm_dft / norm_cwt by the caller.
+ * FFTs run in rocFFT; its plans (and any work buffer they need) are cached
+ * by the library per device, length and batch until the process ends.
+ * Asynchronous on hip_stream.  Errors: FD_EINVAL, FD_ENOMEM, FD_EDEVICE.
+ */
+size_t fd_dispersion_workspace_bytes(int nt, int nrec, int nscale);
+int fd_dispersion(const float* num, const float* ref, int nt, int nrec, double dt, int nscale,
+                  double omega0, float* gamma_dft, double* norm_dft, double* norm_cwt, void* workspace,
+                  size_t ws_bytes, void* hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

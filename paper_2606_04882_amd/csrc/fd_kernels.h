@@ -287,4 +287,12 @@ void launch_accum2d(float* g, long long ldg, const float* a, int nx, int nz, hip
 // flags[] slots in the workspace
 enum { FLAG_BAD_REC = 0, FLAG_NONFINITE = 1, FLAG_BAD_VEL = 2, FLAG_COUNT = 4 };
 
+// Dispersion metrics (k_disp.hip).  Half spectra are double2 [rc][nt/2+1],
+// CWT fields double2 [rc][ns][nt].
+void launch_rows_f64(const float* in, double* out, int nt, int nrec, int r0, int rc, hipStream_t s);
+void launch_gamma_dft(const void* A, const void* B, int nt, int rc, float* gamma, long long ldg, double* norm,
+                      hipStream_t s);
+void launch_cwt_spectra(const void* A, int nt, int rc, int ns, double dt, double omega0, void* W, hipStream_t s);
+void launch_gamma_cwt(const void* Wn, const void* Wr, int nt, int rc, int ns, double* norm, hipStream_t s);
+
 }  // namespace fdw

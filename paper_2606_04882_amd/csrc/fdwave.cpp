@@ -4,6 +4,7 @@
 #include "../../include/fdwave.h"
 
 #include <hip/hip_runtime.h>
+#include <rocfft/rocfft.h>
 
 #include <algorithm>
 #include <cmath>
@@ -1317,6 +1318,104 @@ int prepare(CallCtx& c, const fd_grid* g, const float* vel, const fd_shot* shots
     return FD_OK;
 }
 
+// ---------------------------------------------------------------------------
+// dispersion metrics (Appendix A): rocFFT plans and receiver chunking
+// ---------------------------------------------------------------------------
+// Plans are cached per (device, kind, length, batch) with their work buffer
+// and execution info; like the graph cache they live until the process ends.
+struct FftPlan {
+    int dev, kind;            // kind 0: real forward, 1: complex inverse (in place)
+    size_t len, batch;
+    rocfft_plan plan = nullptr;
+    rocfft_execution_info info = nullptr;
+    void* work = nullptr;
+    size_t work_bytes = 0;
+};
+std::list<FftPlan> g_fft;   // stable addresses for the returned plans
+std::mutex g_fft_mu;
+
+int fft_plan(int kind, size_t len, size_t batch, FftPlan** out) {
+    std::lock_guard<std::mutex> lk(g_fft_mu);
+    int dev = 0;
+    HIP_OK(hipGetDevice(&dev));
+    for (FftPlan& p : g_fft)
+        if (p.dev == dev && p.kind == kind && p.len == len && p.batch == batch) {
+            *out = &p;
+            return FD_OK;
+        }
+    static bool setup = false;
+    if (!setup) {
+        if (rocfft_setup() != rocfft_status_success) return fail(FD_EDEVICE, "rocfft_setup failed");
+        setup = true;
+    }
+    FftPlan p;
+    p.dev = dev;
+    p.kind = kind;
+    p.len = len;
+    p.batch = batch;
+    const rocfft_status st = rocfft_plan_create(
+        &p.plan, kind == 0 ? rocfft_placement_notinplace : rocfft_placement_inplace,
+        kind == 0 ? rocfft_transform_type_real_forward : rocfft_transform_type_complex_inverse,
+        rocfft_precision_double, 1, &len, batch, nullptr);
+    if (st != rocfft_status_success) return fail(FD_EDEVICE, "rocfft_plan_create failed (%d)", (int)st);
+    if (rocfft_plan_get_work_buffer_size(p.plan, &p.work_bytes) != rocfft_status_success)
+        return fail(FD_EDEVICE, "rocfft_plan_get_work_buffer_size failed");
+    if (rocfft_execution_info_create(&p.info) != rocfft_status_success)
+        return fail(FD_EDEVICE, "rocfft_execution_info_create failed");
+    if (p.work_bytes) {
+        HIP_OK(hipMalloc(&p.work, p.work_bytes));
+        if (rocfft_execution_info_set_work_buffer(p.info, p.work, p.work_bytes) != rocfft_status_success)
+            return fail(FD_EDEVICE, "rocfft_execution_info_set_work_buffer failed");
+    }
+    g_fft.push_back(p);
+    *out = &g_fft.back();
+    return FD_OK;
+}
+
+int fft_run(FftPlan* p, void* in, void* out, hipStream_t st) {
+    std::lock_guard<std::mutex> lk(g_fft_mu);
+    if (rocfft_execution_info_set_stream(p->info, st) != rocfft_status_success)
+        return fail(FD_EDEVICE, "rocfft_execution_info_set_stream failed");
+    void* ib[1] = {in};
+    void* ob[1] = {out};
+    if (rocfft_execute(p->plan, ib, out ? ob : nullptr, p->info) != rocfft_status_success)
+        return fail(FD_EDEVICE, "rocfft_execute failed");
+    return FD_OK;
+}
+
+// receivers per chunk: at most 64, and the two CWT fields of a chunk within
+// 512 MiB
+int disp_chunk(int nt, int nrec, int nscale) {
+    long long r = std::min(nrec, 64);
+    if (nscale > 0) {
+        const long long per = 2LL * nscale * nt * 16;
+        r = std::min(r, std::max(1LL, (512LL << 20) / per));
+    }
+    return (int)r;
+}
+
+struct DispLayout {
+    size_t xa, xb, fa, fb, wa, wb, total;
+};
+
+DispLayout disp_layout(int nt, int nrec, int nscale) {
+    const int R = disp_chunk(nt, nrec, nscale);
+    const size_t nh = (size_t)nt / 2 + 1;
+    DispLayout L;
+    size_t off = 0;
+    L.xa = off; off = align256(off + 8 * (size_t)R * nt);
+    L.xb = off; off = align256(off + 8 * (size_t)R * nt);
+    L.fa = off; off = align256(off + 16 * (size_t)R * nh);
+    L.fb = off; off = align256(off + 16 * (size_t)R * nh);
+    L.wa = L.wb = 0;
+    if (nscale > 0) {
+        L.wa = off; off = align256(off + 16 * (size_t)R * nscale * nt);
+        L.wb = off; off = align256(off + 16 * (size_t)R * nscale * nt);
+    }
+    L.total = off;
+    return L;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -1506,6 +1605,53 @@ int fd_adjoint_gradient(const fd_grid* g, const float* vel, const fd_shot* shots
     rc = run_call(c, 1, st);
     if (rc) return rc;
     return finish_checks(c, st);
+}
+
+size_t fd_dispersion_workspace_bytes(int nt, int nrec, int nscale) {
+    if (nt < 2 || nrec < 1 || nscale < 0) return 0;
+    return disp_layout(nt, nrec, nscale).total;
+}
+
+int fd_dispersion(const float* num, const float* ref, int nt, int nrec, double dt, int nscale,
+                  double omega0, float* gamma_dft, double* norm_dft, double* norm_cwt, void* workspace,
+                  size_t ws_bytes, void* hip_stream) {
+    g_err.clear();
+    if (!num || !ref || !norm_dft) return fail(FD_EINVAL, "num, ref and norm_dft are required");
+    if (nt < 2 || nrec < 1) return fail(FD_EINVAL, "need nt >= 2 and nrec >= 1");
+    if (nscale < 0 || nscale > nt / 2) return fail(FD_EINVAL, "nscale must be in [0, nt/2]");
+    if (norm_cwt && (nscale < 1 || !(dt > 0) || !(omega0 > 0)))
+        return fail(FD_EINVAL, "the CWT norm needs nscale >= 1, dt > 0 and omega0 > 0");
+    if (!workspace) return fail(FD_EINVAL, "workspace is NULL");
+    if ((uintptr_t)workspace % 256) return fail(FD_EINVAL, "workspace must be 256-byte aligned");
+    const int ns = norm_cwt ? nscale : 0;
+    const DispLayout L = disp_layout(nt, nrec, ns);
+    if (ws_bytes < L.total) return fail(FD_ENOMEM, "workspace too small: %zu < %zu bytes", ws_bytes, L.total);
+    char* ws = (char*)workspace;
+    hipStream_t st = (hipStream_t)hip_stream;
+    const int R = disp_chunk(nt, nrec, ns);
+    for (int r0 = 0; r0 < nrec; r0 += R) {
+        const int rc = std::min(R, nrec - r0);
+        FftPlan* fwd = nullptr;
+        int rc2 = fft_plan(0, (size_t)nt, (size_t)rc, &fwd);
+        if (rc2) return rc2;
+        launch_rows_f64(num, (double*)(ws + L.xa), nt, nrec, r0, rc, st);
+        launch_rows_f64(ref, (double*)(ws + L.xb), nt, nrec, r0, rc, st);
+        if ((rc2 = fft_run(fwd, ws + L.xa, ws + L.fa, st))) return rc2;
+        if ((rc2 = fft_run(fwd, ws + L.xb, ws + L.fb, st))) return rc2;
+        launch_gamma_dft(ws + L.fa, ws + L.fb, nt, rc, gamma_dft ? gamma_dft + (long long)r0 * nt : nullptr,
+                         nt, norm_dft + r0, st);
+        if (ns > 0) {
+            FftPlan* inv = nullptr;
+            if ((rc2 = fft_plan(1, (size_t)nt, (size_t)rc * ns, &inv))) return rc2;
+            launch_cwt_spectra(ws + L.fa, nt, rc, ns, dt, omega0, ws + L.wa, st);
+            launch_cwt_spectra(ws + L.fb, nt, rc, ns, dt, omega0, ws + L.wb, st);
+            if ((rc2 = fft_run(inv, ws + L.wa, nullptr, st))) return rc2;
+            if ((rc2 = fft_run(inv, ws + L.wb, nullptr, st))) return rc2;
+            launch_gamma_cwt(ws + L.wa, ws + L.wb, nt, rc, ns, norm_cwt + r0, st);
+        }
+    }
+    HIP_OK(hipGetLastError());
+    return FD_OK;
 }
 
 }  // extern "C"

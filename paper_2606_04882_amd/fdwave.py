@@ -81,6 +81,11 @@ def _load() -> ctypes.CDLL:
                                ctypes.c_size_t, ctypes.c_void_p]
     lib.fd_adjoint_gradient.argtypes = [P(FdGrid), ctypes.c_void_p, P(FdShot), ctypes.c_int, ctypes.c_int,
                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
+    lib.fd_dispersion_workspace_bytes.restype = ctypes.c_size_t
+    lib.fd_dispersion_workspace_bytes.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int]
+    lib.fd_dispersion.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                  ctypes.c_int, ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p,
+                                  ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
     return lib
 
 
@@ -285,3 +290,31 @@ def fd_adjoint_gradient(grid: Grid, vel: torch.Tensor, shots: Sequence[Shot], ck
         ws = workspace(nbytes, vel.device)
     _check(_lib.fd_adjoint_gradient(ctypes.byref(g), _ptr(vel), arr, len(shots), ckpt_every, _ptr(grad),
                                     _ptr(ws), ws.numel(), ctypes.c_void_p(_stream_handle(vel.device))))
+
+
+# ---------------------------------------------------------------------------
+# dispersion metrics
+# ---------------------------------------------------------------------------
+def fd_dispersion(num: torch.Tensor, ref: torch.Tensor, dt: float = 0.0, nscale: int = 0, omega0: float = 6.0,
+                  gamma: bool = False) -> dict:
+    """Appendix A metrics between traces num and ref ([nt, nrec] float32 on
+    the GPU): {"norm_dft": [nrec], "norm_cwt": [nrec] (nscale > 0),
+    "gamma_dft": [nrec, nt] (gamma=True)} as float64 / float32 tensors."""
+    if num.shape != ref.shape or num.dim() != 2:
+        raise ValueError("num and ref must be [nt, nrec] of the same shape")
+    nt, nrec = int(num.shape[0]), int(num.shape[1])
+    dev = num.device
+    out = {"norm_dft": torch.zeros(nrec, dtype=torch.float64, device=dev)}
+    if nscale > 0:
+        out["norm_cwt"] = torch.zeros(nrec, dtype=torch.float64, device=dev)
+    if gamma:
+        out["gamma_dft"] = torch.zeros(nrec, nt, dtype=torch.float32, device=dev)
+    nbytes = int(_lib.fd_dispersion_workspace_bytes(nt, nrec, nscale))
+    ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
+    base = ws.data_ptr()
+    aligned = (base + 255) // 256 * 256
+    num_c, ref_c = num.contiguous(), ref.contiguous()
+    _check(_lib.fd_dispersion(_ptr(num_c), _ptr(ref_c), nt, nrec, float(dt), nscale, float(omega0),
+                              _ptr(out.get("gamma_dft")), _ptr(out["norm_dft"]), _ptr(out.get("norm_cwt")),
+                              aligned, nbytes, _stream_handle(dev)))
+    return out

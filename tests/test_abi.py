@@ -202,3 +202,18 @@ def test_n_shape_cfl_matches_the_oracle(F, shape, M, N):
     sid = F.fd_weights_set(2, shape, M, w, N=N)
     ref = W.cfl_limit(2, shape, M, w, N)
     assert abs(F.fd_cfl_limit(sid) - ref) <= 1e-4 * ref
+
+
+def test_dispersion_workspace_and_validation(F):
+    import ctypes
+    small = F._lib.fd_dispersion_workspace_bytes(500, 10, 0)
+    withcwt = F._lib.fd_dispersion_workspace_bytes(500, 10, 40)
+    assert small >= 2 * 8 * 10 * 500 and withcwt > small
+    assert F._lib.fd_dispersion_workspace_bytes(1, 10, 0) == 0
+    d = ctypes.c_double()
+    # argument checks run before any device work (pointers here are never read)
+    rc = F._lib.fd_dispersion(16, 16, 500, 10, 1e-3, 300, 6.0, None, ctypes.addressof(d), ctypes.addressof(d),
+                              256, withcwt, None)
+    assert rc == F.FD_EINVAL and "nscale" in F.fd_last_error()
+    rc = F._lib.fd_dispersion(16, 16, 500, 10, 1e-3, 40, 6.0, None, ctypes.addressof(d), None, 256, 10, None)
+    assert rc == F.FD_ENOMEM

@@ -1,0 +1,82 @@
+"""GPU dispersion metrics (Appendix A) against the oracle (marked gpu).
+
+Bar: per-receiver norms within 1e-6 relative (FP64 transforms on both
+sides; the traces are FP32 inputs on both), gamma^F within 1e-6 of its
+scale wherever the oracle's value is not at a +-pi phase jump."""
+import math
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+from oracle import analytic as AN  # noqa: E402
+from oracle import dispersion as OD  # noqa: E402
+
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def F():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2606_04882_amd import fdwave
+    return fdwave
+
+
+def pair(nt, nrec, dt, seed):
+    """Ricker pulses at receiver-dependent delays and a slightly slower,
+    attenuated reference: a dispersion-like phase drift."""
+    rng = np.random.default_rng(seed)
+    t = np.arange(nt) * dt
+    num = np.zeros((nt, nrec))
+    ref = np.zeros((nt, nrec))
+    for r in range(nrec):
+        t0 = 0.1 + 0.3 * rng.random()
+        num[:, r] = AN.ricker(t, 20.0, t0) + 0.3 * AN.ricker(t, 35.0, t0 + 0.05)
+        ref[:, r] = 0.9 * AN.ricker(t, 19.5, t0 + 0.004 * (r % 5)) + 0.3 * AN.ricker(t, 35.0, t0 + 0.052)
+    return num.astype(np.float32), ref.astype(np.float32)
+
+
+@pytest.mark.parametrize("nt,nrec,nscale", [(500, 7, 24), (1001, 70, 10), (2000, 3, 0), (333, 130, 5)])
+def test_norms_match_oracle(F, nt, nrec, nscale):
+    dt = 1e-3
+    num, ref = pair(nt, nrec, dt, seed=nt)
+    out = F.fd_dispersion(torch.tensor(num, device=DEV), torch.tensor(ref, device=DEV), dt, nscale, gamma=True)
+    torch.cuda.synchronize()
+    nd = out["norm_dft"].cpu().numpy()
+    g = out["gamma_dft"].cpu().numpy()
+    for r in range(nrec):
+        x, y = num[:, r].astype(np.float64), ref[:, r].astype(np.float64)
+        gref, nref = OD.gamma_dft(x, y)
+        assert abs(nd[r] - nref) <= 1e-6 * max(nref, 1e-12)
+        # a phase difference of exactly +-pi (e.g. the real bin k = 0 when the
+        # two sums have opposite signs) is correct with either sign
+        d = OD.wrap(OD.phase(np.fft.fft(x)) - OD.phase(np.fft.fft(y)))
+        ok = np.abs(np.abs(d) - math.pi) > 1e-6
+        assert np.max(np.abs(g[r][ok] - gref[ok])) <= 1e-6
+        assert np.max(np.abs(np.abs(g[r]) - np.abs(gref))) <= 1e-6
+    if nscale:
+        nc = out["norm_cwt"].cpu().numpy()
+        for r in range(0, nrec, max(1, nrec // 5)):
+            _, cref = OD.gamma_cwt(num[:, r].astype(np.float64), ref[:, r].astype(np.float64), dt, nscale)
+            assert abs(nc[r] - cref) <= 1e-6 * max(cref, 1e-12)
+
+
+def test_identical_traces_and_a_phase_shifted_tone(F):
+    nt, dt = 512, 2e-3
+    n = np.arange(nt)
+    a = np.cos(2 * math.pi * 24 * n / nt + 0.5)
+    b = 0.5 * np.cos(2 * math.pi * 24 * n / nt - 0.2)
+    num = np.stack([a, a], axis=1).astype(np.float32)
+    ref = np.stack([a, b], axis=1).astype(np.float32)
+    out = F.fd_dispersion(torch.tensor(num, device=DEV), torch.tensor(ref, device=DEV), dt, 48)
+    torch.cuda.synchronize()
+    nd = out["norm_dft"].cpu().numpy()
+    nc = out["norm_cwt"].cpu().numpy()
+    assert nd[0] == 0 and nc[0] == 0
+    assert abs(nd[1] - math.sqrt(2 * (0.7 / math.pi) ** 2 / nt)) < 1e-6
+    _, cref = OD.gamma_cwt(num[:, 1].astype(np.float64), ref[:, 1].astype(np.float64), dt, 48)
+    assert abs(nc[1] - cref) < 1e-6 * cref

@@ -7,7 +7,10 @@
 
 namespace fdw {
 
-enum { SH_CROSS = 0, SH_RHOMBUS = 1, SH_SQUARE = 2 };
+// Kernel families: cross, rhombus and square with their extents known at
+// compile time, and SH_NSHAPE for the 2D cross-rhombus / cross-square
+// shapes, whose dense kernels read each column's z extent from Weights::mz.
+enum { SH_CROSS = 0, SH_RHOMBUS = 1, SH_SQUARE = 2, SH_NSHAPE = 3 };
 constexpr int kMaxOrbits = 64;
 constexpr int kBlock = 256;   // threads per block: 4 waves of 64
 constexpr int kTileX = 64;    // tile width along x = one wave
@@ -23,7 +26,8 @@ constexpr int kBlock3 = 64 * kWaves3;
 // column's z difference u(z+dz) + u(z-dz) - 2u: w(0, dz) + 2 sum_dx w(dx, dz),
 // formed in FP64 from the FP32 weights and rounded once.  mz[dx] (dx = 1..M)
 // is the z extent of the dense 2D kernels' offset group at column dx: the
-// shape holds (dx, dz) exactly for dz = 0..mz[dx].  For the cross kernels,
+// shape holds (dx, dz) exactly for dz = 0..mz[dx] (read by SH_NSHAPE
+// kernels only; the others know it at compile time).  For the cross kernels,
 // w[m] is the weight of the axis offset m.
 constexpr int kMaxDense = 81;
 struct Weights {

@@ -108,15 +108,16 @@ bool valid_shape(int ndim, int shape, int M, int N) {
     return false;
 }
 
-// Kernel family of a shape: N-shapes without off-axis points are crosses;
-// the others run the dense 2D kernels, which take each column's extent from
-// the stencil's mz table.
-int kernel_shape(int shape, int N) {
+// Kernel family of a shape: N-shapes without off-axis points are crosses,
+// cross-rhombus(M, M) is the rhombus and cross-square(M, M) the square; the
+// other N-shapes run the dense 2D kernels that take each column's extent
+// from the stencil's mz table.
+int kernel_shape(int shape, int M, int N) {
     switch (shape) {
         case FD_CROSS: return SH_CROSS;
         case FD_RHOMBUS: return SH_RHOMBUS;
-        case FD_CROSS_RHOMBUS: return N <= 1 ? SH_CROSS : SH_SQUARE;
-        case FD_CROSS_SQUARE: return N == 0 ? SH_CROSS : SH_SQUARE;
+        case FD_CROSS_RHOMBUS: return N <= 1 ? SH_CROSS : N == M ? SH_RHOMBUS : SH_NSHAPE;
+        case FD_CROSS_SQUARE: return N == 0 ? SH_CROSS : N == M ? SH_SQUARE : SH_NSHAPE;
         default: return SH_SQUARE;
     }
 }
@@ -212,7 +213,7 @@ void symbol_extrema(const Symbol& S, double* max_neg, double* max_pos) {
 // stencil registry
 // ---------------------------------------------------------------------------
 struct Stencil {
-    int ndim, shape, M, nw;   // shape: kernel family (SH_CROSS / SH_RHOMBUS / SH_SQUARE)
+    int ndim, shape, M, nw;   // shape: kernel family (SH_CROSS / SH_RHOMBUS / SH_SQUARE / SH_NSHAPE)
     int ushape, N;            // the caller's shape and inner size
     std::vector<double> w64;
     Weights w32;
@@ -1038,7 +1039,7 @@ int enqueue_batched_adjoint(const CallCtx& c, Recorder& R) {
 // Relative cost of one update with stencil (shape, M): stencil points plus
 // a fixed part for the loads, the update and the store.
 double update_cost(int shape, int M) {
-    const int P = shape == FD_CROSS ? 4 * M + 1 : (shape == FD_RHOMBUS ? 2 * M * M + 2 * M + 1
+    const int P = shape == SH_CROSS ? 4 * M + 1 : (shape == SH_RHOMBUS ? 2 * M * M + 2 * M + 1
                                                                        : (2 * M + 1) * (2 * M + 1));
     return P + 24.0;
 }
@@ -1464,7 +1465,7 @@ int fd_weights_set_n(int ndim, int shape, int M, int N, const double* w, int nw,
     symbol_extrema(S, &mneg, &mpos);
     if (mpos > 1e-9 * asum) return fail(FD_EUNSTABLE, "stencil symbol is positive (%.3g): unstable for every dt", mpos);
     if (!(mneg > 0)) return fail(FD_EINVAL, "stencil symbol is identically zero");
-    const int ks = kernel_shape(shape, N);
+    const int ks = kernel_shape(shape, M, N);
     Stencil st;
     st.ndim = ndim;
     st.shape = ks;

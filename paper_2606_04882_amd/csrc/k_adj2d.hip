@@ -76,6 +76,7 @@ bool launch_adj2d(const AdjArgs& a, int shape, int M, int rows, hipStream_t s) {
         case SH_CROSS: return dispatch_m<SH_CROSS>(a, M, rows, s);
         case SH_RHOMBUS: return dispatch_m<SH_RHOMBUS>(a, M, rows, s);
         case SH_SQUARE: return dispatch_m<SH_SQUARE>(a, M, rows, s);
+        case SH_NSHAPE: return dispatch_m<SH_NSHAPE>(a, M, rows, s);
         default: return false;
     }
 }

@@ -23,7 +23,9 @@ constexpr int kBatchRows = 4;
     CASE(SH_RHOMBUS, 2) CASE(SH_RHOMBUS, 3) CASE(SH_RHOMBUS, 4) CASE(SH_RHOMBUS, 5)             \
     CASE(SH_RHOMBUS, 6) CASE(SH_RHOMBUS, 7) CASE(SH_RHOMBUS, 8) CASE(SH_SQUARE, 1)              \
     CASE(SH_SQUARE, 2) CASE(SH_SQUARE, 3) CASE(SH_SQUARE, 4) CASE(SH_SQUARE, 5)                 \
-    CASE(SH_SQUARE, 6) CASE(SH_SQUARE, 7) CASE(SH_SQUARE, 8)
+    CASE(SH_SQUARE, 6) CASE(SH_SQUARE, 7) CASE(SH_SQUARE, 8) CASE(SH_NSHAPE, 1)                \
+    CASE(SH_NSHAPE, 2) CASE(SH_NSHAPE, 3) CASE(SH_NSHAPE, 4) CASE(SH_NSHAPE, 5)                 \
+    CASE(SH_NSHAPE, 6) CASE(SH_NSHAPE, 7) CASE(SH_NSHAPE, 8)
 
 template <int SH, int MM>
 __global__ __launch_bounds__(kBlock) void k_batch2d(BatchArgs p) {

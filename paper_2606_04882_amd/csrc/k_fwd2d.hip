@@ -72,7 +72,7 @@ static bool dispatch_m(const StepArgs& a, int M, int rows, hipStream_t s) {
 }
 
 bool have_fwd2d(int shape, int M, int rows) {
-    return shape >= 0 && shape <= 2 && M >= 1 && M <= 8 && (rows == 2 || rows == 4 || rows == 8);
+    return shape >= 0 && shape <= 3 && M >= 1 && M <= 8 && (rows == 2 || rows == 4 || rows == 8);
 }
 
 bool launch_fwd2d(const StepArgs& a, int shape, int M, int rows, hipStream_t s) {
@@ -80,6 +80,7 @@ bool launch_fwd2d(const StepArgs& a, int shape, int M, int rows, hipStream_t s) 
         case SH_CROSS: return dispatch_m<SH_CROSS>(a, M, rows, s);
         case SH_RHOMBUS: return dispatch_m<SH_RHOMBUS>(a, M, rows, s);
         case SH_SQUARE: return dispatch_m<SH_SQUARE>(a, M, rows, s);
+        case SH_NSHAPE: return dispatch_m<SH_NSHAPE>(a, M, rows, s);
         default: return false;
     }
 }

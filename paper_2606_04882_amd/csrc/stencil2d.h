@@ -79,20 +79,23 @@ __device__ __forceinline__ void s2_dx(const float* tile, int tx, int ty, const f
 // and exhausts the register file); the centre value of each row is read from
 // LDS again rather than kept in registers.  W.wd holds the weight of group
 // (dx, dz) at wd[dx*(M+1) + dz]; the group extent along z for a given dx is
-// W.mz[dx], a wave-uniform value (so one kernel serves every dense shape:
-// rhombus, square, cross-rhombus, cross-square).
+// M (square), M - dx (rhombus) or, for the cross-rhombus / cross-square
+// family, the stencil's W.mz[dx], a wave-uniform value.  With a compile-time
+// extent only the rows a column needs are differenced; with a table extent
+// every row of the tile is, so that the LDS reads carry no branches (rows
+// beyond the extent are never weighted).
 template <int SHAPE, int M, int RY, int LW>
 __device__ __forceinline__ void s2_dense_dx(const float* tile, int tx, int ty, float* acc,
                                             const Weights& W) {
 #pragma unroll 1
     for (int dx = 1; dx <= M; ++dx) {
-        const int mz = W.mz[dx];
+        const int mz = SHAPE == SH_SQUARE ? M : SHAPE == SH_RHOMBUS ? M - dx : W.mz[dx];
         const float* wrow = W.wd + dx * (M + 1);
         float d[RY + 2 * M];
 #pragma unroll
         for (int j = 0; j < RY + 2 * M; ++j) {
             d[j] = 0.f;
-            if (j >= M - mz && j < M + RY + mz) {
+            if (SHAPE == SH_NSHAPE || (j >= M - mz && j < M + RY + mz)) {
                 const float* row = tile + (ty * RY + j) * LW + tx + M;
                 d[j] = fmaf(-2.f, row[0], row[-dx] + row[dx]);
             }

@@ -209,6 +209,70 @@ size_t fd_workspace_bytes(const fd_grid* g, const fd_shot* shots, int nshots, in
                           int ckpt_every);
 
 /*
+ * Adjoint options: checkpointing scheme and gradient parameter.
+ *
+ * FD_CKPT_SEGMENT: (u^{jK-1}, u^{jK}) stored every K = ckpt_every steps,
+ *   each segment recomputed into K fields (2 ceil(nt/K) + K window fields
+ *   per shot, one extra forward pass); multi-shot 2D calls run batched.
+ * FD_CKPT_REVOLVE: binomial checkpointing with nsnap snapshots of
+ *   (u^{k-1}, u^k) (Griewank & Walther, ACM TOMS 26, 2000, Algorithm 799):
+ *   2 nsnap + 5 window fields, and the least number of forward steps any
+ *   schedule with nsnap snapshots needs (fd_revolve_plan gives it).  For
+ *   large grids whose segment storage does not fit (3D FWI).  The shots of
+ *   a call run one after another with the single-shot kernels.
+ *
+ * The gradient is dJ/dc (FD_PARAM_VELOCITY), dJ/ds for the slowness s = 1/c
+ * (FD_PARAM_SLOWNESS: -c^2 dJ/dc) or dJ/dm for m = 1/c^2 (FD_PARAM_M:
+ * -(c^3/2) dJ/dc); the factor is applied per term inside the adjoint
+ * kernels.  Results are identical across checkpointing schemes (the
+ * recomputed forward states are bitwise those of the first pass).
+ */
+#define FD_CKPT_SEGMENT 0
+#define FD_CKPT_REVOLVE 1
+#define FD_PARAM_VELOCITY 0
+#define FD_PARAM_SLOWNESS 1
+#define FD_PARAM_M 2
+
+typedef struct {
+    int ckpt;         /* FD_CKPT_SEGMENT or FD_CKPT_REVOLVE */
+    int ckpt_every;   /* FD_CKPT_SEGMENT: segment length K, 1 <= K <= nt */
+    int nsnap;        /* FD_CKPT_REVOLVE: snapshots, 0 <= nsnap <= nt */
+    int param;        /* FD_PARAM_VELOCITY, FD_PARAM_SLOWNESS or FD_PARAM_M */
+} fd_adjoint_opts;
+
+/* fd_adjoint_gradient with options (opts [host], required); grad receives
+ * the gradient of the chosen parameter (ADDED).  FD_EINVAL for unknown
+ * values in opts. */
+int fd_adjoint_gradient_ex(const fd_grid* g, const float* vel, const fd_shot* shots, int nshots,
+                           const fd_adjoint_opts* opts, float* grad, void* workspace, size_t ws_bytes,
+                           void* hip_stream);
+
+/* Workspace bytes of fd_adjoint_gradient_ex (0 for invalid input). */
+size_t fd_adjoint_workspace_bytes(const fd_grid* g, const fd_shot* shots, int nshots,
+                                  const fd_adjoint_opts* opts);
+
+/*
+ * The binomial plan that FD_CKPT_REVOLVE executes for nt steps and nsnap
+ * snapshots, as (op, arg) pairs in order:
+ *   FD_OP_ADVANCE  t   advance the current state to S_t = (u^{t-1}, u^t)
+ *   FD_OP_STORE    j   copy the current state into snapshot j (0 <= j < nsnap)
+ *   FD_OP_RESTORE  j   make snapshot j current (j = -1: the initial state S_0)
+ *   FD_OP_ADJOINT  k   adjoint iteration k on the current state S_k
+ * ADJOINT ops appear for k = nt .. 1 in that order.
+ *   ops        [host, out, optional] 2 * max_ops ints
+ *   nops       [host, out] number of ops (even when ops is NULL or too short)
+ *   fwd_steps  [host, out, optional] forward steps of the plan (each ADVANCE
+ *              from the current state's step to t counts t minus that step)
+ * FD_EINVAL for nt < 1, nsnap < 0 or nsnap > nt; FD_ENOMEM (with *nops set)
+ * when max_ops is smaller than the plan.
+ */
+#define FD_OP_ADVANCE 0
+#define FD_OP_STORE 1
+#define FD_OP_RESTORE 2
+#define FD_OP_ADJOINT 3
+int fd_revolve_plan(int nt, int nsnap, int* ops, long long max_ops, long long* nops, long long* fwd_steps);
+
+/*
  * Kernel tile configuration used for a stencil: rows per thread along the
  * marching axis (2D: z; 3D: y) and the z-chunk of the 3D kernels.
  * fd_set_tile overrides the built-in choice (as found by the autotuner);

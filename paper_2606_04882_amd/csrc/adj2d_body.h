@@ -1,6 +1,7 @@
 // One 2D adjoint tile (shared by the single-shot and the batched kernels):
 //     psi^k = b [ 2 psi^{k+1} - a psi^{k+2} + v (W * psi^{k+1}) ]
-//     grad += (2 / c) psi^{k+1} (W * u^k),   2/c = gscale / sqrt(v)
+//     grad += f psi^{k+1} (W * u^k),   f = grad_factor(gparam, gscale, v)
+//     (f = 2/c for the gradient in the velocity)
 #pragma once
 
 #include "fd_kernels.h"
@@ -23,6 +24,7 @@ struct AdjTile {
     float* grad;
     long long ldg;                    // row stride of grad
     float gscale;
+    int gparam;
     int nx, nz, x0, z0;
     int with_grad, with_update;
 };
@@ -68,7 +70,7 @@ __device__ __forceinline__ void adj2d_tile(const AdjTile& t, const Sponge& sp, c
         const int gz = t.z0 + ty * RY + j;
         if (gz >= t.nz) break;
         if (t.with_grad)
-            t.grad[(long long)gz * t.ldg + gx] = fmaf(t.gscale * rsqrtf(vv[j]) * pc[j], lu[j], gg[j]);
+            t.grad[(long long)gz * t.ldg + gx] = fmaf(grad_factor(t.gparam, t.gscale, vv[j]) * pc[j], lu[j], gg[j]);
         if (!t.with_update) continue;
         const long long k = (long long)gz * t.nx + gx;
         const int dzb = sp.nb > 0 ? band_depth(gz, t.nz, sp.nb) : 0;

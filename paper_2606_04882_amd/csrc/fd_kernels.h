@@ -145,6 +145,18 @@ struct StepArgs {
     Weights w;
 };
 
+// Gradient parameter of the adjoint kernels: the gradient term at a point is
+// f psi^{k+1} (W u^k) with f the derivative of the misfit's dependence on
+// the chosen parameter, written through v = (c dt / h)^2:
+//   velocity c:        2 / c      = gscale / sqrt(v),  gscale =  2 dt / h
+//   slowness s = 1/c:  -2 c       = gscale * sqrt(v),  gscale = -2 h / dt
+//   m = 1/c^2:         -c^2       = gscale * v,        gscale = -h^2 / dt^2
+enum { GP_VELOCITY = 0, GP_SLOWNESS = 1, GP_M = 2 };
+
+__device__ __forceinline__ float grad_factor(int gparam, float gscale, float v) {
+    return gparam == GP_VELOCITY ? gscale * rsqrtf(v) : gparam == GP_SLOWNESS ? gscale * sqrtf(v) : gscale * v;
+}
+
 // Per-step parameters of the adjoint + gradient kernels.
 struct AdjArgs {
     const float* __restrict__ pcur;  // psi^{k+1}
@@ -153,13 +165,14 @@ struct AdjArgs {
     const float* __restrict__ ufwd;  // u^k, paired with psi^{k+1} in the gradient
     const float* __restrict__ v;     // model v at the window origin
     float* __restrict__ grad;        // model gradient at the window origin (+=)
-    float gscale;                    // 2 dt / h: 2/c = gscale / sqrt(v)
+    float gscale;                    // see grad_factor
+    int gparam;                      // GP_VELOCITY / GP_SLOWNESS / GP_M
     long long ldv_y, ldv_z;
     int nx, ny, nz;
     int tiles_x, tiles_y, ntiles;
     int zchunk;
     Sponge sp;
-    int with_grad;                   // accumulate (2/c) psi^{k+1} (W u^k) into grad
+    int with_grad;                   // accumulate f psi^{k+1} (W u^k) into grad
     int with_update;                 // write psi^k
     Weights w;
 };
@@ -215,7 +228,8 @@ struct BatchAdjArgs {
     int f_pcur, f_pprev, f_pnext;    // psi^{k+1}, psi^{k+2}, psi^k slots
     int f_ufwd;                      // u^k slot (gradient pairing)
     int with_grad, with_update;
-    float gscale;                    // 2 dt / h
+    float gscale;                    // see grad_factor
+    int gparam;
     Sponge sp;
 };
 

@@ -261,8 +261,12 @@ struct Layout {
     size_t total;
 };
 
+// Call modes: forward, adjoint with segment checkpoints (K = segment
+// length), adjoint with binomial checkpoints (K = snapshot count).
+enum { MODE_FORWARD = 0, MODE_ADJ_SEGMENT = 1, MODE_ADJ_REVOLVE = 2 };
+
 bool use_batch(const fd_grid* g, int nshots, int mode) {
-    return nshots > 1 && g->ndim == 2 && !(g->flags & FD_NO_BATCH);
+    return nshots > 1 && g->ndim == 2 && !(g->flags & FD_NO_BATCH) && mode != MODE_ADJ_REVOLVE;
 }
 
 int shot_tiles2d(const fd_shot& s, int rows, int* tiles_x) {
@@ -295,10 +299,12 @@ Layout make_layout(const fd_grid* g, const fd_shot* shots, int nshots, int mode,
     L.v = off;
     off = align256(off + sizeof(float) * (size_t)mpts);
     const bool batch = use_batch(g, nshots, mode);
-    const int nseg = mode == 1 ? (g->nt + K - 1) / K : 0;
+    const int nseg = mode == MODE_ADJ_SEGMENT ? (g->nt + K - 1) / K : 0;
     // 2D single-shot forward keeps four fields so that two-steps-per-launch
-    // kernels can write out of place
-    L.nslots = (batch && mode == 1) ? AdjSlots{nseg, K}.count() : ((g->ndim == 2 && !batch && mode == 0) ? 4 : 2);
+    // kernels can write out of place; the binomial adjoint keeps its fields
+    // in the shared scratch below
+    L.nslots = (batch && mode == MODE_ADJ_SEGMENT) ? AdjSlots{nseg, K}.count()
+             : mode == MODE_ADJ_REVOLVE ? 0 : ((g->ndim == 2 && !batch && mode == MODE_FORWARD) ? 4 : 2);
     long long wmax = 0;
     for (int i = 0; i < nshots; ++i) {
         const long long wp = window_points(shots[i], g->ndim);
@@ -311,15 +317,20 @@ Layout make_layout(const fd_grid* g, const fd_shot* shots, int nshots, int mode,
         L.shots.push_back(sl);
     }
     L.psiA = L.psiB = L.ckpt = L.seg = 0;
-    if (mode == 1 && !batch) {
+    if (mode != MODE_FORWARD && !batch) {
+        // segments: nseg checkpoints of two fields and K segment fields;
+        // binomial: K snapshots of two fields and three working fields (two
+        // for the current state, one of zeros for an absent initial state)
+        const size_t nck = mode == MODE_ADJ_SEGMENT ? (size_t)nseg : (size_t)K;
+        const size_t nsegf = mode == MODE_ADJ_SEGMENT ? (size_t)K : 3;
         L.psiA = off;
         off = align256(off + sizeof(float) * (size_t)wmax);
         L.psiB = off;
         off = align256(off + sizeof(float) * (size_t)wmax);
         L.ckpt = off;
-        off = align256(off + sizeof(float) * (size_t)wmax * 2 * (size_t)nseg);
+        off = align256(off + sizeof(float) * (size_t)wmax * 2 * nck);
         L.seg = off;
-        off = align256(off + sizeof(float) * (size_t)wmax * (size_t)K);
+        off = align256(off + sizeof(float) * (size_t)wmax * nsegf);
     }
     L.desc = L.jobs = 0;
     L.njobs = 0;
@@ -549,8 +560,10 @@ struct CallCtx {
     long long ldv_y, ldv_z;
     Sponge sp;
     float q;
-    // adjoint
+    // adjoint: K = segment length (segments) or snapshot count (binomial);
+    // gparam = GP_* parameter of the gradient
     int K;
+    int gparam = GP_VELOCITY;
     float* grad;
     // host-built data uploaded to the workspace before the work runs
     std::vector<unsigned char> blob;
@@ -752,12 +765,21 @@ int adj_rows(const CallCtx& c, const ShotCtx& s) {
     return c.g->ndim == 3 ? adj_rows3d(s.st.shape, s.st.rows) : s.st.rows;
 }
 
+// gscale of grad_factor for the call's gradient parameter
+float grad_scale(const CallCtx& c) {
+    const double dt = c.g->dt, h = c.g->h;
+    if (c.gparam == GP_SLOWNESS) return (float)(-2.0 * h / dt);
+    if (c.gparam == GP_M) return (float)(-(h * h) / (dt * dt));
+    return (float)(2.0 * dt / h);
+}
+
 AdjArgs base_adj(const CallCtx& c, const ShotCtx& s) {
     AdjArgs a;
     std::memset(&a, 0, sizeof a);
     a.v = s.v;
     a.grad = c.grad + model_offset(c, *s.s);
-    a.gscale = (float)(2.0 * c.g->dt / c.g->h);
+    a.gscale = grad_scale(c);
+    a.gparam = c.gparam;
     a.ldv_y = c.ldv_y;
     a.ldv_z = c.ldv_z;
     a.nx = s.nx;
@@ -842,6 +864,216 @@ int enqueue_adjoint_shot(const CallCtx& c, const ShotCtx& s, Recorder& R) {
         a.with_grad = 1;
         a.with_update = 0;
         if (!launch_adj(c, s, a, st)) return fail(FD_EUNSUPPORTED, "adjoint kernel not compiled");
+        R.launched();
+    }
+    return R.err;
+}
+
+// ---------------------------------------------------------------------------
+// binomial checkpointing (Griewank & Walther, ACM TOMS 26, 2000: "revolve")
+// ---------------------------------------------------------------------------
+// The adjoint iteration k (k = nt .. 1) needs u^k, i.e. the forward state
+// S_k = (u^{k-1}, u^k); S_0 is the initial data.  With s snapshot slots, the
+// least number of forward steps that serves every iteration is, for
+// l = nt + 1 and r = s + 1 stored states (S_0 included), t l - C(r+t, r+1)
+// with t the least integer such that C(r+t, r) >= l.  The plan reaches it by
+// the binomial split: advance S_a -> S_{a+m}, store it, serve (a+m, b] with
+// one slot fewer, run iteration a+m on the stored state, then serve
+// (a, a+m-1] from S_a with every slot; m minimises
+// m + cost(b-a-m, s-1) + cost(m-1, s), a convex function of m.
+struct RevolvePlanner {
+    int nsnap;
+    std::vector<int> ops;   // (op, arg) pairs, FD_OP_*
+
+    static long long cost(long long L, int s) {
+        if (L <= 0) return 0;
+        const long long l = L + 1;
+        const unsigned long long r = (unsigned long long)s + 1;
+        // b = C(r+t, r), grown one t at a time (exact: C(n+1, r) = C(n, r) (n+1) / (n+1-r))
+        unsigned long long b = 1, t = 0;
+        while (b < (unsigned long long)l) {
+            ++t;
+            b = (unsigned long long)((unsigned __int128)b * (r + t) / t);
+        }
+        // C(r+t, r+1) = C(r+t, r) t / (r+1)
+        const unsigned long long b1 = (unsigned long long)((unsigned __int128)b * t / (r + 1));
+        return (long long)(t * (unsigned long long)l - b1);
+    }
+    void emit(int op, int arg) {
+        ops.push_back(op);
+        ops.push_back(arg);
+    }
+    // serve iterations b .. a+1; S_a is in slot sa (-1: the initial data);
+    // slots >= next are free; cur: whether the current state is S_a
+    void serve(int a, int b, int sa, int next, bool cur) {
+        while (b > a) {
+            const int l = b - a, k = nsnap - next;
+            if (!cur) emit(FD_OP_RESTORE, sa);
+            cur = false;
+            if (l == 1 || k == 0) {   // advance to b, iteration b, restart from S_a
+                emit(FD_OP_ADVANCE, b);
+                emit(FD_OP_ADJOINT, b);
+                --b;
+                continue;
+            }
+            int best = l;
+            long long bc = cost(l - 1, k) + l;
+            for (int m = 1; m < l; ++m) {
+                const long long c = m + cost(l - m, k - 1) + cost(m - 1, k);
+                if (c < bc) {
+                    bc = c;
+                    best = m;
+                }
+            }
+            if (best == l) {
+                emit(FD_OP_ADVANCE, b);
+                emit(FD_OP_ADJOINT, b);
+                --b;
+                continue;
+            }
+            emit(FD_OP_ADVANCE, a + best);
+            emit(FD_OP_STORE, next);
+            serve(a + best, b, next, next + 1, true);
+            emit(FD_OP_RESTORE, next);
+            emit(FD_OP_ADJOINT, a + best);
+            b = a + best - 1;
+        }
+    }
+    long long plan(int nt, int s) {
+        nsnap = s;
+        ops.clear();
+        serve(0, nt, -1, 0, true);
+        long long steps = 0, cur = 0;
+        std::vector<long long> slot(std::max(s, 1), 0);
+        for (size_t i = 0; i < ops.size(); i += 2) {
+            if (ops[i] == FD_OP_ADVANCE) {
+                steps += ops[i + 1] - cur;
+                cur = ops[i + 1];
+            } else if (ops[i] == FD_OP_STORE) {
+                slot[ops[i + 1]] = cur;
+            } else if (ops[i] == FD_OP_RESTORE) {
+                cur = ops[i + 1] < 0 ? 0 : slot[ops[i + 1]];
+            }
+        }
+        return steps;
+    }
+};
+
+// Adjoint of one shot under a binomial plan.  Snapshot j holds two fields
+// at ckpt + 2 j n; the current state (P, C) = (u^{k-1}, u^k) lives in
+// snapshots, the initial data or the working fields W0, W1 (a step writes
+// over P only when P is a working field).  An ADVANCE followed by STORE j
+// writes its last two levels straight into snapshot j.  Traces are written
+// the first time a step runs (the first pass runs every step in order).
+int enqueue_adjoint_revolve(const CallCtx& c, const ShotCtx& s, Recorder& R) {
+    hipStream_t st = R.stream;
+    const int nt = c.g->nt, nrec = s.s->nrec;
+    const long long n = s.npts;
+    float* ckpt = (float*)(c.ws + c.L.ckpt);
+    float* W0 = (float*)(c.ws + c.L.seg);
+    float* W1 = W0 + n;
+    float* Z = W0 + 2 * n;
+    float* pa = (float*)(c.ws + c.L.psiA);
+    float* pb = (float*)(c.ws + c.L.psiB);
+    RevolvePlanner planner;
+    planner.plan(nt, c.K);
+    const std::vector<int>& ops = planner.ops;
+
+    launch_rec_index(s.s->rec, nrec, c.g->ndim, s.nx, s.ny, s.nz, s.rec, c.flags, st);
+    R.launched();
+    if (!s.s->init_prev || !s.s->init_cur) {
+        launch_fill(Z, n, 0.f, st);
+        R.launched();
+    }
+    const float* init_p = s.s->init_prev ? s.s->init_prev : Z;
+    const float* init_c = s.s->init_cur ? s.s->init_cur : Z;
+    auto snapP = [&](int j) { return ckpt + (size_t)j * 2 * n; };
+    auto snapC = [&](int j) { return ckpt + (size_t)j * 2 * n + n; };
+    const float* P = init_p;
+    const float* C = init_c;
+    int cur = 0, hi = 0;
+    std::vector<int> slot_step(std::max(c.K, 1), 0);
+    StepArgs f = base_step(c, s);
+    launch_fill(pa, n, 0.f, st);   // psi^{nt+1}
+    launch_fill(pb, n, 0.f, st);   // psi^{nt+2}
+    R.launched(2);
+    float* pcur = pa;
+    float* pprev = pb;
+    AdjArgs a = base_adj(c, s);
+    for (size_t i = 0; i < ops.size(); i += 2) {
+        const int op = ops[i], arg = ops[i + 1];
+        if (op == FD_OP_ADVANCE) {
+            const int tgt = (i + 2 < ops.size() && ops[i + 2] == FD_OP_STORE) ? ops[i + 3] : -1;
+            if (tgt >= 0 && arg == cur + 1) {   // u^{arg-1} is C: copy it into the snapshot
+                launch_copy(snapP(tgt), C, n, st);
+                R.launched();
+            }
+            while (cur < arg) {
+                float* D;
+                if (tgt >= 0 && cur + 1 == arg - 1) D = snapP(tgt);
+                else if (tgt >= 0 && cur + 1 == arg) D = snapC(tgt);
+                else if (P == W0 || P == W1) D = (float*)P;
+                else D = C == W0 ? W1 : W0;
+                f.ucur = C;
+                f.uprev = P;
+                f.unext = D;
+                f.step = cur;
+                f.trace_out = (cur >= hi && cur >= 1 && nrec > 0) ? s.s->traces + (size_t)(cur - 1) * nrec : nullptr;
+                if (!launch_step(c, s, f, st)) return fail(FD_EUNSUPPORTED, "kernel not compiled");
+                R.launched();
+                P = C;
+                C = D;
+                ++cur;
+                if (cur > hi) {
+                    hi = cur;
+                    if (hi == nt) {   // trace nt-1 <- u^nt; final states
+                        if (nrec > 0) launch_gather(C, s.rec, nrec, s.s->traces + (size_t)(nt - 1) * nrec, st);
+                        if (s.s->final_prev) launch_copy(s.s->final_prev, P, n, st);
+                        if (s.s->final_cur) launch_copy(s.s->final_cur, C, n, st);
+                        R.launched(3);
+                    }
+                }
+            }
+        } else if (op == FD_OP_STORE) {
+            if (P != snapP(arg) || C != snapC(arg)) {
+                launch_copy(snapP(arg), P, n, st);
+                launch_copy(snapC(arg), C, n, st);
+                R.launched(2);
+                P = snapP(arg);
+                C = snapC(arg);
+            }
+            slot_step[arg] = cur;
+        } else if (op == FD_OP_RESTORE) {
+            P = arg < 0 ? init_p : snapP(arg);
+            C = arg < 0 ? init_c : snapC(arg);
+            cur = arg < 0 ? 0 : slot_step[arg];
+        } else {   // FD_OP_ADJOINT: psi^k from psi^{k+1}, psi^{k+2}; gradient with u^k
+            a.pcur = pcur;
+            a.pprev = pprev;
+            a.pnext = pprev;
+            a.ufwd = C;
+            a.with_grad = arg < nt;
+            a.with_update = 1;
+            if (!launch_adj(c, s, a, st)) return fail(FD_EUNSUPPORTED, "adjoint kernel not compiled");
+            if (nrec > 0)
+                launch_inject(pprev, s.rec, nrec, s.s->trace_adj + (size_t)(arg - 1) * nrec, s.v, c.ldv_y,
+                              c.ldv_z, c.sp, s.nx, s.ny, s.nz, st);
+            std::swap(pcur, pprev);
+            R.launched(2);
+        }
+    }
+    if (s.s->init_cur) {   // last gradient term f psi^1 (W u^0)
+        a.pcur = pcur;
+        a.pprev = pprev;
+        a.pnext = pprev;
+        a.ufwd = s.s->init_cur;
+        a.with_grad = 1;
+        a.with_update = 0;
+        if (!launch_adj(c, s, a, st)) return fail(FD_EUNSUPPORTED, "adjoint kernel not compiled");
+        R.launched();
+    }
+    if (c.g->check_finite && nrec > 0) {
+        launch_check_finite(s.s->traces, (long long)nt * nrec, c.flags, st);
         R.launched();
     }
     return R.err;
@@ -948,7 +1180,8 @@ int enqueue_batched_adjoint(const CallCtx& c, Recorder& R) {
     };
     BatchAdjArgs a;
     a.shots = dshots;
-    a.gscale = (float)(2.0 * c.g->dt / c.g->h);
+    a.gscale = grad_scale(c);
+    a.gparam = c.gparam;
     a.sp = c.sp;
     auto adj = [&](bool inject, int k) {
         for (const CallCtx::Group& g : c.groups) {
@@ -1057,7 +1290,7 @@ void build_batch_blob(CallCtx& c, int mode) {
     std::vector<BatchShot> desc(nshots);
     std::vector<int2> jobs;
     jobs.reserve((size_t)c.L.njobs);
-    const AdjSlots S{mode == 1 ? (c.g->nt + c.K - 1) / c.K : 0, c.K};
+    const AdjSlots S{mode == MODE_ADJ_SEGMENT ? (c.g->nt + c.K - 1) / c.K : 0, c.K};
     c.groups.clear();
     std::vector<double> gcost;
     for (int k = 0; k < nshots; ++k) {
@@ -1094,7 +1327,7 @@ void build_batch_blob(CallCtx& c, int mode) {
         d.trace_adj = s.s->trace_adj;
         d.init_prev = s.s->init_prev;
         d.init_cur = s.s->init_cur;
-        d.gacc = mode == 1 ? s.bufA + (long long)S.gacc() * s.npts : nullptr;
+        d.gacc = mode == MODE_ADJ_SEGMENT ? s.bufA + (long long)S.gacc() * s.npts : nullptr;
         d.variant = variant(order[k]);
         d.w = s.st.w32;
         for (int t = 0; t < d.ntiles; ++t) jobs.push_back(make_int2(k, t));
@@ -1130,17 +1363,18 @@ int enqueue_call(const CallCtx& c, int mode, Recorder& R) {
     launch_vprep(c.vel, c.vfield, mpts, c.g->dt / c.g->h, c.flags, R.stream);
     R.launched(2);
     if (use_batch(c.g, (int)c.shots.size(), mode))
-        return mode == 0 ? enqueue_batched(c, R) : enqueue_batched_adjoint(c, R);
+        return mode == MODE_FORWARD ? enqueue_batched(c, R) : enqueue_batched_adjoint(c, R);
     // forward shots own their fields: unless FD_NO_BATCH asks for shot after
     // shot, they run on parallel branches (adjoint shots share the checkpoint
     // and adjoint fields and the gradient, so they stay in sequence)
     const int ns = (int)c.shots.size();
-    const bool par = mode == 0 && ns > 1 && !(c.g->flags & FD_NO_BATCH);
+    const bool par = mode == MODE_FORWARD && ns > 1 && !(c.g->flags & FD_NO_BATCH);
     if (par) R.fork(ns);
     for (int i = 0; i < ns; ++i) {
         if (par) R.active = i;
-        rc = mode == 0 ? enqueue_forward_shot(c, c.shots[i], nullptr, 0, nullptr, R)
-                       : enqueue_adjoint_shot(c, c.shots[i], R);
+        rc = mode == MODE_FORWARD ? enqueue_forward_shot(c, c.shots[i], nullptr, 0, nullptr, R)
+           : mode == MODE_ADJ_SEGMENT ? enqueue_adjoint_shot(c, c.shots[i], R)
+                                      : enqueue_adjoint_revolve(c, c.shots[i], R);
         if (rc) break;
     }
     R.active = -1;
@@ -1184,6 +1418,7 @@ int run_call(CallCtx& c, int mode, hipStream_t user) {
     key.push_back((uint64_t)dev);
     key.push_back((uint64_t)mode);
     key.push_back((uint64_t)c.K);
+    key.push_back((uint64_t)c.gparam);
     key.push_back((uint64_t)(uintptr_t)c.grad);
     key_push(key, c.g, sizeof(fd_grid));
     key.push_back((uint64_t)(uintptr_t)c.vel);
@@ -1275,7 +1510,8 @@ int prepare(CallCtx& c, const fd_grid* g, const float* vel, const fd_shot* shots
     if (rc) return rc;
     if (!vel) return fail(FD_EINVAL, "vel is NULL");
     if (!shots || nshots < 1) return fail(FD_EINVAL, "need at least one shot");
-    if (mode == 1 && (K < 1 || K > g->nt)) return fail(FD_EINVAL, "ckpt_every must be in [1, nt]");
+    if (mode == MODE_ADJ_SEGMENT && (K < 1 || K > g->nt)) return fail(FD_EINVAL, "ckpt_every must be in [1, nt]");
+    if (mode == MODE_ADJ_REVOLVE && (K < 0 || K > g->nt)) return fail(FD_EINVAL, "nsnap must be in [0, nt]");
     c.g = g;
     c.vel = vel;
     c.nshots = nshots;
@@ -1299,7 +1535,7 @@ int prepare(CallCtx& c, const fd_grid* g, const float* vel, const fd_shot* shots
     c.grad = nullptr;
     for (int i = 0; i < nshots; ++i) {
         ShotCtx s;
-        rc = check_shot(g, shots[i], i, mode == 1, &s.st);
+        rc = check_shot(g, shots[i], i, mode != MODE_FORWARD, &s.st);
         if (rc) return rc;
         s.s = &shots[i];
         s.nx = (int)shots[i].extent[0];
@@ -1577,7 +1813,7 @@ int fd_get_tile(int stencil_id, int* rows, int* zchunk) {
 }
 
 size_t fd_workspace_bytes(const fd_grid* g, const fd_shot* shots, int nshots, int mode, int ckpt_every) {
-    if (check_grid(g) || !shots || nshots < 1) return 0;
+    if (check_grid(g) || !shots || nshots < 1 || mode < 0 || mode > 1) return 0;
     if (mode == 1 && (ckpt_every < 1 || ckpt_every > g->nt)) return 0;
     return make_layout(g, shots, nshots, mode, mode == 1 ? ckpt_every : 1).total;
 }
@@ -1606,6 +1842,67 @@ int fd_adjoint_gradient(const fd_grid* g, const float* vel, const fd_shot* shots
     rc = run_call(c, 1, st);
     if (rc) return rc;
     return finish_checks(c, st);
+}
+
+namespace {
+int adjoint_opts(const fd_adjoint_opts* o, int* mode, int* K) {
+    if (!o) return fail(FD_EINVAL, "opts is NULL");
+    if (o->param < FD_PARAM_VELOCITY || o->param > FD_PARAM_M)
+        return fail(FD_EINVAL, "unknown gradient parameter %d", o->param);
+    if (o->ckpt == FD_CKPT_SEGMENT) {
+        *mode = MODE_ADJ_SEGMENT;
+        *K = o->ckpt_every;
+    } else if (o->ckpt == FD_CKPT_REVOLVE) {
+        *mode = MODE_ADJ_REVOLVE;
+        *K = o->nsnap;
+    } else {
+        return fail(FD_EINVAL, "unknown checkpointing scheme %d", o->ckpt);
+    }
+    return FD_OK;
+}
+}  // namespace
+
+int fd_adjoint_gradient_ex(const fd_grid* g, const float* vel, const fd_shot* shots, int nshots,
+                           const fd_adjoint_opts* opts, float* grad, void* workspace, size_t ws_bytes,
+                           void* hip_stream) {
+    g_err.clear();
+    int mode = 0, K = 0;
+    int rc = adjoint_opts(opts, &mode, &K);
+    if (rc) return rc;
+    if (!grad) return fail(FD_EINVAL, "grad is NULL");
+    CallCtx c;
+    rc = prepare(c, g, vel, shots, nshots, mode, K, workspace, ws_bytes);
+    if (rc) return rc;
+    c.grad = grad;
+    c.gparam = opts->param == FD_PARAM_SLOWNESS ? GP_SLOWNESS : opts->param == FD_PARAM_M ? GP_M : GP_VELOCITY;
+    hipStream_t st = (hipStream_t)hip_stream;
+    rc = run_call(c, mode, st);
+    if (rc) return rc;
+    return finish_checks(c, st);
+}
+
+size_t fd_adjoint_workspace_bytes(const fd_grid* g, const fd_shot* shots, int nshots, const fd_adjoint_opts* opts) {
+    int mode = 0, K = 0;
+    if (adjoint_opts(opts, &mode, &K) || check_grid(g) || !shots || nshots < 1) return 0;
+    if (mode == MODE_ADJ_SEGMENT && (K < 1 || K > g->nt)) return 0;
+    if (mode == MODE_ADJ_REVOLVE && (K < 0 || K > g->nt)) return 0;
+    return make_layout(g, shots, nshots, mode, K).total;
+}
+
+int fd_revolve_plan(int nt, int nsnap, int* ops, long long max_ops, long long* nops, long long* fwd_steps) {
+    g_err.clear();
+    if (nt < 1) return fail(FD_EINVAL, "nt must be >= 1");
+    if (nsnap < 0 || nsnap > nt) return fail(FD_EINVAL, "nsnap must be in [0, nt]");
+    if (!nops) return fail(FD_EINVAL, "nops is NULL");
+    RevolvePlanner p;
+    const long long steps = p.plan(nt, nsnap);
+    *nops = (long long)p.ops.size() / 2;
+    if (fwd_steps) *fwd_steps = steps;
+    if (ops) {
+        if (max_ops < *nops) return fail(FD_ENOMEM, "plan has %lld ops, room for %lld", *nops, max_ops);
+        std::memcpy(ops, p.ops.data(), sizeof(int) * p.ops.size());
+    }
+    return FD_OK;
 }
 
 size_t fd_dispersion_workspace_bytes(int nt, int nrec, int nscale) {

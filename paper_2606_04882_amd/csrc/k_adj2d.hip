@@ -32,6 +32,7 @@ __global__ __launch_bounds__(kBlock) void k_adj2d(AdjArgs p) {
     a.grad = p.grad;
     a.ldg = p.ldv_y;
     a.gscale = p.gscale;
+    a.gparam = p.gparam;
     a.nx = p.nx;
     a.nz = p.nz;
     a.x0 = bx * kTileX;

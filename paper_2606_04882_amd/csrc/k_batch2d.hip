@@ -78,6 +78,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_adj2d(BatchAdjArgs p) {
     a.grad = s.gacc;
     a.ldg = s.nx;
     a.gscale = p.gscale;
+    a.gparam = p.gparam;
     a.nx = s.nx;
     a.nz = s.nz;
     const int tz = lt / s.tiles_x;

@@ -316,7 +316,7 @@ __global__ __launch_bounds__(kBlock3) void k_adj3d_cross(AdjArgs p) {
                 const long long k = ((long long)z * p.ny + gy) * p.nx + b.gx;
                 const long long kv = (long long)z * p.ldv_z + (long long)gy * p.ldv_y + b.gx;
                 const float pc = qp[j][M];
-                if (p.with_grad) p.grad[kv] = fmaf(p.gscale * rsqrtf(vv[j]) * pc, Lu, gg[j]);
+                if (p.with_grad) p.grad[kv] = fmaf(grad_factor(p.gparam, p.gscale, vv[j]) * pc, Lu, gg[j]);
                 if (p.with_update) {
                     bool inband;
                     const float e = damp_e(p.sp, b.gx, gy, z, p.nx, p.ny, p.nz, inband);
@@ -558,7 +558,7 @@ __global__ __launch_bounds__(kBlock3) void k_adj3d_gen(AdjArgs p) {
             if (b.gx < p.nx && gy < p.ny) {
                 const long long k = ((long long)z * p.ny + gy) * p.nx + b.gx;
                 const long long kv = (long long)z * p.ldv_z + (long long)gy * p.ldv_y + b.gx;
-                if (p.with_grad) p.grad[kv] = fmaf(p.gscale * rsqrtf(vv[j]) * pc, Lu, gg[j]);
+                if (p.with_grad) p.grad[kv] = fmaf(grad_factor(p.gparam, p.gscale, vv[j]) * pc, Lu, gg[j]);
                 if (p.with_update) {
                     bool inband;
                     const float e = damp_e(p.sp, b.gx, gy, z, p.nx, p.ny, p.nz, inband);

@@ -31,6 +31,11 @@ FD_NO_GRAPH, FD_NO_BATCH = 1, 2
 FD_CROSS_RHOMBUS, FD_CROSS_SQUARE = 3, 4
 SHAPES = {"cross": FD_CROSS, "rhombus": FD_RHOMBUS, "square": FD_SQUARE,
           "cross_rhombus": FD_CROSS_RHOMBUS, "cross_square": FD_CROSS_SQUARE}
+FD_CKPT_SEGMENT, FD_CKPT_REVOLVE = 0, 1
+FD_PARAM_VELOCITY, FD_PARAM_SLOWNESS, FD_PARAM_M = 0, 1, 2
+CKPT = {"segment": FD_CKPT_SEGMENT, "revolve": FD_CKPT_REVOLVE}
+PARAMS = {"velocity": FD_PARAM_VELOCITY, "slowness": FD_PARAM_SLOWNESS, "m": FD_PARAM_M}
+FD_OP_ADVANCE, FD_OP_STORE, FD_OP_RESTORE, FD_OP_ADJOINT = 0, 1, 2, 3
 _STATUS = {1: "EINVAL", 2: "EUNSTABLE", 3: "ENOMEM", 4: "EDEVICE", 5: "ENONFINITE", 6: "EUNSUPPORTED"}
 
 
@@ -54,6 +59,11 @@ class FdShot(ctypes.Structure):
                 ("traces", ctypes.c_void_p), ("trace_adj", ctypes.c_void_p),
                 ("init_prev", ctypes.c_void_p), ("init_cur", ctypes.c_void_p),
                 ("final_prev", ctypes.c_void_p), ("final_cur", ctypes.c_void_p)]
+
+
+class FdAdjointOpts(ctypes.Structure):
+    _fields_ = [("ckpt", ctypes.c_int), ("ckpt_every", ctypes.c_int), ("nsnap", ctypes.c_int),
+                ("param", ctypes.c_int)]
 
 
 def _load() -> ctypes.CDLL:
@@ -81,6 +91,12 @@ def _load() -> ctypes.CDLL:
                                ctypes.c_size_t, ctypes.c_void_p]
     lib.fd_adjoint_gradient.argtypes = [P(FdGrid), ctypes.c_void_p, P(FdShot), ctypes.c_int, ctypes.c_int,
                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
+    lib.fd_adjoint_gradient_ex.argtypes = [P(FdGrid), ctypes.c_void_p, P(FdShot), ctypes.c_int, P(FdAdjointOpts),
+                                           ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
+    lib.fd_adjoint_workspace_bytes.restype = ctypes.c_size_t
+    lib.fd_adjoint_workspace_bytes.argtypes = [P(FdGrid), P(FdShot), ctypes.c_int, P(FdAdjointOpts)]
+    lib.fd_revolve_plan.argtypes = [ctypes.c_int, ctypes.c_int, P(ctypes.c_int), ctypes.c_longlong,
+                                    P(ctypes.c_longlong), P(ctypes.c_longlong)]
     lib.fd_dispersion_workspace_bytes.restype = ctypes.c_size_t
     lib.fd_dispersion_workspace_bytes.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int]
     lib.fd_dispersion.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_double,
@@ -274,22 +290,53 @@ def fd_forward(grid: Grid, vel: torch.Tensor, shots: Sequence[Shot], ws: Optiona
                            ctypes.c_void_p(_stream_handle(vel.device))))
 
 
+def _adjoint_opts(ckpt: str, ckpt_every: int, nsnap: int, param: str) -> "FdAdjointOpts":
+    if ckpt not in CKPT or param not in PARAMS:
+        raise ValueError(f"ckpt must be one of {sorted(CKPT)}, param one of {sorted(PARAMS)}")
+    return FdAdjointOpts(CKPT[ckpt], int(ckpt_every), int(nsnap), PARAMS[param])
+
+
+def fd_adjoint_workspace_bytes(grid: Grid, shots: Sequence[Shot], ckpt: str = "segment", ckpt_every: int = 1,
+                               nsnap: int = 0, param: str = "velocity") -> int:
+    g = grid.c()
+    arr = (FdShot * len(shots))(*[_shot_c(s, grid) for s in shots])
+    o = _adjoint_opts(ckpt, ckpt_every, nsnap, param)
+    return int(_lib.fd_adjoint_workspace_bytes(ctypes.byref(g), arr, len(shots), ctypes.byref(o)))
+
+
 def fd_adjoint_gradient(grid: Grid, vel: torch.Tensor, shots: Sequence[Shot], ckpt_every: int,
-                        grad: torch.Tensor, ws: Optional[torch.Tensor] = None):
-    """Adjoint run; dJ/dc of every shot is added into `grad`."""
+                        grad: torch.Tensor, ws: Optional[torch.Tensor] = None, ckpt: str = "segment",
+                        nsnap: int = 0, param: str = "velocity"):
+    """Adjoint run; the gradient of every shot (in `param`: velocity,
+    slowness or m = 1/c^2) is added into `grad`.  ckpt "segment" stores
+    states every `ckpt_every` steps; "revolve" runs the binomial plan with
+    `nsnap` snapshots."""
     if vel.dtype != torch.float32 or tuple(vel.shape) != tuple(grid.shape):
         raise ValueError(f"vel must be float32 of shape {grid.shape}")
     if grad.dtype != torch.float32 or tuple(grad.shape) != tuple(grid.shape):
         raise ValueError("grad must be float32 with the model's shape")
     g = grid.c()
     arr = (FdShot * len(shots))(*[_shot_c(s, grid) for s in shots])
-    nbytes = int(_lib.fd_workspace_bytes(ctypes.byref(g), arr, len(shots), 1, ckpt_every))
+    o = _adjoint_opts(ckpt, ckpt_every, nsnap, param)
+    nbytes = int(_lib.fd_adjoint_workspace_bytes(ctypes.byref(g), arr, len(shots), ctypes.byref(o)))
     if nbytes == 0:
-        raise FdError(FD_EINVAL, "invalid grid/shots/ckpt_every for fd_workspace_bytes")
+        raise FdError(FD_EINVAL, "invalid grid/shots/checkpointing options for fd_adjoint_workspace_bytes")
     if ws is None:
         ws = workspace(nbytes, vel.device)
-    _check(_lib.fd_adjoint_gradient(ctypes.byref(g), _ptr(vel), arr, len(shots), ckpt_every, _ptr(grad),
-                                    _ptr(ws), ws.numel(), ctypes.c_void_p(_stream_handle(vel.device))))
+    _check(_lib.fd_adjoint_gradient_ex(ctypes.byref(g), _ptr(vel), arr, len(shots), ctypes.byref(o), _ptr(grad),
+                                       _ptr(ws), ws.numel(), ctypes.c_void_p(_stream_handle(vel.device))))
+
+
+def fd_revolve_plan(nt: int, nsnap: int):
+    """(ops as an [n, 2] int array of (FD_OP_*, arg), forward steps) of the
+    binomial plan for nt steps and nsnap snapshots."""
+    n = ctypes.c_longlong(0)
+    steps = ctypes.c_longlong(0)
+    _check(_lib.fd_revolve_plan(nt, nsnap, None, 0, ctypes.byref(n), ctypes.byref(steps)))
+    ops = np.zeros(2 * max(n.value, 1), dtype=np.int32)
+    _check(_lib.fd_revolve_plan(nt, nsnap, ops.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), n.value,
+                                ctypes.byref(n), ctypes.byref(steps)))
+    return ops[: 2 * n.value].reshape(-1, 2), int(steps.value)
 
 
 # ---------------------------------------------------------------------------

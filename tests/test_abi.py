@@ -217,3 +217,61 @@ def test_dispersion_workspace_and_validation(F):
     assert rc == F.FD_EINVAL and "nscale" in F.fd_last_error()
     rc = F._lib.fd_dispersion(16, 16, 500, 10, 1e-3, 40, 6.0, None, ctypes.addressof(d), None, 256, 10, None)
     assert rc == F.FD_ENOMEM
+
+
+@pytest.mark.parametrize("nt", [1, 2, 3, 7, 40, 333, 1000])
+@pytest.mark.parametrize("nsnap", [0, 1, 2, 5, 12])
+def test_revolve_plan_is_valid_and_optimal(F, nt, nsnap):
+    """The library's binomial plan serves iterations nt..1 in order within
+    nsnap slots (checked by the oracle's model) with the least number of
+    forward steps (the oracle's closed form, itself pinned by exhaustive
+    search and the split recursion)."""
+    from oracle import checkpoint as CK
+    if nsnap > nt:
+        pytest.skip("nsnap > nt is rejected")
+    ops, steps = F.fd_revolve_plan(nt, nsnap)
+    assert CK.simulate_plan([(int(a), int(b)) for a, b in ops], nt, nsnap) == steps
+    assert steps == CK.binomial_cost(nt, nsnap)
+    if nt <= 40 and nsnap <= 5:
+        assert steps == CK.optimal_cost(nt, nsnap)
+
+
+def test_revolve_plan_and_adjoint_options_are_validated(F):
+    import ctypes
+    n = ctypes.c_longlong(0)
+    assert F._lib.fd_revolve_plan(0, 0, None, 0, ctypes.byref(n), None) == F.FD_EINVAL
+    assert F._lib.fd_revolve_plan(10, -1, None, 0, ctypes.byref(n), None) == F.FD_EINVAL
+    assert F._lib.fd_revolve_plan(10, 11, None, 0, ctypes.byref(n), None) == F.FD_EINVAL
+    assert F._lib.fd_revolve_plan(10, 2, None, 0, None, None) == F.FD_EINVAL
+    buf = (ctypes.c_int * 4)()
+    assert F._lib.fd_revolve_plan(10, 2, buf, 2, ctypes.byref(n), None) == F.FD_ENOMEM
+    assert n.value == len(F.fd_revolve_plan(10, 2)[0])
+    sid = F.fd_weights_set(2, "cross", 4, oracle_weights(2, "taylor", "cross", 4))
+    wav = np.zeros(100, np.float32)
+    g = F.Grid(shape=(300, 400), h=10.0, dt=1e-3, nt=100, nb=10, eta_max=1.0, vmax=3000.0).c()
+    s = F.FdShot()
+    s.stencil_id = sid
+    s.src[0], s.src[1], s.src[2] = 20, 0, 20
+    s.extent[0], s.extent[1], s.extent[2] = 400, 1, 300
+    s.wavelet = wav.ctypes.data
+    arr = (F.FdShot * 1)(s)
+
+    def ws(ckpt, every, nsnap, param=0):
+        o = F.FdAdjointOpts(ckpt, every, nsnap, param)
+        return int(F._lib.fd_adjoint_workspace_bytes(ctypes.byref(g), arr, 1, ctypes.byref(o)))
+
+    field = 300 * 400 * 4
+    seg10 = ws(F.FD_CKPT_SEGMENT, 10, 0)
+    assert seg10 == _ws_bytes(F, (300, 400), 1, 10, sid, wav)
+    r0, r4 = ws(F.FD_CKPT_REVOLVE, 0, 0), ws(F.FD_CKPT_REVOLVE, 0, 4)
+    assert r4 - r0 == 8 * field                  # two fields per snapshot
+    assert r0 < seg10 and r0 >= 5 * field        # psi x2 and three working fields
+    assert ws(F.FD_CKPT_REVOLVE, 0, 101) == 0    # nsnap > nt
+    assert ws(F.FD_CKPT_SEGMENT, 0, 0) == 0      # K < 1
+    assert ws(2, 10, 0) == 0 and ws(F.FD_CKPT_SEGMENT, 10, 0, 3) == 0
+    o = F.FdAdjointOpts(F.FD_CKPT_REVOLVE, 0, 2, 7)
+    rc = F._lib.fd_adjoint_gradient_ex(ctypes.byref(g), ctypes.c_void_p(16), arr, 1, ctypes.byref(o),
+                                       ctypes.c_void_p(16), None, 0, None)
+    assert rc == F.FD_EINVAL and "parameter" in F.fd_last_error()
+    assert F._lib.fd_adjoint_gradient_ex(ctypes.byref(g), ctypes.c_void_p(16), arr, 1, None,
+                                         ctypes.c_void_p(16), None, 0, None) == F.FD_EINVAL

@@ -1,0 +1,172 @@
+"""GPU parity of the binomial-checkpointing adjoint and of the gradient in
+slowness and m = 1/c^2 (marked gpu).
+
+* The binomial plan recomputes forward states with the same kernels as the
+  first pass, so its gradient and traces are bitwise those of the segment
+  scheme, for any snapshot count (2D and 3D, with and without initial data).
+* dJ/ds and dJ/dm from the kernels match the oracle's FP64 gradient mapped by
+  the chain rule (itself pinned by finite differences in s and m) to the
+  1e-3 gradient bar, in 2D (single-shot and batched) and 3D.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+from oracle import checkpoint as CK  # noqa: E402
+from oracle import stepper as S  # noqa: E402
+from paper_2606_04882_amd import synth  # noqa: E402
+from tests.fdcase import layered, oracle_weights, q32, rel_l2, rounded_stencil, v32  # noqa: E402
+
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def F():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2606_04882_amd import fdwave
+    return fdwave
+
+
+def case(F, ndim, shape, M, nt, seed=1, init=False):
+    h, nb = 10.0, 6
+    dims = (40, 56) if ndim == 2 else (22, 18, 36)
+    vel = layered(dims, seed=seed)
+    vmax = float(vel.max())
+    dt = (0.5 if ndim == 2 else 0.4) * 0.45 * h / vmax
+    wo = oracle_weights(ndim, "specls" if shape == "square" else "dispte", shape, M, vmax * dt / h)
+    sid = F.fd_weights_set(ndim, shape, M, wo)
+    if ndim == 3:
+        F.fd_set_tile(sid, 2 if shape == "cross" else 1, 8)
+    eta = synth.sponge_eta_max(vmax, nb, h)
+    wav = synth.ricker(nt, dt, 30.0)
+    nx = dims[-1]
+    if ndim == 2:
+        rec = np.array([[x, 8] for x in range(3, nx - 3, 2)], dtype=np.int32)
+        src = (nx // 2, 12)
+    else:
+        rec = np.array([[x, y, 6] for x in range(2, nx - 2, 3) for y in range(2, dims[1] - 2, 3)], dtype=np.int32)
+        src = (nx // 2, 9, 9)
+    rho = np.random.default_rng(seed).standard_normal((nt, len(rec))).astype(np.float32)
+    ini = None
+    if init:
+        grids = np.meshgrid(*[np.arange(n) - n / 2 for n in dims], indexing="ij")
+        bump = np.exp(-sum(gq ** 2 for gq in grids) / 30.0).astype(np.float32)
+        ini = (0.9 * bump, bump)
+    return dict(vel=vel, h=h, dt=dt, nt=nt, nb=nb, eta=eta, vmax=vmax, sid=sid, wo=wo, wav=wav, rec=rec,
+                src=src, rho=rho, ini=ini, ndim=ndim, shape=shape, M=M)
+
+
+def run(F, c, ckpt, K=0, nsnap=0, param="velocity", final=False):
+    g = F.Grid(shape=c["vel"].shape, h=c["h"], dt=c["dt"], nt=c["nt"], nb=c["nb"], eta_max=c["eta"],
+               vmax=c["vmax"])
+    sh = F.Shot(stencil_id=c["sid"], src=c["src"], wavelet=torch.tensor(c["wav"].astype(np.float32), device=DEV),
+                rec=torch.tensor(c["rec"], device=DEV), traces=torch.zeros(c["nt"], len(c["rec"]), device=DEV),
+                trace_adj=torch.tensor(c["rho"], device=DEV))
+    if c["ini"] is not None:
+        sh.init = tuple(torch.tensor(a, device=DEV) for a in c["ini"])
+    if final:
+        sh.final = (torch.zeros(c["vel"].shape, device=DEV), torch.zeros(c["vel"].shape, device=DEV))
+    grad = torch.zeros(c["vel"].shape, device=DEV)
+    F.fd_adjoint_gradient(g, torch.tensor(c["vel"], device=DEV), [sh], K, grad, ckpt=ckpt, nsnap=nsnap,
+                          param=param)
+    torch.cuda.synchronize()
+    fin = tuple(t.cpu().numpy() for t in sh.final) if final else None
+    return grad.cpu().numpy(), sh.traces.cpu().numpy(), fin
+
+
+def oracle_grad(c, param):
+    st = rounded_stencil(c["ndim"], c["shape"], c["M"], c["wo"])
+    vel, dt, h = c["vel"], c["dt"], c["h"]
+    gc, _ = S.adjoint_gradient(st, v32(vel, dt, h), vel.astype(np.float64), dt, c["nt"], c["nb"], c["eta"],
+                               c["src"], q32(c["wav"], dt, h, c["ndim"]), c["rec"], c["rho"].astype(np.float64),
+                               init=None if c["ini"] is None else tuple(a.astype(np.float64) for a in c["ini"]))
+    return CK.gradient_param(gc, vel, param)
+
+
+@pytest.mark.parametrize("nsnap", [0, 1, 3, 9, 120])
+def test_revolve_equals_segments_bitwise_2d(F, nsnap):
+    c = case(F, 2, "cross", 4, nt=120, seed=2)
+    g0, t0, f0 = run(F, c, "segment", K=25, final=True)
+    g1, t1, f1 = run(F, c, "revolve", nsnap=nsnap, final=True)
+    assert np.array_equal(g0, g1)
+    assert np.array_equal(t0, t1)
+    assert np.array_equal(f0[0], f1[0]) and np.array_equal(f0[1], f1[1])
+
+
+@pytest.mark.parametrize("shape,M", [("rhombus", 3), ("square", 2)])
+def test_revolve_with_initial_state_and_dense_stencils(F, shape, M):
+    c = case(F, 2, shape, M, nt=90, seed=4, init=True)
+    g0, t0, _ = run(F, c, "segment", K=30)
+    g1, t1, _ = run(F, c, "revolve", nsnap=4)
+    assert np.array_equal(g0, g1) and np.array_equal(t0, t1)
+    assert rel_l2(g1, oracle_grad(c, "velocity")) <= 1e-3
+
+
+@pytest.mark.parametrize("shape,M", [("cross", 4), ("rhombus", 2)])
+def test_revolve_equals_segments_bitwise_3d(F, shape, M):
+    c = case(F, 3, shape, M, nt=70, seed=5)
+    g0, t0, _ = run(F, c, "segment", K=17)
+    g1, t1, _ = run(F, c, "revolve", nsnap=3)
+    assert np.array_equal(g0, g1) and np.array_equal(t0, t1)
+    assert rel_l2(g1, oracle_grad(c, "velocity")) <= 1e-3
+
+
+@pytest.mark.parametrize("param", ["slowness", "m"])
+@pytest.mark.parametrize("ckpt", ["segment", "revolve"])
+def test_parametrised_gradient_2d(F, param, ckpt):
+    c = case(F, 2, "cross", 4, nt=120, seed=7)
+    g, _, _ = run(F, c, ckpt, K=30, nsnap=5, param=param)
+    ref = oracle_grad(c, param)
+    assert rel_l2(g, ref) <= 1e-3
+    big = np.abs(ref) >= 0.1 * np.abs(ref).max()
+    assert np.all(np.abs(g[big] - ref[big]) <= 1e-3 * np.abs(ref[big]) + 1e-4 * np.abs(ref).max())
+
+
+@pytest.mark.parametrize("param", ["slowness", "m"])
+def test_parametrised_gradient_3d(F, param):
+    c = case(F, 3, "cross", 4, nt=70, seed=8)
+    g, _, _ = run(F, c, "revolve", nsnap=2, param=param)
+    assert rel_l2(g, oracle_grad(c, param)) <= 1e-3
+
+
+def test_parametrised_gradient_batched_and_revolve_multishot(F):
+    """Three shots with their own windows and stencils: the batched segment
+    adjoint (one launch per step for all shots) and the shot-after-shot
+    binomial adjoint give the same dJ/dm, which matches the oracle's."""
+    NZ, NX, h, nt, nb = 50, 120, 10.0, 100, 6
+    model = layered((NZ, NX), seed=12)
+    vmax = float(model.max())
+    dt = 0.5 * 0.45 * h / vmax
+    C = vmax * dt / h
+    eta = synth.sponge_eta_max(vmax, nb, h)
+    wav = synth.ricker(nt, dt, 30.0)
+    rng = np.random.default_rng(13)
+    specs = [(0, 0, 120, 50, "cross", 4, (60, 10)), (10, 4, 80, 44, "square", 2, (40, 9)),
+             (40, 0, 80, 46, "rhombus", 3, (30, 12))]
+    shots, gref = [], np.zeros((NZ, NX))
+    for ox, oz, ex, ez, shape, M, src in specs:
+        wo = oracle_weights(2, "dispte" if shape != "square" else "specls", shape, M, C)
+        sid = F.fd_weights_set(2, shape, M, wo)
+        rec = np.array([[x, 7] for x in range(2, ex - 2, 3)], dtype=np.int32)
+        rho = rng.standard_normal((nt, len(rec))).astype(np.float32)
+        shots.append(F.Shot(stencil_id=sid, src=src, wavelet=torch.tensor(wav.astype(np.float32), device=DEV),
+                            rec=torch.tensor(rec, device=DEV), traces=torch.zeros(nt, len(rec), device=DEV),
+                            trace_adj=torch.tensor(rho, device=DEV), origin=(ox, 0, oz), extent=(ex, 1, ez)))
+        crop = np.ascontiguousarray(model[oz:oz + ez, ox:ox + ex])
+        gi, _ = S.adjoint_gradient(rounded_stencil(2, shape, M, wo), v32(crop, dt, h), crop.astype(np.float64),
+                                   dt, nt, nb, eta, src, q32(wav, dt, h, 2), rec, rho.astype(np.float64))
+        gref[oz:oz + ez, ox:ox + ex] += CK.gradient_param(gi, crop, "m")
+    vel = torch.tensor(model, device=DEV)
+    g = F.Grid(shape=model.shape, h=h, dt=dt, nt=nt, nb=nb, eta_max=eta, vmax=vmax)
+    gb = torch.zeros(model.shape, device=DEV)
+    F.fd_adjoint_gradient(g, vel, shots, 20, gb, param="m")
+    gr = torch.zeros(model.shape, device=DEV)
+    F.fd_adjoint_gradient(g, vel, shots, 0, gr, ckpt="revolve", nsnap=3, param="m")
+    torch.cuda.synchronize()
+    gb, gr = gb.cpu().numpy(), gr.cpu().numpy()
+    assert rel_l2(gb, gr) <= 1e-5
+    assert rel_l2(gb, gref) <= 1e-3

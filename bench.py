@@ -74,10 +74,11 @@ def parse():
     ap.add_argument("--no-vol3d", action="store_true")
     ap.add_argument("--no-ragged", action="store_true")
     ap.add_argument("--no-dispersion", action="store_true")
+    ap.add_argument("--no-fwi3d", action="store_true")
     ap.add_argument("--vol3d-nt", type=int, default=1000)
     ap.add_argument("--ragged-nt", type=int, default=3000)
     ap.add_argument("--no-tune", action="store_true", help="skip the tile autotuner")
-    ap.add_argument("--only", choices=["2d", "vol3d", "ragged", "fwi", "copy"], default=None,
+    ap.add_argument("--only", choices=["2d", "vol3d", "ragged", "fwi", "fwi3d", "copy"], default=None,
                     help="run one workload alone (for profiling); no value line")
     ap.add_argument("--stencil", default=None,
                     help="--only 2d: run this stencil alone (e.g. specls-square-M8)")
@@ -117,6 +118,8 @@ def main():
             res = only_2d(torch, F, autotune, configs, design, dev, args)
         elif args.only == "vol3d":
             res = vol3d_bench(torch, F, design, configs, dev, args.vol3d_nt, not args.no_tune)
+        elif args.only == "fwi3d":
+            res = fwi3d_bench(torch, F, design, configs, dev, args.vol3d_nt)
         elif args.only == "ragged":
             res = ragged_bench(torch, F, design, configs, dev, args.ragged_nt)
         else:
@@ -233,6 +236,9 @@ def main():
     if not args.no_fwi:
         line["fwi"] = fwi_bench(torch, F, design, configs, dev)
         log("fwi done")
+    if not args.no_fwi3d:
+        line["fwi3d"] = fwi3d_bench(torch, F, design, configs, dev, args.vol3d_nt)
+        log("fwi3d done")
     if not args.no_dispersion:
         line["dispersion"] = dispersion_bench(torch, F, variants, w)
         log("dispersion done")
@@ -439,6 +445,65 @@ def fwi_bench(torch, F, design, configs, dev):
     return {"workload": w.name, "shots": len(shots), "nt": w.nt, "ckpt_every": K,
             "s_per_shot": round(t_fast, 5), "plain_s_per_shot": round(t_plain, 5),
             "speedup_vs_plain": round(t_plain / t_fast, 3), "grad_rel_diff_vs_plain": diff}
+
+
+def fwi3d_bench(torch, F, design, configs, dev, nt):
+    """3D FWI gradient: one shot on the 512^3 layered volume, 1000 steps,
+    DispTE cross M=4, 256 x 256 receivers, gradient in m = 1/c^2 of the
+    least-squares misfit against data from a 3 % faster model.  The forward
+    states cannot all be kept (1000 x 512 MiB); the adjoint runs with
+    segment checkpoints (K = 45: 93 fields, 46.5 GiB), with binomial
+    checkpoints in the same memory (44 snapshots) and in 10.5 GiB (8
+    snapshots).  Seconds per gradient against one plain forward run."""
+    w = configs.volume_3d(nt=nt)
+    model = configs.volume_3d_model(w)
+    vel = torch.tensor(model, device=dev)
+    vtrue = vel * 1.03
+    wav = torch.tensor(w.wavelet().astype(np.float32), device=dev)
+    rec = torch.tensor(w.rec.astype(np.int32), device=dev)
+    grid = F.Grid(shape=w.shape, h=w.h, dt=w.dt, nt=w.nt, nb=w.nb, eta_max=w.eta_max, vmax=w.c_max * 1.03)
+    sid = F.fd_weights_set(3, "cross", 4, design.weights(3, "dispte", "cross", 4, w.courant))
+    shot = F.Shot(stencil_id=sid, src=w.src, wavelet=wav, rec=rec, traces=torch.zeros(w.nt, len(w.rec), device=dev))
+    F.fd_forward(grid, vtrue, [shot])
+    dobs = shot.traces.clone()
+    del vtrue
+    F.fd_forward(grid, vel, [shot])
+    torch.cuda.synchronize()
+    ms_fwd = _event_time(torch, lambda: F.fd_forward(grid, vel, [shot]))
+    shot.trace_adj = (shot.traces - dobs).contiguous()
+    npts = int(np.prod(w.shape))
+    field_gib = npts * 4 / 2 ** 30
+    out = {"workload": w.name + "-fwi", "nt": w.nt, "param": "m", "forward_ms": round(ms_fwd, 1), "runs": []}
+    ref = None
+    for name, ckpt, K, nsnap in [("segment K=45", "segment", 45, 0), ("revolve 44 snapshots", "revolve", 0, 44),
+                                 ("revolve 8 snapshots", "revolve", 0, 8)]:
+        nbytes = F.fd_adjoint_workspace_bytes(grid, [shot], ckpt=ckpt, ckpt_every=max(K, 1), nsnap=nsnap, param="m")
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        grad = torch.zeros(w.shape, device=dev)
+        F.fd_adjoint_gradient(grid, vel, [shot], K, grad, ws=ws, ckpt=ckpt, nsnap=nsnap, param="m")   # capture
+        torch.cuda.synchronize()
+
+        def run():
+            grad.zero_()
+            F.fd_adjoint_gradient(grid, vel, [shot], K, grad, ws=ws, ckpt=ckpt, nsnap=nsnap, param="m")
+
+        ms = _event_time(torch, run)
+        # segments: the first pass plus every segment but the last once more
+        steps = (w.nt + (-(-w.nt // K) - 1) * K) if ckpt == "segment" else F.fd_revolve_plan(w.nt, nsnap)[1]
+        out["runs"].append({"scheme": name, "s_per_gradient": round(ms * 1e-3, 3),
+                            "vs_forward": round(ms / ms_fwd, 2), "forward_steps": steps,
+                            "workspace_gib": round(nbytes / 2 ** 30, 1),
+                            "adjoint_ms_per_step_est": round((ms - steps * ms_fwd / w.nt) / w.nt, 3)})
+        if ref is None:
+            ref = grad.clone()
+        else:
+            out["runs"][-1]["bitwise_equal_to_segment"] = bool(torch.equal(ref, grad))
+        del ws
+        log(f"fwi3d {name} done")
+    out["field_gib"] = round(field_gib, 3)
+    del vel
+    torch.cuda.empty_cache()
+    return out
 
 
 def dispersion_bench(torch, F, variants, w, nscale=64):

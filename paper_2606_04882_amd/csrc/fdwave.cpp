@@ -959,25 +959,43 @@ struct RevolvePlanner {
     }
 };
 
-// Adjoint of one shot under a binomial plan.  Snapshot j holds two fields
-// at ckpt + 2 j n; the current state (P, C) = (u^{k-1}, u^k) lives in
-// snapshots, the initial data or the working fields W0, W1 (a step writes
-// over P only when P is a working field).  An ADVANCE followed by STORE j
-// writes its last two levels straight into snapshot j.  Traces are written
-// the first time a step runs (the first pass runs every step in order).
+// Adjoint of one shot under a binomial plan.  The forward fields live in a
+// pool of 2 nsnap + 2 window fields (the snapshot region and W0, W1);
+// a snapshot is a pair of references into the pool (or to the initial data),
+// so STORE copies nothing.  A step writes u^{k+1} over u^{k-1} when no live
+// snapshot references that field, else into a pool field referenced by
+// neither a snapshot nor the current state: at most 2 nsnap fields are
+// referenced by snapshots and one more by the current state, so one is
+// always free.  Traces are written the first time a step runs (the first
+// pass runs every step in order).
 int enqueue_adjoint_revolve(const CallCtx& c, const ShotCtx& s, Recorder& R) {
     hipStream_t st = R.stream;
-    const int nt = c.g->nt, nrec = s.s->nrec;
+    const int nt = c.g->nt, nrec = s.s->nrec, nsnap = c.K;
     const long long n = s.npts;
     float* ckpt = (float*)(c.ws + c.L.ckpt);
     float* W0 = (float*)(c.ws + c.L.seg);
-    float* W1 = W0 + n;
     float* Z = W0 + 2 * n;
     float* pa = (float*)(c.ws + c.L.psiA);
     float* pb = (float*)(c.ws + c.L.psiB);
     RevolvePlanner planner;
-    planner.plan(nt, c.K);
+    planner.plan(nt, nsnap);
     const std::vector<int>& ops = planner.ops;
+
+    // pool field i: the snapshot region for i < 2 nsnap, then W0, W1
+    const int npool = 2 * nsnap + 2;
+    auto field = [&](int i) { return i < 2 * nsnap ? ckpt + (size_t)i * n : W0 + (size_t)(i - 2 * nsnap) * n; };
+    auto index = [&](const float* f) -> int {
+        for (int i = 0; i < npool; ++i)
+            if (field(i) == f) return i;
+        return -1;   // initial data or the zero field
+    };
+    std::vector<int> pins(npool, 0);
+    std::vector<const float*> snap_p(std::max(nsnap, 1), nullptr), snap_c(std::max(nsnap, 1), nullptr);
+    std::vector<int> snap_step(std::max(nsnap, 1), 0);
+    auto pin = [&](const float* f, int d) {
+        const int i = index(f);
+        if (i >= 0) pins[i] += d;
+    };
 
     launch_rec_index(s.s->rec, nrec, c.g->ndim, s.nx, s.ny, s.nz, s.rec, c.flags, st);
     R.launched();
@@ -987,12 +1005,9 @@ int enqueue_adjoint_revolve(const CallCtx& c, const ShotCtx& s, Recorder& R) {
     }
     const float* init_p = s.s->init_prev ? s.s->init_prev : Z;
     const float* init_c = s.s->init_cur ? s.s->init_cur : Z;
-    auto snapP = [&](int j) { return ckpt + (size_t)j * 2 * n; };
-    auto snapC = [&](int j) { return ckpt + (size_t)j * 2 * n + n; };
     const float* P = init_p;
     const float* C = init_c;
     int cur = 0, hi = 0;
-    std::vector<int> slot_step(std::max(c.K, 1), 0);
     StepArgs f = base_step(c, s);
     launch_fill(pa, n, 0.f, st);   // psi^{nt+1}
     launch_fill(pb, n, 0.f, st);   // psi^{nt+2}
@@ -1003,17 +1018,13 @@ int enqueue_adjoint_revolve(const CallCtx& c, const ShotCtx& s, Recorder& R) {
     for (size_t i = 0; i < ops.size(); i += 2) {
         const int op = ops[i], arg = ops[i + 1];
         if (op == FD_OP_ADVANCE) {
-            const int tgt = (i + 2 < ops.size() && ops[i + 2] == FD_OP_STORE) ? ops[i + 3] : -1;
-            if (tgt >= 0 && arg == cur + 1) {   // u^{arg-1} is C: copy it into the snapshot
-                launch_copy(snapP(tgt), C, n, st);
-                R.launched();
-            }
             while (cur < arg) {
-                float* D;
-                if (tgt >= 0 && cur + 1 == arg - 1) D = snapP(tgt);
-                else if (tgt >= 0 && cur + 1 == arg) D = snapC(tgt);
-                else if (P == W0 || P == W1) D = (float*)P;
-                else D = C == W0 ? W1 : W0;
+                const int ip = index(P), ic = index(C);
+                int id = (ip >= 0 && pins[ip] == 0) ? ip : -1;
+                for (int j = 0; j < npool && id < 0; ++j)
+                    if (pins[j] == 0 && j != ip && j != ic) id = j;
+                if (id < 0) return fail(FD_EDEVICE, "binomial adjoint: no free field (internal error)");
+                float* D = field(id);
                 f.ucur = C;
                 f.uprev = P;
                 f.unext = D;
@@ -1035,18 +1046,19 @@ int enqueue_adjoint_revolve(const CallCtx& c, const ShotCtx& s, Recorder& R) {
                 }
             }
         } else if (op == FD_OP_STORE) {
-            if (P != snapP(arg) || C != snapC(arg)) {
-                launch_copy(snapP(arg), P, n, st);
-                launch_copy(snapC(arg), C, n, st);
-                R.launched(2);
-                P = snapP(arg);
-                C = snapC(arg);
+            if (snap_p[arg]) {
+                pin(snap_p[arg], -1);
+                pin(snap_c[arg], -1);
             }
-            slot_step[arg] = cur;
+            snap_p[arg] = P;
+            snap_c[arg] = C;
+            snap_step[arg] = cur;
+            pin(P, 1);
+            pin(C, 1);
         } else if (op == FD_OP_RESTORE) {
-            P = arg < 0 ? init_p : snapP(arg);
-            C = arg < 0 ? init_c : snapC(arg);
-            cur = arg < 0 ? 0 : slot_step[arg];
+            P = arg < 0 ? init_p : snap_p[arg];
+            C = arg < 0 ? init_c : snap_c[arg];
+            cur = arg < 0 ? 0 : snap_step[arg];
         } else {   // FD_OP_ADJOINT: psi^k from psi^{k+1}, psi^{k+2}; gradient with u^k
             a.pcur = pcur;
             a.pprev = pprev;

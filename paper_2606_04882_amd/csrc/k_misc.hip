@@ -44,6 +44,19 @@ __global__ void k_copy(float* __restrict__ dst, const float* __restrict__ src, l
         dst[i] = src[i];
 }
 
+// 16-byte accesses for fields whose pointers are 16-byte aligned
+__global__ void k_copy4(float4* __restrict__ dst, const float4* __restrict__ src, long long n4) {
+    for (long long i = blockIdx.x * (long long)kBlock + threadIdx.x; i < n4;
+         i += (long long)gridDim.x * kBlock)
+        dst[i] = src[i];
+}
+
+__global__ void k_fill4(float4* __restrict__ p, long long n4, float val) {
+    for (long long i = blockIdx.x * (long long)kBlock + threadIdx.x; i < n4;
+         i += (long long)gridDim.x * kBlock)
+        p[i] = make_float4(val, val, val, val);
+}
+
 // window coordinates (x[, y], z) -> linear window index, or -1 (flagged)
 __global__ void k_rec_index(const int* __restrict__ rec, int nrec, int ndim, int nx, int ny,
                             int nz, long long* __restrict__ lin, int* __restrict__ flags) {
@@ -123,13 +136,27 @@ void launch_vprep(const float* vel, float* v, long long n, double dt_over_h, int
     hipLaunchKernelGGL(k_vprep, dim3(grid_for(n)), dim3(kBlock), 0, s, vel, v, n, dt_over_h, flags);
 }
 void launch_fill(float* p, long long n, float val, hipStream_t s) {
-    if (n > 0) hipLaunchKernelGGL(k_fill, dim3(grid_for(n)), dim3(kBlock), 0, s, p, n, val);
+    if (n <= 0) return;
+    long long head = 0;
+    if (((uintptr_t)p & 15) == 0 && n >= 4) {
+        head = n & ~3LL;
+        hipLaunchKernelGGL(k_fill4, dim3(grid_for(head / 4)), dim3(kBlock), 0, s, (float4*)p, head / 4, val);
+    }
+    if (head < n) hipLaunchKernelGGL(k_fill, dim3(grid_for(n - head)), dim3(kBlock), 0, s, p + head, n - head, val);
 }
 void launch_fill_i32(int* p, long long n, int val, hipStream_t s) {
     if (n > 0) hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(n)), dim3(kBlock), 0, s, p, n, val);
 }
 void launch_copy(float* dst, const float* src, long long n, hipStream_t s) {
-    if (n > 0) hipLaunchKernelGGL(k_copy, dim3(grid_for(n)), dim3(kBlock), 0, s, dst, src, n);
+    if (n <= 0) return;
+    long long head = 0;
+    if ((((uintptr_t)dst | (uintptr_t)src) & 15) == 0 && n >= 4) {
+        head = n & ~3LL;
+        hipLaunchKernelGGL(k_copy4, dim3(grid_for(head / 4)), dim3(kBlock), 0, s, (float4*)dst,
+                           (const float4*)src, head / 4);
+    }
+    if (head < n)
+        hipLaunchKernelGGL(k_copy, dim3(grid_for(n - head)), dim3(kBlock), 0, s, dst + head, src + head, n - head);
 }
 void launch_rec_index(const int* rec, int nrec, int ndim, int nx, int ny, int nz,
                       long long* lin, int* flags, hipStream_t s) {

@@ -2,8 +2,8 @@
 
 forward(vel) runs fd_forward for every shot and returns the traces stacked
 as [nshots, nt, nrec]; backward(dJ/dtraces) runs fd_adjoint_gradient (exact
-discrete adjoint with checkpoints every `ckpt_every` steps) and returns
-dJ/dc.  With the L2 misfit J = 1/2 ||d - d_obs||^2 computed in torch, the
+discrete adjoint; checkpoints every `ckpt_every` steps, or the binomial plan
+with `nsnap` snapshots when ckpt == "revolve") and returns dJ/dc.  With the L2 misfit J = 1/2 ||d - d_obs||^2 computed in torch, the
 incoming gradient is d - d_obs.  The FWI use of the stencils is the one the
 paper points to in its conclusions (Sec. 7).
 """
@@ -26,6 +26,8 @@ class Survey:
     wavelet: torch.Tensor          # [nt] float32 on the device
     rec: torch.Tensor              # [nrec, ndim] int32 on the device
     ckpt_every: int = 100
+    ckpt: str = "segment"          # or "revolve" (binomial, nsnap snapshots)
+    nsnap: int = 0
 
     def shots(self, traces: torch.Tensor = None, adj: torch.Tensor = None) -> List[F.Shot]:
         out = []
@@ -54,7 +56,8 @@ class WaveOp(torch.autograd.Function):
         adj = grad_traces.detach().to(torch.float32).contiguous()
         scratch = torch.zeros_like(adj)      # traces are recomputed by the adjoint run
         grad = torch.zeros_like(vel)
-        F.fd_adjoint_gradient(survey.grid, vel, survey.shots(scratch, adj), survey.ckpt_every, grad)
+        F.fd_adjoint_gradient(survey.grid, vel, survey.shots(scratch, adj), survey.ckpt_every, grad,
+                              ckpt=survey.ckpt, nsnap=survey.nsnap)
         return grad, None
 
 

@@ -307,7 +307,10 @@ const char* fd_last_error(void);
  *     f_j = j / (nt dt), j = 1..nscale, s_j = (w0 + sqrt(2 + w0^2)) / (4 pi f_j).
  * Amplitudes are sqrt(Re^2 + Im^2); phases atan2(Im, Re) in (-pi, pi]; the
  * phase difference is moved into (-pi, pi] by +-2 pi.  Transforms in FP64.
- *   num, ref    [dev] nt*nrec traces, num[n*nrec + r] (the fd_shot.traces layout)
+ *   num, ref    [dev] traces: row n (time) of num starts at num + n*ld_num and
+ *               holds nrec receivers (ld_num = nrec for the fd_shot.traces
+ *               layout; a larger stride reads every k-th row of a finer
+ *               run's traces in place); likewise ref with ld_ref (>= nrec)
  *   dt          sample interval (s); used by the CWT
  *   nscale      number of CWT scales (0: no CWT), <= nt/2
  *   omega0      Morlet centre frequency (the usual choice is 6)
@@ -323,9 +326,29 @@ const char* fd_last_error(void);
  * Asynchronous on hip_stream.  Errors: FD_EINVAL, FD_ENOMEM, FD_EDEVICE.
  */
 size_t fd_dispersion_workspace_bytes(int nt, int nrec, int nscale);
-int fd_dispersion(const float* num, const float* ref, int nt, int nrec, double dt, int nscale,
-                  double omega0, float* gamma_dft, double* norm_dft, double* norm_cwt, void* workspace,
-                  size_t ws_bytes, void* hip_stream);
+int fd_dispersion(const float* num, long long ld_num, const float* ref, long long ld_ref, int nt, int nrec,
+                  double dt, int nscale, double omega0, float* gamma_dft, double* norm_dft, double* norm_cwt,
+                  void* workspace, size_t ws_bytes, void* hip_stream);
+
+/*
+ * Error norms of Sec. 6.1.1 between a numerical solution and a reference
+ * read through strides (e.g. a run on a grid refined r times, sampled on the
+ * coarse nodes and times without a copy):
+ *   e(i, j, k) = num[i sn[0] + j sn[1] + k sn[2]] - ref[i sr[0] + j sr[1] + k sr[2]]
+ * over the box 0 <= i < n[0], 0 <= j < n[1], 0 <= k < n[2] (element strides,
+ * any sign; unused axes have extent 1).
+ *   num, ref    [dev] float32
+ *   num_stride, ref_stride, n  [host] 3 values each
+ *   out         [dev, out] 3 doubles: sum |e|, sum e^2, max |e| (FP64
+ *               accumulation, a fixed reduction order: repeatable); the
+ *               paper's L1 = out[0] / h^2, L2 = sqrt(out[1]) / h, Linf = out[2]
+ *               (tau for h on traces) are the caller's
+ *   workspace   [dev] >= FD_ERROR_NORMS_WS_BYTES bytes, 256-byte aligned
+ * Asynchronous on hip_stream.  Errors: FD_EINVAL, FD_ENOMEM, FD_EDEVICE.
+ */
+#define FD_ERROR_NORMS_WS_BYTES 24576
+int fd_error_norms(const float* num, const long long* num_stride, const float* ref, const long long* ref_stride,
+                   const long long* n, double* out, void* workspace, size_t ws_bytes, void* hip_stream);
 
 #ifdef __cplusplus
 }

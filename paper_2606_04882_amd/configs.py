@@ -159,3 +159,59 @@ def fwi_models(w: Workload) -> Tuple[np.ndarray, np.ndarray]:
     true = synth.gaussian_anomalies(base, 4, 55)
     start = synth._smooth(true, 15.0)
     return true.astype(np.float32), start.astype(np.float32)
+
+
+# --------------------------------------------------------------------------
+# Reference-solution study (Sec. 6.2 homogeneous and two-layer tests)
+# --------------------------------------------------------------------------
+def study_workload(name: str, L: float, n_cells: int, dt: float, nt: int, f0: float, c_max: float, src_m,
+                   trace_m, snap_t: float, refine: int, model: str, nb_cells: int = 40) -> Workload:
+    """A square study model of side L (m) with n_cells coarse cells, refined
+    r times (h / r, dt / r, r nt steps; the sponge keeps its physical width
+    of nb_cells coarse cells); receivers on every coarse node of the line
+    z = trace_m[1] between the sponges, the trace receiver at x = trace_m[0]."""
+    r = int(refine)
+    h = L / n_cells
+    nb = nb_cells * r
+    n = n_cells * r + 1
+    zline = int(round(trace_m[1] / h))
+    xs = np.arange(nb_cells, n_cells - nb_cells + 1)
+    rec = np.stack([xs * r, np.full_like(xs, zline * r)], axis=1).astype(np.int32)
+    return Workload(name=f"{name}-{n_cells + 1}^2" + (f"-refined{r}" if r > 1 else ""), ndim=2, shape=(n, n),
+                    h=h / r, dt=dt / r, nt=nt * r, f0=f0, nb=nb, c_max=c_max, stencils=[],
+                    src=(int(round(src_m[0] / h)) * r, int(round(src_m[1] / h)) * r), rec=rec,
+                    eta_max=synth.sponge_eta_max(c_max, nb, h / r), seed=0,
+                    extra={"refine": r, "model": model, "trace_rec": int(round(trace_m[0] / h)) - nb_cells,
+                           "snap_step": int(round(snap_t / dt)) * r, "coarse_cells": n_cells, "L": L})
+
+
+def study_homogeneous(refine: int = 1) -> Workload:
+    """Homogeneous test of Sec. 6.2: 6000 m x 6000 m, h = 15 m (401^2 nodes),
+    dt = 2 ms, t_F = 1.5 s (750 steps; the table's nt = 1500 contradicts
+    t_F / dt), 30 Hz Ricker at the centre, c = 3000 m/s; 40-cell sponge;
+    trace at (x, z) = (1200, 3000) m among a receiver line on z = 3000 m
+    (x = 600 .. 5400 m, every node); snapshot at 1.05 s.  refine = r gives
+    the reference grid: h / r, dt / r, r nt steps, node r i for coarse node i."""
+    return study_workload("study-homogeneous", 6000.0, 400, 2e-3, 750, 30.0, 3000.0, (3000.0, 3000.0),
+                  (1200.0, 3000.0), 1.05, refine, "homogeneous")
+
+
+def study_two_layer(refine: int = 1) -> Workload:
+    """Two-layer test of Sec. 6.3: 4000 m x 4000 m, h = 10 m (401^2 nodes),
+    dt = 1 ms, 1500 steps, 25 Hz Ricker at (2000, 1600) m; c = 1500 m/s for
+    z <= 1200 m and 3000 m/s below; 40-cell sponge; trace at (1000, 2000) m
+    among a receiver line on z = 2000 m; snapshot at 1.08 s."""
+    return study_workload("study-two-layer", 4000.0, 400, 1e-3, 1500, 25.0, 3000.0, (2000.0, 1600.0),
+                  (1000.0, 2000.0), 1.08, refine, "two_layer")
+
+
+def study_model(w: Workload) -> np.ndarray:
+    """Velocity on the workload's nodes, from physical coordinates (so the
+    refined grid sees the same interface)."""
+    nz, nx = w.shape
+    if w.extra["model"] == "homogeneous":
+        return np.full((nz, nx), 3000.0, dtype=np.float32)
+    z = np.arange(nz) * w.h
+    zi = w.extra.get("interface_m", 1200.0)
+    c = np.where(z <= zi + 1e-9, 1500.0, 3000.0).astype(np.float32)
+    return np.repeat(c[:, None], nx, axis=1)

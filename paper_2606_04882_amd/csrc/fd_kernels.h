@@ -307,7 +307,12 @@ enum { FLAG_BAD_REC = 0, FLAG_NONFINITE = 1, FLAG_BAD_VEL = 2, FLAG_COUNT = 4 };
 
 // Dispersion metrics (k_disp.hip).  Half spectra are double2 [rc][nt/2+1],
 // CWT fields double2 [rc][ns][nt].
-void launch_rows_f64(const float* in, double* out, int nt, int nrec, int r0, int rc, hipStream_t s);
+void launch_rows_f64(const float* in, long long ld, double* out, int nt, int r0, int rc, hipStream_t s);
+// (sum |e|, sum e^2, max |e|) of e = num - ref over an n[0] x n[1] x n[2]
+// box of strided views into out[3] (device); partial holds 3 nblocks doubles
+constexpr int kNormBlocks = 1024;
+void launch_error_norms(const float* num, const long long* sn, const float* ref, const long long* sr,
+                        const long long* n, double* partial, int nblocks, double* out, hipStream_t s);
 void launch_gamma_dft(const void* A, const void* B, int nt, int rc, float* gamma, long long ldg, double* norm,
                       hipStream_t s);
 void launch_cwt_spectra(const void* A, int nt, int rc, int ns, double dt, double omega0, void* W, hipStream_t s);

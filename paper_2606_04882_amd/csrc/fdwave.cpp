@@ -1917,17 +1917,35 @@ int fd_revolve_plan(int nt, int nsnap, int* ops, long long max_ops, long long* n
     return FD_OK;
 }
 
+int fd_error_norms(const float* num, const long long* num_stride, const float* ref, const long long* ref_stride,
+                   const long long* n, double* out, void* workspace, size_t ws_bytes, void* hip_stream) {
+    g_err.clear();
+    if (!num || !ref || !num_stride || !ref_stride || !n || !out)
+        return fail(FD_EINVAL, "num, ref, strides, n and out are required");
+    for (int a = 0; a < 3; ++a)
+        if (n[a] < 1) return fail(FD_EINVAL, "box extents must be >= 1");
+    if (!workspace || ws_bytes < FD_ERROR_NORMS_WS_BYTES)
+        return fail(FD_ENOMEM, "workspace must hold %d bytes", FD_ERROR_NORMS_WS_BYTES);
+    if ((uintptr_t)workspace % 256) return fail(FD_EINVAL, "workspace must be 256-byte aligned");
+    const long long total = n[0] * n[1] * n[2];
+    const int nb = (int)std::min<long long>(kNormBlocks, (total + 255) / 256);
+    launch_error_norms(num, num_stride, ref, ref_stride, n, (double*)workspace, nb, out, (hipStream_t)hip_stream);
+    HIP_OK(hipGetLastError());
+    return FD_OK;
+}
+
 size_t fd_dispersion_workspace_bytes(int nt, int nrec, int nscale) {
     if (nt < 2 || nrec < 1 || nscale < 0) return 0;
     return disp_layout(nt, nrec, nscale).total;
 }
 
-int fd_dispersion(const float* num, const float* ref, int nt, int nrec, double dt, int nscale,
-                  double omega0, float* gamma_dft, double* norm_dft, double* norm_cwt, void* workspace,
-                  size_t ws_bytes, void* hip_stream) {
+int fd_dispersion(const float* num, long long ld_num, const float* ref, long long ld_ref, int nt, int nrec,
+                  double dt, int nscale, double omega0, float* gamma_dft, double* norm_dft, double* norm_cwt,
+                  void* workspace, size_t ws_bytes, void* hip_stream) {
     g_err.clear();
     if (!num || !ref || !norm_dft) return fail(FD_EINVAL, "num, ref and norm_dft are required");
     if (nt < 2 || nrec < 1) return fail(FD_EINVAL, "need nt >= 2 and nrec >= 1");
+    if (ld_num < nrec || ld_ref < nrec) return fail(FD_EINVAL, "row strides must be >= nrec");
     if (nscale < 0 || nscale > nt / 2) return fail(FD_EINVAL, "nscale must be in [0, nt/2]");
     if (norm_cwt && (nscale < 1 || !(dt > 0) || !(omega0 > 0)))
         return fail(FD_EINVAL, "the CWT norm needs nscale >= 1, dt > 0 and omega0 > 0");
@@ -1944,8 +1962,8 @@ int fd_dispersion(const float* num, const float* ref, int nt, int nrec, double d
         FftPlan* fwd = nullptr;
         int rc2 = fft_plan(0, (size_t)nt, (size_t)rc, &fwd);
         if (rc2) return rc2;
-        launch_rows_f64(num, (double*)(ws + L.xa), nt, nrec, r0, rc, st);
-        launch_rows_f64(ref, (double*)(ws + L.xb), nt, nrec, r0, rc, st);
+        launch_rows_f64(num, ld_num, (double*)(ws + L.xa), nt, r0, rc, st);
+        launch_rows_f64(ref, ld_ref, (double*)(ws + L.xb), nt, r0, rc, st);
         if ((rc2 = fft_run(fwd, ws + L.xa, ws + L.fa, st))) return rc2;
         if ((rc2 = fft_run(fwd, ws + L.xb, ws + L.fb, st))) return rc2;
         launch_gamma_dft(ws + L.fa, ws + L.fb, nt, rc, gamma_dft ? gamma_dft + (long long)r0 * nt : nullptr,

@@ -11,7 +11,10 @@
 // on the positive frequencies (H removes the rest), rocFFT's unnormalised
 // inverse transform gives W_n(s_j), and k_gamma_cwt reduces
 // gamma^W = wrap(phi_num - phi_ref)/pi |W_num|/max|W_num| to its norm.
-// Amplitudes are sqrt(Re^2 + Im^2), phases atan2(Im, Re).
+// Amplitudes are sqrt(Re^2 + Im^2), phases atan2(Im, Re).  Trace rows are
+// read with a row stride, so a finer run's traces can be sampled in place.
+// Also here: the error norms of a numerical field or trace against a
+// reference read through strides (Sec. 6.1.1).
 #include "fd_kernels.h"
 
 namespace fdw {
@@ -20,15 +23,15 @@ namespace {
 
 constexpr int kT = 32;   // transpose tile
 
-// out[r - r0][n] = (double) in[n * nrec + r] for r in [r0, r0 + rc)
-__global__ void k_rows_f64(const float* __restrict__ in, double* __restrict__ out, int nt, int nrec,
+// out[r - r0][n] = (double) in[n * ld + r] for r in [r0, r0 + rc)
+__global__ void k_rows_f64(const float* __restrict__ in, double* __restrict__ out, int nt, long long ld,
                            int r0, int rc) {
     __shared__ float t[kT][kT + 1];
     const int n0 = blockIdx.x * kT, rr0 = blockIdx.y * kT;
     const int tx = threadIdx.x, ty = threadIdx.y;   // 32 x 8 threads
     for (int i = ty; i < kT; i += 8) {
         const int n = n0 + i, r = rr0 + tx;
-        t[i][tx] = (n < nt && r < rc) ? in[(long long)n * nrec + r0 + r] : 0.f;
+        t[i][tx] = (n < nt && r < rc) ? in[(long long)n * ld + r0 + r] : 0.f;
     }
     __syncthreads();
     for (int i = ty; i < kT; i += 8) {
@@ -138,11 +141,69 @@ __global__ __launch_bounds__(256) void k_gamma_cwt(const double2* __restrict__ W
     if (threadIdx.x == 0) norm[r] = sqrt(s2 / (double)per);
 }
 
+// Error norms (Sec. 6.1.1) between two strided views of one box: element
+// (i, j, k) of num at i sn[0] + j sn[1] + k sn[2], of ref likewise with sr.
+// Each block writes (sum |e|, sum e^2, max |e|) to partial[3 b .. 3 b + 2];
+// one block then reduces the partials in a fixed order (deterministic).
+struct Box3 {
+    long long n[3], sn[3], sr[3];
+};
+
+__global__ __launch_bounds__(256) void k_error_partials(const float* __restrict__ num, const float* __restrict__ ref,
+                                                        Box3 b, double* __restrict__ partial) {
+    __shared__ double sh[256];
+    const long long total = b.n[0] * b.n[1] * b.n[2];
+    double s1 = 0.0, s2 = 0.0, mx = 0.0;
+    for (long long t = blockIdx.x * 256LL + threadIdx.x; t < total; t += (long long)gridDim.x * 256) {
+        const long long i = t % b.n[0], jk = t / b.n[0];
+        const long long j = jk % b.n[1], k = jk / b.n[1];
+        const double e = (double)num[i * b.sn[0] + j * b.sn[1] + k * b.sn[2]] -
+                         (double)ref[i * b.sr[0] + j * b.sr[1] + k * b.sr[2]];
+        s1 += fabs(e);
+        s2 += e * e;
+        mx = fmax(mx, fabs(e));
+    }
+    s1 = block_sum(s1, sh);
+    s2 = block_sum(s2, sh);
+    mx = block_max(mx, sh);
+    if (threadIdx.x == 0) {
+        partial[3 * blockIdx.x] = s1;
+        partial[3 * blockIdx.x + 1] = s2;
+        partial[3 * blockIdx.x + 2] = mx;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_error_final(const double* __restrict__ partial, int nblocks,
+                                                     double* __restrict__ out) {
+    __shared__ double sh[256];
+    double s1 = 0.0, s2 = 0.0, mx = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += 256) {
+        s1 += partial[3 * b];
+        s2 += partial[3 * b + 1];
+        mx = fmax(mx, partial[3 * b + 2]);
+    }
+    s1 = block_sum(s1, sh);
+    s2 = block_sum(s2, sh);
+    mx = block_max(mx, sh);
+    if (threadIdx.x == 0) {
+        out[0] = s1;
+        out[1] = s2;
+        out[2] = mx;
+    }
+}
+
 }  // namespace
 
-void launch_rows_f64(const float* in, double* out, int nt, int nrec, int r0, int rc, hipStream_t s) {
+void launch_rows_f64(const float* in, long long ld, double* out, int nt, int r0, int rc, hipStream_t s) {
     dim3 grid((nt + kT - 1) / kT, (rc + kT - 1) / kT);
-    hipLaunchKernelGGL(k_rows_f64, grid, dim3(kT, 8), 0, s, in, out, nt, nrec, r0, rc);
+    hipLaunchKernelGGL(k_rows_f64, grid, dim3(kT, 8), 0, s, in, out, nt, ld, r0, rc);
+}
+
+void launch_error_norms(const float* num, const long long* sn, const float* ref, const long long* sr,
+                        const long long* n, double* partial, int nblocks, double* out, hipStream_t s) {
+    const Box3 b{{n[0], n[1], n[2]}, {sn[0], sn[1], sn[2]}, {sr[0], sr[1], sr[2]}};
+    hipLaunchKernelGGL(k_error_partials, dim3(nblocks), dim3(256), 0, s, num, ref, b, partial);
+    hipLaunchKernelGGL(k_error_final, dim3(1), dim3(256), 0, s, partial, nblocks, out);
 }
 
 void launch_gamma_dft(const void* A, const void* B, int nt, int rc, float* gamma, long long ldg, double* norm,

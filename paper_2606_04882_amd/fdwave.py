@@ -99,9 +99,13 @@ def _load() -> ctypes.CDLL:
                                     P(ctypes.c_longlong), P(ctypes.c_longlong)]
     lib.fd_dispersion_workspace_bytes.restype = ctypes.c_size_t
     lib.fd_dispersion_workspace_bytes.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int]
-    lib.fd_dispersion.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_double,
-                                  ctypes.c_int, ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p,
-                                  ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
+    lib.fd_dispersion.argtypes = [ctypes.c_void_p, ctypes.c_longlong, ctypes.c_void_p, ctypes.c_longlong,
+                                  ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_double,
+                                  ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                  ctypes.c_size_t, ctypes.c_void_p]
+    lib.fd_error_norms.argtypes = [ctypes.c_void_p, P(ctypes.c_longlong), ctypes.c_void_p, P(ctypes.c_longlong),
+                                   P(ctypes.c_longlong), ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                                   ctypes.c_void_p]
     return lib
 
 
@@ -342,13 +346,24 @@ def fd_revolve_plan(nt: int, nsnap: int):
 # ---------------------------------------------------------------------------
 # dispersion metrics
 # ---------------------------------------------------------------------------
+def _rows(t: torch.Tensor, name: str) -> int:
+    """Row stride of a [nt, nrec] view whose rows are dense."""
+    if t.dtype != torch.float32 or not t.is_cuda:
+        raise ValueError(f"{name} must be a float32 GPU tensor")
+    if t.shape[1] > 1 and t.stride(1) != 1:
+        raise ValueError(f"{name} rows must be dense (stride 1 along receivers)")
+    return int(t.stride(0))
+
+
 def fd_dispersion(num: torch.Tensor, ref: torch.Tensor, dt: float = 0.0, nscale: int = 0, omega0: float = 6.0,
                   gamma: bool = False) -> dict:
     """Appendix A metrics between traces num and ref ([nt, nrec] float32 on
-    the GPU): {"norm_dft": [nrec], "norm_cwt": [nrec] (nscale > 0),
+    the GPU; views with any row stride, e.g. fine[r-1::r], are read in
+    place): {"norm_dft": [nrec], "norm_cwt": [nrec] (nscale > 0),
     "gamma_dft": [nrec, nt] (gamma=True)} as float64 / float32 tensors."""
     if num.shape != ref.shape or num.dim() != 2:
         raise ValueError("num and ref must be [nt, nrec] of the same shape")
+    ld_num, ld_ref = _rows(num, "num"), _rows(ref, "ref")
     nt, nrec = int(num.shape[0]), int(num.shape[1])
     dev = num.device
     out = {"norm_dft": torch.zeros(nrec, dtype=torch.float64, device=dev)}
@@ -360,8 +375,34 @@ def fd_dispersion(num: torch.Tensor, ref: torch.Tensor, dt: float = 0.0, nscale:
     ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
     base = ws.data_ptr()
     aligned = (base + 255) // 256 * 256
-    num_c, ref_c = num.contiguous(), ref.contiguous()
-    _check(_lib.fd_dispersion(_ptr(num_c), _ptr(ref_c), nt, nrec, float(dt), nscale, float(omega0),
-                              _ptr(out.get("gamma_dft")), _ptr(out["norm_dft"]), _ptr(out.get("norm_cwt")),
-                              aligned, nbytes, _stream_handle(dev)))
+    _check(_lib.fd_dispersion(num.data_ptr(), max(ld_num, nrec), ref.data_ptr(), max(ld_ref, nrec), nt, nrec,
+                              float(dt), nscale, float(omega0), _ptr(out.get("gamma_dft")), _ptr(out["norm_dft"]),
+                              _ptr(out.get("norm_cwt")), aligned, nbytes, _stream_handle(dev)))
+    return out
+
+
+FD_ERROR_NORMS_WS_BYTES = 24576
+
+
+def fd_error_norms(num: torch.Tensor, ref: torch.Tensor) -> torch.Tensor:
+    """(sum |e|, sum e^2, max |e|) of e = num - ref as a float64 GPU tensor
+    of 3; num and ref are float32 GPU views of one shape (up to 3 axes, any
+    strides: a finer run's field or traces sampled by slicing, no copy)."""
+    if num.shape != ref.shape or num.dim() < 1 or num.dim() > 3:
+        raise ValueError("num and ref must have one shape of 1 to 3 axes")
+    for t, name in ((num, "num"), (ref, "ref")):
+        if t.dtype != torch.float32 or not t.is_cuda:
+            raise ValueError(f"{name} must be a float32 GPU tensor")
+    dims = list(reversed(range(num.dim())))          # fastest axis first
+    L3 = ctypes.c_longlong * 3
+    n = L3(*([int(num.shape[d]) for d in dims] + [1] * (3 - num.dim())))
+    sn = L3(*([int(num.stride(d)) for d in dims] + [0] * (3 - num.dim())))
+    sr = L3(*([int(ref.stride(d)) for d in dims] + [0] * (3 - num.dim())))
+    out = torch.zeros(3, dtype=torch.float64, device=num.device)
+    ws = torch.empty(FD_ERROR_NORMS_WS_BYTES + 256, dtype=torch.uint8, device=num.device)
+    aligned = (ws.data_ptr() + 255) // 256 * 256
+    if num.numel() == 0:
+        return out
+    _check(_lib.fd_error_norms(num.data_ptr(), sn, ref.data_ptr(), sr, n, _ptr(out), aligned,
+                               FD_ERROR_NORMS_WS_BYTES, _stream_handle(num.device)))
     return out

@@ -212,11 +212,29 @@ def test_dispersion_workspace_and_validation(F):
     assert F._lib.fd_dispersion_workspace_bytes(1, 10, 0) == 0
     d = ctypes.c_double()
     # argument checks run before any device work (pointers here are never read)
-    rc = F._lib.fd_dispersion(16, 16, 500, 10, 1e-3, 300, 6.0, None, ctypes.addressof(d), ctypes.addressof(d),
-                              256, withcwt, None)
+    rc = F._lib.fd_dispersion(16, 10, 16, 10, 500, 10, 1e-3, 300, 6.0, None, ctypes.addressof(d),
+                              ctypes.addressof(d), 256, withcwt, None)
     assert rc == F.FD_EINVAL and "nscale" in F.fd_last_error()
-    rc = F._lib.fd_dispersion(16, 16, 500, 10, 1e-3, 40, 6.0, None, ctypes.addressof(d), None, 256, 10, None)
+    rc = F._lib.fd_dispersion(16, 10, 16, 10, 500, 10, 1e-3, 40, 6.0, None, ctypes.addressof(d), None, 256, 10,
+                              None)
     assert rc == F.FD_ENOMEM
+    rc = F._lib.fd_dispersion(16, 10, 16, 9, 500, 10, 1e-3, 40, 6.0, None, ctypes.addressof(d), None, 256,
+                              withcwt, None)
+    assert rc == F.FD_EINVAL and "stride" in F.fd_last_error()
+
+
+def test_error_norms_validation(F):
+    import ctypes
+    L3 = ctypes.c_longlong * 3
+    one, n = L3(1, 4, 16), L3(4, 4, 1)
+    args = (16, one, 16, one)
+    assert F._lib.fd_error_norms(*args, L3(4, 0, 1), 16, 256, F.FD_ERROR_NORMS_WS_BYTES, None) == F.FD_EINVAL
+    assert F._lib.fd_error_norms(*args, n, 16, 256, F.FD_ERROR_NORMS_WS_BYTES - 1, None) == F.FD_ENOMEM
+    assert F._lib.fd_error_norms(*args, n, 16, 320, F.FD_ERROR_NORMS_WS_BYTES, None) == F.FD_EINVAL
+    assert F._lib.fd_error_norms(16, None, 16, one, n, 16, 256, F.FD_ERROR_NORMS_WS_BYTES, None) == F.FD_EINVAL
+    # the binding's constant is the header's
+    text = open(HEADER).read()
+    assert f"#define FD_ERROR_NORMS_WS_BYTES {F.FD_ERROR_NORMS_WS_BYTES}" in text
 
 
 @pytest.mark.parametrize("nt", [1, 2, 3, 7, 40, 333, 1000])

@@ -75,10 +75,11 @@ def parse():
     ap.add_argument("--no-ragged", action="store_true")
     ap.add_argument("--no-dispersion", action="store_true")
     ap.add_argument("--no-fwi3d", action="store_true")
+    ap.add_argument("--no-study", action="store_true")
     ap.add_argument("--vol3d-nt", type=int, default=1000)
     ap.add_argument("--ragged-nt", type=int, default=3000)
     ap.add_argument("--no-tune", action="store_true", help="skip the tile autotuner")
-    ap.add_argument("--only", choices=["2d", "vol3d", "ragged", "fwi", "fwi3d", "copy"], default=None,
+    ap.add_argument("--only", choices=["2d", "vol3d", "ragged", "fwi", "fwi3d", "study", "copy"], default=None,
                     help="run one workload alone (for profiling); no value line")
     ap.add_argument("--stencil", default=None,
                     help="--only 2d: run this stencil alone (e.g. specls-square-M8)")
@@ -118,6 +119,8 @@ def main():
             res = only_2d(torch, F, autotune, configs, design, dev, args)
         elif args.only == "vol3d":
             res = vol3d_bench(torch, F, design, configs, dev, args.vol3d_nt, not args.no_tune)
+        elif args.only == "study":
+            res = study_bench(torch)
         elif args.only == "fwi3d":
             res = fwi3d_bench(torch, F, design, configs, dev, args.vol3d_nt)
         elif args.only == "ragged":
@@ -239,6 +242,8 @@ def main():
     if not args.no_fwi3d:
         line["fwi3d"] = fwi3d_bench(torch, F, design, configs, dev, args.vol3d_nt)
         log("fwi3d done")
+    if not args.no_study:
+        line["study"] = study_bench(torch)
     if not args.no_dispersion:
         line["dispersion"] = dispersion_bench(torch, F, variants, w)
         log("dispersion done")
@@ -503,6 +508,27 @@ def fwi3d_bench(torch, F, design, configs, dev, nt):
     out["field_gib"] = round(field_gib, 3)
     del vel
     torch.cuda.empty_cache()
+    return out
+
+
+def study_bench(torch, refine=16):
+    """Sec. 6 reference-solution study at the paper's sizes: 401^2 coarse
+    runs of every scheme (SpatTE / SpecTE-theta crosses, DispTE (homogeneous)
+    or DispLS (two-layer) cross-rhombus, M = 1..6) against a reference on the
+    6401^2 grid refined 16 times in space and time (Taylor cross M = 8)."""
+    from paper_2606_04882_amd import study as SD
+    out = {}
+    for name, fn in (("homogeneous", SD.homogeneous), ("two_layer", SD.two_layer)):
+        res = fn(refine=refine, tune=True, time_reference=True)
+        torch.cuda.synchronize()
+        keep = ("scheme", "stable", "snap_l2", "trace_l2", "trace_gamma_dft", "trace_gamma_cwt",
+                "rec_gamma_dft_avg", "rec_gamma_cwt_avg")
+        out[name] = {"reference": res["reference"], "coarse_seconds": res["coarse_seconds"],
+                     "courant": round(res["courant"], 4),
+                     "ranking_M6_trace_gamma_dft": SD.ranking(res, 6),
+                     "schemes": [{k: (float(f"{v:.4g}") if isinstance(v, float) else v) for k, v in r.items() if k in keep}
+                                 for r in res["schemes"]]}
+        log(f"study {name} done")
     return out
 
 

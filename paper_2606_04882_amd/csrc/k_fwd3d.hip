@@ -262,77 +262,108 @@ __global__ __launch_bounds__(kBlock3) void k_fwd3d_cross(StepArgs p) {
     }
 }
 
+// Adjoint step and gradient term (cross), pipelined like k_fwd3d_cross: the
+// operands of plane z+1 (queue fronts of psi^{k+1} and u^k, psi^{k+2}, v,
+// the gradient and both halos) are fetched while plane z is computed; both
+// xy planes alternate between two LDS buffers (one barrier per plane).
+// psi^{k+2}, v and the gradient are touched once per step and streamed
+// non-temporally; psi^{k+1} and u^k stay cacheable for the neighbouring
+// blocks' halo reads.  psi^k may overwrite psi^{k+2} in place: every point is
+// read (fetch of its plane) before the same thread writes it.
 template <int M, int RY>
 __global__ __launch_bounds__(kBlock3) void k_adj3d_cross(AdjArgs p) {
     using G = Geo3<M, RY>;
     constexpr int NQ = 2 * M + 1;
-    __shared__ float tp[G::PLANE];
-    __shared__ float tu[G::PLANE];
+    __shared__ float tp[2][G::PLANE];
+    __shared__ float tu[2][G::PLANE];
     const Pos3 b = block_pos<RY>(p.ntiles, p.tiles_x, p.tiles_y, p.zchunk, p.nz);
     const bool xok = b.gx < p.nx;
+    const long long plane = (long long)p.nx * p.ny;
+    const bool wg = p.with_grad, wu = p.with_update;
     float qp[RY][NQ], qu[RY][NQ];
     bool ok[RY];
+    long long col[RY], vcol[RY];
 #pragma unroll
     for (int j = 0; j < RY; ++j) {
         const int gy = b.y0 + b.ty * RY + j;
         ok[j] = xok && gy < p.ny;
+        col[j] = (long long)gy * p.nx + b.gx;
+        vcol[j] = (long long)gy * p.ldv_y + b.gx;
 #pragma unroll
         for (int i = 0; i < 2 * M; ++i) {
             const int z = b.zs - M + i;
             const bool in = ok[j] && (unsigned)z < (unsigned)p.nz;
-            const long long k = ((long long)z * p.ny + gy) * p.nx + b.gx;
-            qp[j][i] = in ? p.pcur[k] : 0.f;
-            qu[j][i] = (in && p.with_grad) ? p.ufwd[k] : 0.f;
+            qp[j][i] = in ? p.pcur[z * plane + col[j]] : 0.f;
+            qu[j][i] = (in && wg) ? p.ufwd[z * plane + col[j]] : 0.f;
         }
     }
-    for (int z = b.zs; z < b.ze; ++z) {
-        float pp[RY], vv[RY], gg[RY];
+    Halo<M, RY> hp, hu;
+    float fp[RY], fu[RY], pp[RY], vv[RY], gg[RY];
+    auto fetch = [&](int z) {
 #pragma unroll
         for (int j = 0; j < RY; ++j) {
-            const int gy = b.y0 + b.ty * RY + j;
             const int zz = z + M;
-            const bool in = ok[j] && zz < p.nz;
-            const long long kf = ((long long)zz * p.ny + gy) * p.nx + b.gx;
-            qp[j][2 * M] = in ? p.pcur[kf] : 0.f;
-            qu[j][2 * M] = (in && p.with_grad) ? p.ufwd[kf] : 0.f;
-            const long long k = ((long long)z * p.ny + gy) * p.nx + b.gx;
-            const long long kv = (long long)z * p.ldv_z + (long long)gy * p.ldv_y + b.gx;
-            pp[j] = (ok[j] && p.with_update) ? p.pprev[k] : 0.f;
-            vv[j] = ok[j] ? p.v[kv] : 0.f;
-            gg[j] = (ok[j] && p.with_grad) ? p.grad[kv] : 0.f;
-            tp[(b.ty * RY + j + M) * G::LW + b.tx + M] = qp[j][M];
-            tu[(b.ty * RY + j + M) * G::LW + b.tx + M] = qu[j][M];
+            const bool in = ok[j] && z < b.ze;
+            const bool fin = in && zz < p.nz;
+            fp[j] = fin ? p.pcur[zz * plane + col[j]] : 0.f;
+            fu[j] = (fin && wg) ? p.ufwd[zz * plane + col[j]] : 0.f;
+            pp[j] = (in && wu) ? __builtin_nontemporal_load(p.pprev + z * plane + col[j]) : 0.f;
+            vv[j] = in ? __builtin_nontemporal_load(p.v + (long long)z * p.ldv_z + vcol[j]) : 0.f;
+            gg[j] = (in && wg) ? __builtin_nontemporal_load(p.grad + (long long)z * p.ldv_z + vcol[j]) : 0.f;
         }
-        load_halo<M, RY>(tp, p.pcur, p.nx, p.ny, p.nz, b.x0, b.y0, z);
-        if (p.with_grad) load_halo<M, RY>(tu, p.ufwd, p.nx, p.ny, p.nz, b.x0, b.y0, z);
+        if (z < b.ze) {
+            hp.fetch(p.pcur, p.nx, p.ny, p.nz, b.x0, b.y0, z);
+            if (wg) hu.fetch(p.ufwd, p.nx, p.ny, p.nz, b.x0, b.y0, z);
+        }
+    };
+    fetch(b.zs);
+    int buf = 0;
+    for (int z = b.zs; z < b.ze; ++z) {
+        float* tpb = tp[buf];
+        float* tub = tu[buf];
+        float ppc[RY], vvc[RY], ggc[RY];
+#pragma unroll
+        for (int j = 0; j < RY; ++j) {
+            qp[j][2 * M] = fp[j];
+            qu[j][2 * M] = fu[j];
+            ppc[j] = pp[j];
+            vvc[j] = vv[j];
+            ggc[j] = gg[j];
+            tpb[(b.ty * RY + j + M) * G::LW + b.tx + M] = qp[j][M];
+            tub[(b.ty * RY + j + M) * G::LW + b.tx + M] = qu[j][M];
+        }
+        hp.store(tpb);
+        if (wg) hu.store(tub);
+        fetch(z + 1);
         __syncthreads();
 #pragma unroll
         for (int j = 0; j < RY; ++j) {
             const int row = b.ty * RY + j + M;
-            const float Lp = cross_sum<M, RY>(tp, qp[j], row, b.tx + M, p.w);
-            const float Lu = p.with_grad ? cross_sum<M, RY>(tu, qu[j], row, b.tx + M, p.w) : 0.f;
+            const float Lp = cross_sum<M, RY>(tpb, qp[j], row, b.tx + M, p.w);
+            const float Lu = wg ? cross_sum<M, RY>(tub, qu[j], row, b.tx + M, p.w) : 0.f;
             if (ok[j]) {
                 const int gy = b.y0 + b.ty * RY + j;
-                const long long k = ((long long)z * p.ny + gy) * p.nx + b.gx;
-                const long long kv = (long long)z * p.ldv_z + (long long)gy * p.ldv_y + b.gx;
+                const long long k = z * plane + col[j];
+                const long long kv = (long long)z * p.ldv_z + vcol[j];
                 const float pc = qp[j][M];
-                if (p.with_grad) p.grad[kv] = fmaf(grad_factor(p.gparam, p.gscale, vv[j]) * pc, Lu, gg[j]);
-                if (p.with_update) {
+                if (wg)
+                    __builtin_nontemporal_store(fmaf(grad_factor(p.gparam, p.gscale, vvc[j]) * pc, Lu, ggc[j]),
+                                                p.grad + kv);
+                if (wu) {
                     bool inband;
                     const float e = damp_e(p.sp, b.gx, gy, z, p.nx, p.ny, p.nz, inband);
                     float r;
                     if (!inband) {
-                        r = fmaf(vv[j], Lp, 2.f * pc - pp[j]);
+                        r = fmaf(vvc[j], Lp, 2.f * pc - ppc[j]);
                     } else {
-                        r = fmaf(-(1.f - e), pp[j], 2.f * pc);
-                        r = fmaf(vv[j], Lp, r);
+                        r = fmaf(-(1.f - e), ppc[j], 2.f * pc);
+                        r = fmaf(vvc[j], Lp, r);
                         r = r / (1.f + e);
                     }
-                    p.pnext[k] = r;
+                    __builtin_nontemporal_store(r, p.pnext + k);
                 }
             }
         }
-        __syncthreads();
 #pragma unroll
         for (int j = 0; j < RY; ++j)
 #pragma unroll
@@ -340,6 +371,7 @@ __global__ __launch_bounds__(kBlock3) void k_adj3d_cross(AdjArgs p) {
                 qp[j][i] = qp[j][i + 1];
                 qu[j][i] = qu[j][i + 1];
             }
+        buf ^= 1;
     }
 }
 

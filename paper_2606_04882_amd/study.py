@@ -20,7 +20,7 @@ from typing import Dict, List, Optional, Sequence
 import numpy as np
 import torch
 
-from . import configs, design
+from . import autotune, configs, design
 from . import fdwave as F
 
 
@@ -87,10 +87,13 @@ def _event_seconds(fn) -> float:
 
 
 def run(w: configs.Workload, wf: configs.Workload, schemes: Sequence[Scheme], nscale: int = 128,
-        device: str = "cuda:0", reference: Scheme = REFERENCE) -> Dict:
+        device: str = "cuda:0", reference: Scheme = REFERENCE, tune: bool = False, time_reference: bool = False) -> Dict:
     """Coarse runs of every scheme against the refined reference: per
     scheme the snapshot and trace error norms and the gamma^F / gamma^W norms
-    at the trace receiver, averaged and maximised over the receiver line."""
+    at the trace receiver, averaged and maximised over the receiver line.
+    tune: autotune the reference stencil's tile on the refined grid;
+    time_reference: run the reference traces twice and time the second call
+    (the first one captures the call's graphs)."""
     dev = torch.device(device)
     r = wf.extra["refine"]
     if (wf.shape[0] - 1) != r * (w.shape[0] - 1) or wf.nt != r * w.nt:
@@ -106,8 +109,13 @@ def run(w: configs.Workload, wf: configs.Workload, schemes: Sequence[Scheme], ns
     rec_f = torch.tensor(wf.rec, device=dev)
     ref_tr = torch.zeros(wf.nt, len(wf.rec), device=dev)
     ref_u = (torch.zeros(wf.shape, device=dev), torch.zeros(wf.shape, device=dev))
+    if tune:
+        autotune.tune(rid, 2, reference.shape, reference.M, _grid(wf, wf.nt), vel_f, wf.src, nt=40, reps=2,
+                      N=reference.N)
     shot = F.Shot(stencil_id=rid, src=wf.src, wavelet=wav_f, rec=rec_f, traces=ref_tr)
     t_tr = _event_seconds(lambda: F.fd_forward(_grid(wf, wf.nt), vel_f, [shot]))
+    if time_reference:
+        t_tr = _event_seconds(lambda: F.fd_forward(_grid(wf, wf.nt), vel_f, [shot]))
     snap_shot = F.Shot(stencil_id=rid, src=wf.src, wavelet=wav_f, final=ref_u)
     t_sn = _event_seconds(lambda: F.fd_forward(_grid(wf, r * nsnap), vel_f, [snap_shot]))
     del vel_f
@@ -152,8 +160,9 @@ def run(w: configs.Workload, wf: configs.Workload, schemes: Sequence[Scheme], ns
     return {"study": w.name, "refine": r, "courant": w.courant, "nt": w.nt, "snap_step": nsnap,
             "trace_rec": itr, "nrec": nrec, "nscale": nscale,
             "reference": {"stencil": reference.label, "grid": list(wf.shape), "nt": wf.nt,
+                          "tile": list(F.fd_get_tile(rid)), "steps_per_launch": F.fd_get_time_block(rid),
                           "seconds_traces": round(t_tr, 3), "seconds_snapshot": round(t_sn, 3),
-                          "gupd_s": round(upd_f * (wf.nt + r * nsnap) / (t_tr + t_sn) / 1e9, 1)},
+                          "gupd_s_traces": round(upd_f * wf.nt / t_tr / 1e9, 1)},
             "coarse_seconds": round(t_coarse, 3), "schemes": rows}
 
 
@@ -163,10 +172,12 @@ def ranking(result: Dict, M: int, key: str = "trace_gamma_dft") -> List[str]:
     return [r["scheme"] for r in sorted(rows, key=lambda r: r[key])]
 
 
-def homogeneous(refine: int = 16, Ms: Sequence[int] = range(1, 7), nscale: int = 128, device: str = "cuda:0"):
+def homogeneous(refine: int = 16, Ms: Sequence[int] = range(1, 7), nscale: int = 128, device: str = "cuda:0",
+                **kw):
     return run(configs.study_homogeneous(1), configs.study_homogeneous(refine), homogeneous_schemes(Ms), nscale,
-               device)
+               device, **kw)
 
 
-def two_layer(refine: int = 16, Ms: Sequence[int] = range(1, 7), nscale: int = 128, device: str = "cuda:0"):
-    return run(configs.study_two_layer(1), configs.study_two_layer(refine), two_layer_schemes(Ms), nscale, device)
+def two_layer(refine: int = 16, Ms: Sequence[int] = range(1, 7), nscale: int = 128, device: str = "cuda:0", **kw):
+    return run(configs.study_two_layer(1), configs.study_two_layer(refine), two_layer_schemes(Ms), nscale, device,
+               **kw)

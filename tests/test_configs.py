@@ -63,3 +63,26 @@ def test_generators_are_seeded_and_in_range():
         assert 0 <= sh.origin[0] and sh.origin[0] + sh.extent[0] <= 2000
         assert sh.stencil[1] in ("cross", "square") and 4 <= sh.stencil[2] <= 8
     assert {sh.stencil[1] for sh in shots} == {"cross", "square"}
+
+
+@pytest.mark.parametrize("make", ["study_homogeneous", "study_two_layer"])
+def test_study_workloads_refine_consistently(make):
+    """The refined reference grid covers the same domain: nodes, receivers,
+    source, sponge width, damping, time axis and snapshot time map by r."""
+    from paper_2606_04882_amd import configs as C
+    w, wf = getattr(C, make)(1), getattr(C, make)(16)
+    r = wf.extra["refine"]
+    assert r == 16 and (wf.shape[0] - 1) == r * (w.shape[0] - 1) and wf.shape[0] == wf.shape[1]
+    assert wf.h * r == pytest.approx(w.h) and wf.dt * r == pytest.approx(w.dt) and wf.nt == r * w.nt
+    assert np.array_equal(wf.rec, w.rec * r) and tuple(wf.src) == tuple(s * r for s in w.src)
+    assert wf.nb == r * w.nb and wf.eta_max == pytest.approx(w.eta_max)
+    assert wf.courant == pytest.approx(w.courant)
+    assert wf.extra["snap_step"] == r * w.extra["snap_step"]
+    # the trace receiver sits at the documented point
+    x, z = w.rec[w.extra["trace_rec"]] * w.h
+    assert (x, z) == ((1200.0, 3000.0) if make == "study_homogeneous" else (1000.0, 2000.0))
+    # the two-layer interface lies at 1200 m on both grids
+    vc, vf = C.study_model(w), C.study_model(wf)
+    assert np.array_equal(vc, vf[::r, ::r])
+    if make == "study_two_layer":
+        assert vc[120, 0] == 1500.0 and vc[121, 0] == 3000.0

@@ -73,42 +73,107 @@ __device__ __forceinline__ void s2_dx(const float* tile, int tx, int ty, const f
 //     w (d(z+dz) + d(z-dz)) + 2 w (u(x, z+dz) + u(x, z-dz) - 2 u(x, z)),
 // and the second part, summed over dx, is folded into the centre column's
 // weight wc[dz].  Every term stays a small difference of nearby values, at
-// two operations per group instead of three.  dx runs as a real loop,
-// uniform across the wave, so only one column group of LDS values is live at
-// a time (a fully unrolled form lets the compiler hoist every group's reads
-// and exhausts the register file); the centre value of each row is read from
-// LDS again rather than kept in registers.  W.wd holds the weight of group
-// (dx, dz) at wd[dx*(M+1) + dz]; the group extent along z for a given dx is
-// M (square), M - dx (rhombus) or, for the cross-rhombus / cross-square
-// family, the stencil's W.mz[dx], a wave-uniform value.  With a compile-time
-// extent only the rows a column needs are differenced; with a table extent
-// every row of the tile is, so that the LDS reads carry no branches (rows
-// beyond the extent are never weighted).
+// two operations per group instead of three.  W.wd holds the weight of group
+// (dx, dz) at wd[dx*(M+1) + dz].
+//
+// dx runs as a real loop, uniform across the wave, so that only one column
+// group of LDS values is live at a time (a fully unrolled form lets the
+// compiler hoist every group's reads and exhausts the register file).  The
+// square's z extent is M for every dx.  For the rhombus (extent M - dx) each
+// iteration branches to a body compiled for its dx (s2_dense_col<DX>), so the
+// row range is a constant and the reads are straight-line code with
+// immediate offsets (with a run-time extent every read sat behind its own
+// branch: 10.6 vs 8.3 us per 1001^2 step at M = 8; the same bodies made the
+// square 6 % slower, so it keeps the plain loop).  The cross-rhombus /
+// cross-square family (SH_NSHAPE) reads its extent from the stencil's
+// W.mz[dx] and differences every row of the tile (no branch on the reads;
+// rows beyond the extent are never weighted).
+template <int SHAPE, int M, int RY, int LW, int DX>
+__device__ __forceinline__ void s2_dense_col(const float* tile, int tx, int ty, float* acc, const Weights& W) {
+    constexpr int MZ = M - DX;   // rhombus
+    const float* wrow = W.wd + DX * (M + 1);
+    float d[RY + 2 * MZ];
+#pragma unroll
+    for (int j = 0; j < RY + 2 * MZ; ++j) {
+        const float* row = tile + (ty * RY + M - MZ + j) * LW + tx + M;
+        d[j] = fmaf(-2.f, row[0], row[-DX] + row[DX]);
+    }
+    const float w0 = wrow[0];
+#pragma unroll
+    for (int j = 0; j < RY; ++j) acc[j] = fmaf(w0, d[j + MZ], acc[j]);
+#pragma unroll
+    for (int dz = 1; dz <= MZ; ++dz) {
+        const float w = wrow[dz];
+#pragma unroll
+        for (int j = 0; j < RY; ++j) acc[j] = fmaf(w, d[j + MZ + dz] + d[j + MZ - dz], acc[j]);
+    }
+}
+
 template <int SHAPE, int M, int RY, int LW>
 __device__ __forceinline__ void s2_dense_dx(const float* tile, int tx, int ty, float* acc,
                                             const Weights& W) {
+    if constexpr (SHAPE == SH_SQUARE) {
 #pragma unroll 1
-    for (int dx = 1; dx <= M; ++dx) {
-        const int mz = SHAPE == SH_SQUARE ? M : SHAPE == SH_RHOMBUS ? M - dx : W.mz[dx];
-        const float* wrow = W.wd + dx * (M + 1);
-        float d[RY + 2 * M];
+        for (int dx = 1; dx <= M; ++dx) {
+            const float* wrow = W.wd + dx * (M + 1);
+            float d[RY + 2 * M];
 #pragma unroll
-        for (int j = 0; j < RY + 2 * M; ++j) {
-            d[j] = 0.f;
-            if (SHAPE == SH_NSHAPE || (j >= M - mz && j < M + RY + mz)) {
+            for (int j = 0; j < RY + 2 * M; ++j) {
                 const float* row = tile + (ty * RY + j) * LW + tx + M;
                 d[j] = fmaf(-2.f, row[0], row[-dx] + row[dx]);
             }
-        }
-        const float w0 = wrow[0];
+            const float w0 = wrow[0];
 #pragma unroll
-        for (int j = 0; j < RY; ++j) acc[j] = fmaf(w0, d[j + M], acc[j]);
+            for (int j = 0; j < RY; ++j) acc[j] = fmaf(w0, d[j + M], acc[j]);
 #pragma unroll
-        for (int dz = 1; dz <= M; ++dz) {
-            if (dz <= mz) {
+            for (int dz = 1; dz <= M; ++dz) {
                 const float w = wrow[dz];
 #pragma unroll
                 for (int j = 0; j < RY; ++j) acc[j] = fmaf(w, d[j + M + dz] + d[j + M - dz], acc[j]);
+            }
+        }
+    } else if constexpr (SHAPE == SH_NSHAPE) {
+#pragma unroll 1
+        for (int dx = 1; dx <= M; ++dx) {
+            const int mz = W.mz[dx];
+            const float* wrow = W.wd + dx * (M + 1);
+            float d[RY + 2 * M];
+#pragma unroll
+            for (int j = 0; j < RY + 2 * M; ++j) {
+                const float* row = tile + (ty * RY + j) * LW + tx + M;
+                d[j] = fmaf(-2.f, row[0], row[-dx] + row[dx]);
+            }
+            const float w0 = wrow[0];
+#pragma unroll
+            for (int j = 0; j < RY; ++j) acc[j] = fmaf(w0, d[j + M], acc[j]);
+#pragma unroll
+            for (int dz = 1; dz <= M; ++dz) {
+                if (dz <= mz) {
+                    const float w = wrow[dz];
+#pragma unroll
+                    for (int j = 0; j < RY; ++j) acc[j] = fmaf(w, d[j + M + dz] + d[j + M - dz], acc[j]);
+                }
+            }
+        }
+    } else {
+#pragma unroll 1
+        for (int dx = 1; dx <= M; ++dx) {
+            switch (dx) {
+#define FDW_DENSE_COL(D)                                                                   \
+    case D:                                                                                \
+        if constexpr (D <= M) s2_dense_col<SHAPE, M, RY, LW, (D <= M ? D : 1)>(tile, tx, ty, acc, W); \
+        break;
+                FDW_DENSE_COL(1)
+                FDW_DENSE_COL(2)
+                FDW_DENSE_COL(3)
+                FDW_DENSE_COL(4)
+                FDW_DENSE_COL(5)
+                FDW_DENSE_COL(6)
+                FDW_DENSE_COL(7)
+                FDW_DENSE_COL(8)
+#undef FDW_DENSE_COL
+                default:
+                    break;
             }
         }
     }

@@ -367,6 +367,7 @@ def vol3d_bench(torch, F, design, configs, dev, nt, tune=True):
             "tflops": round(npts * flops / (launch_us * 1e-6) / 1e12, 2),
             "kernel": f"k_fwd3d_{'cross' if shape == 'cross' else 'gen'}<M={M},rows={rows},zchunk={zc}>",
             "tuning_ms_per_20_steps": tuned})
+        out["stencils"][-1]["traffic"] = traffic_for(out["stencils"][-1]["kernel"], npts)
     del vel
     torch.cuda.empty_cache()
     return out

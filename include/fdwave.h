@@ -52,7 +52,7 @@ typedef enum {
     FD_ENOMEM = 3,        /* workspace too small */
     FD_EDEVICE = 4,       /* a HIP runtime call failed */
     FD_ENONFINITE = 5,    /* non-finite values found (check_finite) */
-    FD_EUNSUPPORTED = 6   /* valid request this build does not implement */
+    FD_EUNSUPPORTED = 6   /* valid request with no compiled kernel (shape, radius, tile) */
 } fd_status;
 
 typedef enum {

@@ -985,8 +985,9 @@ int enqueue_adjoint_revolve(const CallCtx& c, const ShotCtx& s, Recorder& R) {
     const int npool = 2 * nsnap + 2;
     auto field = [&](int i) { return i < 2 * nsnap ? ckpt + (size_t)i * n : W0 + (size_t)(i - 2 * nsnap) * n; };
     auto index = [&](const float* f) -> int {
-        for (int i = 0; i < npool; ++i)
-            if (field(i) == f) return i;
+        if (nsnap > 0 && f >= ckpt && f < ckpt + (size_t)2 * nsnap * n) return (int)((f - ckpt) / n);
+        if (f == W0) return 2 * nsnap;
+        if (f == W0 + n) return 2 * nsnap + 1;
         return -1;   // initial data or the zero field
     };
     std::vector<int> pins(npool, 0);
@@ -1282,7 +1283,14 @@ int enqueue_batched_adjoint(const CallCtx& c, Recorder& R) {
 }
 
 // Relative cost of one update with stencil (shape, M): stencil points plus
-// a fixed part for the loads, the update and the store.
+// a fixed part for the loads, the update and the store.  A launch adds a
+// fixed cost of its own (ramp-up and drain, about 4.3 us on gfx950, where a
+// 10^6-point window costs about 0.021 us per stencil point): kLaunchCost in
+// the same units (points x update_cost).  Without it a group of short,
+// latency-bound launches looks cheap and the balancing stacks several of
+// them on one branch, where their latencies add up every step.
+constexpr double kLaunchCost = 2.0e8;
+
 double update_cost(int shape, int M) {
     const int P = shape == SH_CROSS ? 4 * M + 1 : (shape == SH_RHOMBUS ? 2 * M * M + 2 * M + 1
                                                                        : (2 * M + 1) * (2 * M + 1));
@@ -1319,7 +1327,7 @@ void build_batch_blob(CallCtx& c, int mode) {
             g.maxrec = 0;
             g.branch = 0;
             c.groups.push_back(g);
-            gcost.push_back(0.0);
+            gcost.push_back(kLaunchCost);
         }
         CallCtx::Group& g = c.groups.back();
         BatchShot& d = desc[k];

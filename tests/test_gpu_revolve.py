@@ -170,3 +170,45 @@ def test_parametrised_gradient_batched_and_revolve_multishot(F):
     gb, gr = gb.cpu().numpy(), gr.cpu().numpy()
     assert rel_l2(gb, gr) <= 1e-5
     assert rel_l2(gb, gref) <= 1e-3
+
+
+@pytest.mark.parametrize("nt,nsnap", [(1, 0), (1, 1), (7, 7), (7, 2), (40, 40)])
+def test_revolve_edge_cases(F, nt, nsnap):
+    """Single-step runs, one snapshot per step and no recomputation at all
+    give the segment scheme's gradient and traces bitwise."""
+    c = case(F, 2, "cross", 2, nt=nt, seed=9)
+    g0, t0, _ = run(F, c, "segment", K=max(1, nt // 3))
+    g1, t1, _ = run(F, c, "revolve", nsnap=nsnap)
+    assert np.array_equal(g0, g1) and np.array_equal(t0, t1)
+
+
+def test_revolve_multishot_3d(F):
+    """Two 3D shots (windows of one model) under the binomial plan equal the
+    segment scheme shot after shot (3D calls never batch)."""
+    nz, ny, nx, h, nt, nb = 20, 16, 40, 10.0, 50, 4
+    vel = layered((nz, ny, nx), seed=21)
+    vmax = float(vel.max())
+    dt = 0.4 * 0.45 * h / vmax
+    wo = oracle_weights(3, "dispte", "cross", 4, vmax * dt / h)
+    sid = F.fd_weights_set(3, "cross", 4, wo)
+    eta = synth.sponge_eta_max(vmax, nb, h)
+    wav = torch.tensor(synth.ricker(nt, dt, 30.0).astype(np.float32), device=DEV)
+    g = F.Grid(shape=vel.shape, h=h, dt=dt, nt=nt, nb=nb, eta_max=eta, vmax=vmax)
+    rng = np.random.default_rng(22)
+    shots = []
+    for ox, ex in ((0, 30), (10, 30)):
+        rec = np.array([[x, y, 5] for x in range(2, ex - 2, 4) for y in range(2, ny - 2, 4)], dtype=np.int32)
+        shots.append(F.Shot(stencil_id=sid, src=(ex // 2, 8, 8), wavelet=wav, rec=torch.tensor(rec, device=DEV),
+                            traces=torch.zeros(nt, len(rec), device=DEV),
+                            trace_adj=torch.tensor(rng.standard_normal((nt, len(rec))).astype(np.float32),
+                                                   device=DEV),
+                            origin=(ox, 0, 0), extent=(ex, ny, nz)))
+    v = torch.tensor(vel, device=DEV)
+    ga = torch.zeros(vel.shape, device=DEV)
+    F.fd_adjoint_gradient(g, v, shots, 12, ga)
+    ta = [s.traces.clone() for s in shots]
+    gb = torch.zeros(vel.shape, device=DEV)
+    F.fd_adjoint_gradient(g, v, shots, 0, gb, ckpt="revolve", nsnap=3)
+    torch.cuda.synchronize()
+    assert torch.equal(ga, gb)
+    assert all(torch.equal(a, s.traces) for a, s in zip(ta, shots))

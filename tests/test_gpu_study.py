@@ -132,3 +132,24 @@ def test_unstable_schemes_are_reported_not_run(study):
                     reference=study.Scheme("taylor", "cross", 1))
     assert res["schemes"][0]["stable"] is False
     assert res["schemes"][1]["stable"] is True and res["schemes"][1]["snap_l2"] > 0
+
+
+@pytest.mark.parametrize("shape,slicer", [((37,), lambda t: t), ((1001, 3), lambda t: t[:, 1]),
+                                          ((65, 97), lambda t: t[::4, ::8]), ((9, 33, 50), lambda t: t[1::2, ::3, 5:])])
+def test_error_norms_on_strided_views(shape, slicer):
+    """fd_error_norms over views with arbitrary strides equals numpy's sums
+    on copies (FP64 accumulation of FP32 differences)."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2606_04882_amd import fdwave as F
+    g = torch.Generator().manual_seed(int(np.prod(shape)))
+    a = torch.randn(shape, generator=g).to("cuda")
+    b = torch.randn(shape, generator=g).to("cuda")
+    va, vb = slicer(a), slicer(b)
+    out = F.fd_error_norms(va, vb).cpu().numpy()
+    e = va.cpu().numpy().astype(np.float64) - vb.cpu().numpy().astype(np.float64)
+    assert abs(out[0] - np.abs(e).sum()) <= 1e-12 * np.abs(e).sum()
+    assert abs(out[1] - (e * e).sum()) <= 1e-12 * (e * e).sum()
+    assert out[2] == np.abs(e).max()
+    # deterministic: the same call gives the same bits
+    assert np.array_equal(out, F.fd_error_norms(va, vb).cpu().numpy())

@@ -282,12 +282,13 @@ int fd_set_tile(int stencil_id, int rows, int zchunk);
 int fd_get_tile(int stencil_id, int* rows, int* zchunk);
 
 /*
- * Time steps per kernel launch of the single-shot 2D forward (1 or 2).  With
- * 2, one launch advances two steps on a tile staged with a 2M halo (fields
- * written out of place), halving launches and HBM passes; results are
- * bit-identical to 1.  Compiled for cross stencils with rows 2 or 4
- * (FD_EUNSUPPORTED otherwise); the default is 2 where compiled.  Calls with
- * checkpoints (the adjoint) and batched calls always use one step per launch.
+ * Time steps per kernel launch of the single-shot forward (1 or 2).  With
+ * 2, one launch advances two steps (the first one on the tile plus an M-cell
+ * ring, fields written out of place), halving launches and HBM passes;
+ * results are bit-identical to 1.  Compiled for 2D cross stencils with rows
+ * 2 or 4 and 3D cross stencils with M <= 4 and rows 1 (FD_EUNSUPPORTED
+ * otherwise); the default is 2 for the 2D crosses.  Calls with checkpoints
+ * (the adjoint) and batched calls always use one step per launch.
  */
 int fd_set_time_block(int stencil_id, int steps);
 int fd_get_time_block(int stencil_id, int* steps);

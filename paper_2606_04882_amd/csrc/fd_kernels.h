@@ -274,6 +274,32 @@ struct TbArgs {
 bool launch_fwd2d_tb(const TbArgs& a, int shape, int M, int rows, hipStream_t s);
 bool have_fwd2d_tb(int shape, int M, int rows);
 
+// Two steps per launch, 3D cross stencils (k_fwd3d_cross_tb): the same
+// fields as TbArgs on a [nz][ny][nx] window with model strides for v.
+struct Tb3Args {
+    const float* __restrict__ uprev;   // u^{n-1}
+    const float* __restrict__ ucur;    // u^n
+    float* __restrict__ out1;          // u^{n+1}
+    float* __restrict__ out2;          // u^{n+2}
+    const float* __restrict__ v;
+    long long ldv_y, ldv_z;
+    int nx, ny, nz;
+    int tiles_x, tiles_y, ntiles, zchunk;
+    Sponge sp;
+    long long src;
+    float q;                           // dt^2 / h^3
+    const float* __restrict__ wavelet;
+    int step;                          // n (s^n and s^{n+1} are used)
+    int nrec;
+    const long long* __restrict__ rec_lin;
+    float* __restrict__ trace_a;       // trace n-2 <- u^{n-1}, or nullptr
+    float* __restrict__ trace_b;       // trace n-1 <- u^n, or nullptr
+    Weights w;
+};
+
+bool launch_fwd3d_tb(const Tb3Args& a, int shape, int M, int rows, hipStream_t s);
+bool have_fwd3d_tb(int shape, int M, int rows);
+
 // Launchers (one per translation unit).  Return false when the requested
 // (shape, M, rows) combination was not compiled.
 bool launch_fwd2d(const StepArgs& a, int shape, int M, int rows, hipStream_t s);

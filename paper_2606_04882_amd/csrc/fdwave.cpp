@@ -219,7 +219,7 @@ struct Stencil {
     Weights w32;
     double cfl;
     int rows, zchunk;
-    int tsteps;   // 2D single-shot forward: time steps per launch (1 or 2)
+    int tsteps;   // single-shot forward: time steps per launch (1 or 2)
 };
 
 std::mutex g_mu;
@@ -300,11 +300,11 @@ Layout make_layout(const fd_grid* g, const fd_shot* shots, int nshots, int mode,
     off = align256(off + sizeof(float) * (size_t)mpts);
     const bool batch = use_batch(g, nshots, mode);
     const int nseg = mode == MODE_ADJ_SEGMENT ? (g->nt + K - 1) / K : 0;
-    // 2D single-shot forward keeps four fields so that two-steps-per-launch
+    // a single-shot forward keeps four fields so that two-steps-per-launch
     // kernels can write out of place; the binomial adjoint keeps its fields
     // in the shared scratch below
     L.nslots = (batch && mode == MODE_ADJ_SEGMENT) ? AdjSlots{nseg, K}.count()
-             : mode == MODE_ADJ_REVOLVE ? 0 : ((g->ndim == 2 && !batch && mode == MODE_FORWARD) ? 4 : 2);
+             : mode == MODE_ADJ_REVOLVE ? 0 : ((!batch && mode == MODE_FORWARD) ? 4 : 2);
     long long wmax = 0;
     for (int i = 0; i < nshots; ++i) {
         const long long wp = window_points(shots[i], g->ndim);
@@ -628,8 +628,15 @@ bool launch_step(const CallCtx& c, const ShotCtx& s, const StepArgs& a, hipStrea
     return launch_fwd3d(a, s.st.shape, s.st.M, s.st.rows, st);
 }
 
-// Two steps per launch (2D, no checkpoints): four buffers rotate; traces
-// n-2 and n-1 are gathered from the inputs of the launch covering n, n+1.
+bool have_tb(int ndim, int shape, int M, int rows) {
+    return ndim == 2 ? have_fwd2d_tb(shape, M, rows) : have_fwd3d_tb(shape, M, rows);
+}
+
+// the 3D two-step kernel addresses a plane with 32-bit offsets
+bool tb_fits(const ShotCtx& s) { return (long long)s.nx * s.ny < (1LL << 31); }
+
+// Two steps per launch (no checkpoints): four buffers rotate; traces n-2 and
+// n-1 are gathered from the inputs of the launch covering n, n+1.
 int enqueue_forward_tb(const CallCtx& c, const ShotCtx& s, Recorder& R) {
     hipStream_t st = R.cur();
     const long long n = s.npts;
@@ -640,8 +647,29 @@ int enqueue_forward_tb(const CallCtx& c, const ShotCtx& s, Recorder& R) {
     float* f2 = s.bufA + 3 * n;
     if (s.s->init_prev) launch_copy(prev, s.s->init_prev, n, st); else launch_fill(prev, n, 0.f, st);
     if (s.s->init_cur) launch_copy(cur, s.s->init_cur, n, st); else launch_fill(cur, n, 0.f, st);
-    launch_rec_index(s.s->rec, nrec, 2, s.nx, 1, s.nz, s.rec, c.flags, st);
+    launch_rec_index(s.s->rec, nrec, c.g->ndim, s.nx, s.ny, s.nz, s.rec, c.flags, st);
     R.launched(3);
+    Tb3Args t3;
+    std::memset(&t3, 0, sizeof t3);
+    if (c.g->ndim == 3) {
+        t3.v = s.v;
+        t3.ldv_y = c.ldv_y;
+        t3.ldv_z = c.ldv_z;
+        t3.nx = s.nx;
+        t3.ny = s.ny;
+        t3.nz = s.nz;
+        t3.tiles_x = (s.nx + kTileX - 1) / kTileX;
+        t3.tiles_y = (s.ny + kWaves3 - 1) / kWaves3;
+        t3.zchunk = s.st.zchunk;
+        t3.ntiles = t3.tiles_x * t3.tiles_y * ((s.nz + s.st.zchunk - 1) / s.st.zchunk);
+        t3.sp = c.sp;
+        t3.src = s.src;
+        t3.q = c.q;
+        t3.wavelet = s.s->wavelet;
+        t3.nrec = nrec;
+        t3.rec_lin = s.rec;
+        t3.w = s.st.w32;
+    }
     TbArgs t;
     std::memset(&t, 0, sizeof t);
     t.v = s.v;
@@ -667,8 +695,20 @@ int enqueue_forward_tb(const CallCtx& c, const ShotCtx& s, Recorder& R) {
         t.step = step;
         t.trace_a = (nrec > 0 && step >= 2) ? tr + (size_t)(step - 2) * nrec : nullptr;
         t.trace_b = (nrec > 0 && step >= 1) ? tr + (size_t)(step - 1) * nrec : nullptr;
-        if (!launch_fwd2d_tb(t, s.st.shape, s.st.M, s.st.rows, st))
-            return fail(FD_EUNSUPPORTED, "two-step kernel not compiled");
+        bool ok;
+        if (c.g->ndim == 2) {
+            ok = launch_fwd2d_tb(t, s.st.shape, s.st.M, s.st.rows, st);
+        } else {
+            t3.uprev = prev;
+            t3.ucur = cur;
+            t3.out1 = f1;
+            t3.out2 = f2;
+            t3.step = step;
+            t3.trace_a = t.trace_a;
+            t3.trace_b = t.trace_b;
+            ok = launch_fwd3d_tb(t3, s.st.shape, s.st.M, s.st.rows, st);
+        }
+        if (!ok) return fail(FD_EUNSUPPORTED, "two-step kernel not compiled");
         R.launched();
         std::swap(prev, f1);
         std::swap(cur, f2);
@@ -706,8 +746,8 @@ int enqueue_forward_tb(const CallCtx& c, const ShotCtx& s, Recorder& R) {
 // adjoint needs no recompute for that segment).
 int enqueue_forward_shot(const CallCtx& c, const ShotCtx& s, float* ckpt, int K, float* seg,
                          Recorder& R) {
-    if (!ckpt && c.g->ndim == 2 && s.st.tsteps == 2 && c.L.nslots >= 4 &&
-        have_fwd2d_tb(s.st.shape, s.st.M, s.st.rows))
+    if (!ckpt && s.st.tsteps == 2 && c.L.nslots >= 4 && have_tb(c.g->ndim, s.st.shape, s.st.M, s.st.rows) &&
+        tb_fits(s))
         return enqueue_forward_tb(c, s, R);
     hipStream_t st = R.cur();
     const long long n = s.npts;
@@ -1801,7 +1841,7 @@ int fd_set_tile(int stencil_id, int rows, int zchunk) {
     if (!have) return fail(FD_EUNSUPPORTED, "no kernel compiled for rows = %d", rows);
     s.rows = rows;
     s.zchunk = zchunk;
-    if (s.tsteps == 2 && !have_fwd2d_tb(s.shape, s.M, rows)) s.tsteps = 1;
+    if (s.tsteps == 2 && !have_tb(s.ndim, s.shape, s.M, rows)) s.tsteps = 1;
     return FD_OK;
 }
 
@@ -1810,7 +1850,7 @@ int fd_set_time_block(int stencil_id, int steps) {
     if (stencil_id < 0 || stencil_id >= (int)g_stencils.size()) return fail(FD_EINVAL, "unknown stencil id");
     if (steps != 1 && steps != 2) return fail(FD_EINVAL, "steps must be 1 or 2");
     Stencil& s = g_stencils[stencil_id];
-    if (steps == 2 && (s.ndim != 2 || !have_fwd2d_tb(s.shape, s.M, s.rows)))
+    if (steps == 2 && !have_tb(s.ndim, s.shape, s.M, s.rows))
         return fail(FD_EUNSUPPORTED, "no two-step kernel for this stencil and tile height");
     s.tsteps = steps;
     return FD_OK;

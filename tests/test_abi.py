@@ -104,8 +104,18 @@ def test_time_block_controls(F):
         F.fd_set_time_block(sq, 2)
     assert e.value.code == F.FD_EUNSUPPORTED
     s3 = F.fd_weights_set(3, "cross", 2, oracle_weights(3, "taylor", "cross", 2))
+    F.fd_set_tile(s3, 1, 64)
+    F.fd_set_time_block(s3, 2)                 # 3D crosses with M <= 4 at one row per thread
+    assert F.fd_get_time_block(s3) == 2
+    F.fd_set_tile(s3, 2, 64)                   # two rows: falls back to one step
+    assert F.fd_get_time_block(s3) == 1
     with pytest.raises(F.FdError) as e:
         F.fd_set_time_block(s3, 2)
+    assert e.value.code == F.FD_EUNSUPPORTED
+    s8 = F.fd_weights_set(3, "cross", 8, oracle_weights(3, "taylor", "cross", 8))
+    F.fd_set_tile(s8, 1, 64)
+    with pytest.raises(F.FdError) as e:
+        F.fd_set_time_block(s8, 2)
     assert e.value.code == F.FD_EUNSUPPORTED
     with pytest.raises(F.FdError):
         F.fd_set_time_block(10 ** 6, 1)

@@ -135,3 +135,45 @@ def test_3d_adjoint_gradient(F, shape, M):
     gref, _ = S.adjoint_gradient(rounded_stencil(3, shape, M, wo), v32(vel, dt, h), vel.astype(np.float64), dt,
                                  nt, nb, eta, src, q32(wav, dt, h, 3), rec, rho.astype(np.float64))
     assert rel_l2(grad.cpu().numpy(), gref) <= 1e-3
+
+
+@pytest.mark.parametrize("M,zchunk,nt", [(1, 16, 31), (2, 24, 40), (3, 8, 23), (4, 16, 41), (4, 64, 30)])
+def test_3d_two_steps_per_launch(F, M, zchunk, nt):
+    """Two steps per launch (k_fwd3d_cross_tb) on a window with ragged tiles in
+    x, y and z, a damping band on every face, a source near a block edge and
+    receivers: traces and final states bitwise equal to one step per launch
+    (odd and even nt), and the oracle's to 1e-5."""
+    nz, ny, nx, h, nb = 45, 21, 83, 10.0, 4
+    vel = layered((nz, ny, nx), seed=30 + M)
+    dt = 0.4 * 0.45 * h / float(vel.max())
+    wo = oracle_weights(3, "dispte", "cross", M, float(vel.max()) * dt / h)
+    sid = F.fd_weights_set(3, "cross", M, wo)
+    eta = synth.sponge_eta_max(float(vel.max()), nb, h)
+    wav = synth.ricker(nt, dt, 40.0)
+    src = (64, 8, 15)     # the first column and row of the second tile in x and y
+    rec = [[x, y, 3] for x in range(1, nx - 1, 7) for y in range(1, ny - 1, 5)] + [[63, 8, 15], [82, 20, 44]]
+    F.fd_set_tile(sid, 1, zchunk)
+    F.fd_set_time_block(sid, 1)
+    one = run3(F, vel, h, dt, nt, nb, eta, sid, src, wav, rec, final=True)
+    F.fd_set_time_block(sid, 2)
+    assert F.fd_get_time_block(sid) == 2
+    two = run3(F, vel, h, dt, nt, nb, eta, sid, src, wav, rec, final=True)
+    assert np.array_equal(one["traces"], two["traces"])
+    assert np.array_equal(one["cur"], two["cur"])
+    ref = oracle_traces(3, "cross", M, wo, vel, h, dt, nt, nb, eta, src, wav, rec)
+    assert rel_l2(two["traces"], ref["traces"]) <= 1e-5
+
+
+def test_3d_two_step_controls(F):
+    sid = F.fd_weights_set(3, "cross", 8, oracle_weights(3, "taylor", "cross", 8))
+    F.fd_set_tile(sid, 1, 64)
+    with pytest.raises(F.FdError):
+        F.fd_set_time_block(sid, 2)          # M = 8 has no two-step kernel
+    sid4 = F.fd_weights_set(3, "cross", 4, oracle_weights(3, "taylor", "cross", 4))
+    F.fd_set_tile(sid4, 2, 64)
+    with pytest.raises(F.FdError):
+        F.fd_set_time_block(sid4, 2)         # rows 2 has none either
+    F.fd_set_tile(sid4, 1, 64)
+    F.fd_set_time_block(sid4, 2)
+    F.fd_set_tile(sid4, 2, 64)               # a tile without it falls back to one step
+    assert F.fd_get_time_block(sid4) == 1

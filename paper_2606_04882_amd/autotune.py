@@ -34,6 +34,8 @@ def candidates(ndim: int, shape: str, M: int) -> List[Tuple[int, int, int]]:
         c = [(r, 64, 1) for r in (2, 4, 8)]
         if shape == "cross":
             c += [(r, 64, 2) for r in (2, 4)]
+            # z-marching kernel (one row per thread), for large windows
+            c += [(1, z, 1) for z in (16, 24, 32, 48)]
         return c
     rows = (1, 2, 4) if shape == "cross" else ((1, 2) if M <= 4 else (1,))
     return [(r, z, 1) for r in rows for z in (16, 32, 64, 128)]

@@ -303,6 +303,9 @@ bool have_fwd3d_tb(int shape, int M, int rows);
 // Launchers (one per translation unit).  Return false when the requested
 // (shape, M, rows) combination was not compiled.
 bool launch_fwd2d(const StepArgs& a, int shape, int M, int rows, hipStream_t s);
+// 2D cross stencils marching along z (k_fwd2d_march, one row per thread):
+// kBlock3 columns per block, tiles_x = ceil(nx / kBlock3), zchunk rows
+bool launch_fwd2d_march(const StepArgs& a, int M, hipStream_t s);
 bool launch_fwd3d(const StepArgs& a, int shape, int M, int rows, hipStream_t s);
 bool launch_adj2d(const AdjArgs& a, int shape, int M, int rows, hipStream_t s);
 bool launch_adj3d(const AdjArgs& a, int shape, int M, int rows, hipStream_t s);

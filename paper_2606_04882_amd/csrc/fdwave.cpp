@@ -588,7 +588,12 @@ long long model_offset(const CallCtx& c, const fd_shot& s) {
 }
 
 void fill_tiles(StepArgs& a, int ndim, int rows, int zchunk) {
-    if (ndim == 2) {
+    if (ndim == 2 && rows == 1) {   // marching kernel: kBlock3 columns by zchunk rows
+        a.tiles_x = (a.nx + kBlock3 - 1) / kBlock3;
+        a.tiles_y = 1;
+        a.ntiles = a.tiles_x * ((a.nz + zchunk - 1) / zchunk);
+        a.zchunk = zchunk;
+    } else if (ndim == 2) {
         a.tiles_x = (a.nx + kTileX - 1) / kTileX;
         a.tiles_y = 1;
         const int tz = (a.nz + 4 * rows - 1) / (4 * rows);
@@ -801,8 +806,10 @@ int enqueue_forward_shot(const CallCtx& c, const ShotCtx& s, float* ckpt, int K,
     return R.err;
 }
 
+// the 2D marching forward kernel (rows 1) has no adjoint twin: the 2D
+// adjoint then runs its tiled kernel at 4 rows per thread
 int adj_rows(const CallCtx& c, const ShotCtx& s) {
-    return c.g->ndim == 3 ? adj_rows3d(s.st.shape, s.st.rows) : s.st.rows;
+    return c.g->ndim == 3 ? adj_rows3d(s.st.shape, s.st.rows) : (s.st.rows == 1 ? 4 : s.st.rows);
 }
 
 // gscale of grad_factor for the call's gradient parameter
@@ -838,7 +845,7 @@ AdjArgs base_adj(const CallCtx& c, const ShotCtx& s) {
 }
 
 bool launch_adj(const CallCtx& c, const ShotCtx& s, const AdjArgs& a, hipStream_t st) {
-    if (c.g->ndim == 2) return launch_adj2d(a, s.st.shape, s.st.M, s.st.rows, st);
+    if (c.g->ndim == 2) return launch_adj2d(a, s.st.shape, s.st.M, adj_rows(c, s), st);
     return launch_adj3d(a, s.st.shape, s.st.M, adj_rows(c, s), st);
 }
 

@@ -72,10 +72,12 @@ static bool dispatch_m(const StepArgs& a, int M, int rows, hipStream_t s) {
 }
 
 bool have_fwd2d(int shape, int M, int rows) {
+    if (rows == 1) return shape == SH_CROSS && M >= 1 && M <= 8;   // k_fwd2d_march
     return shape >= 0 && shape <= 3 && M >= 1 && M <= 8 && (rows == 2 || rows == 4 || rows == 8);
 }
 
 bool launch_fwd2d(const StepArgs& a, int shape, int M, int rows, hipStream_t s) {
+    if (rows == 1) return shape == SH_CROSS && launch_fwd2d_march(a, M, s);
     switch (shape) {
         case SH_CROSS: return dispatch_m<SH_CROSS>(a, M, rows, s);
         case SH_RHOMBUS: return dispatch_m<SH_RHOMBUS>(a, M, rows, s);

@@ -208,3 +208,51 @@ def test_v_coefficient_is_rounded_once(F):
     torch.cuda.synchronize()
     v_gpu = ws[256:256 + 4 * vel.size].view(torch.float32).cpu().numpy().reshape(vel.shape)
     assert np.array_equal(v_gpu, v32(vel, dt, h).astype(np.float32))
+
+
+@pytest.mark.parametrize("M,zchunk,shape", [(1, 8, (37, 530)), (4, 64, (150, 1100)), (8, 16, (77, 601)),
+                                            (5, 128, (300, 513))])
+def test_marching_cross_kernel(M, zchunk, shape):
+    """The z-marching cross kernel (one row per thread) on windows with
+    ragged column blocks and chunks, a damping band, a source and receivers:
+    traces and final state bitwise equal to the tiled kernel, and the
+    oracle's to 1e-5; the adjoint with this tile (forward steps marching,
+    adjoint steps tiled) gives the tiled configuration's gradient bitwise."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2606_04882_amd import fdwave as F
+    from tests.fdcase import layered, oracle_traces, oracle_weights, rel_l2
+    from paper_2606_04882_amd import synth
+    nz, nx = shape
+    h, nt, nb = 10.0, 90, 12
+    vel = layered(shape, seed=40 + M)
+    vmax = float(vel.max())
+    dt = 0.5 * 0.45 * h / vmax
+    wo = oracle_weights(2, "dispte", "cross", M, vmax * dt / h)
+    sid = F.fd_weights_set(2, "cross", M, wo)
+    F.fd_set_time_block(sid, 1)
+    eta = synth.sponge_eta_max(vmax, nb, h)
+    wav = synth.ricker(nt, dt, 30.0)
+    rec = np.array([[x, 5] for x in range(0, nx, 9)] + [[nx - 1, nz - 1], [511, nz // 2]], dtype=np.int32)
+    rec = rec[rec[:, 0] < nx]
+    src = (min(512, nx - 3), nz // 3)
+    g = F.Grid(shape=shape, h=h, dt=dt, nt=nt, nb=nb, eta_max=eta, vmax=vmax)
+    rho = torch.tensor(np.random.default_rng(M).standard_normal((nt, len(rec))).astype(np.float32), device="cuda")
+
+    def run(rows):
+        F.fd_set_tile(sid, rows, zchunk)
+        sh = F.Shot(stencil_id=sid, src=src, wavelet=torch.tensor(wav.astype(np.float32), device="cuda"),
+                    rec=torch.tensor(rec, device="cuda"), traces=torch.zeros(nt, len(rec), device="cuda"),
+                    trace_adj=rho, final=(torch.zeros(shape, device="cuda"), torch.zeros(shape, device="cuda")))
+        v = torch.tensor(vel, device="cuda")
+        F.fd_forward(g, v, [sh])
+        grad = torch.zeros(shape, device="cuda")
+        F.fd_adjoint_gradient(g, v, [sh], 30, grad)
+        torch.cuda.synchronize()
+        return sh.traces.cpu().numpy(), sh.final[1].cpu().numpy(), grad.cpu().numpy()
+
+    tr1, u1, g1 = run(1)
+    tr4, u4, g4 = run(4)
+    assert np.array_equal(tr1, tr4) and np.array_equal(u1, u4) and np.array_equal(g1, g4)
+    ref = oracle_traces(2, "cross", M, wo, vel, h, dt, nt, nb, eta, src, wav, rec)
+    assert rel_l2(tr1, ref["traces"]) <= 1e-5

@@ -1,8 +1,9 @@
 """Tile autotuner for the forward kernels.
 
 For a stencil on a given grid, times a short forward run for every compiled
-configuration (2D: rows per thread 2, 4, 8, and for crosses also one or two
-time steps per launch; 3D: rows 1, 2, 4 times z-chunk 16, 32, 64, 128) and
+configuration (2D: rows per thread 2, 4, 8, and for crosses also two time
+steps per launch and the z-marching kernel with chunks of 16-48 rows; 3D:
+rows 1, 2, 4 times z-chunk 16, 32, 64, 128) and
 installs the fastest with fd_set_tile / fd_set_time_block.  Results are
 cached in a JSON file keyed by device, dimension, stencil and grid size, so a
 tuned configuration is reused by later runs; configurations tuned on MI355X

@@ -24,7 +24,14 @@ Also reported on the same line:
                 on the 601 x 301 workload, against the plain form (per-step
                 launches, full forward storage, shot after shot)
   variants      per-stencil Gpt-updates/s, each stencil's call alone
-  vol3d, ragged 512^3 volume per stencil; 64 ragged shots batched vs plain
+  vol3d, ragged 512^3 volume per stencil (with measured traffic where a
+                counter record matches); 64 ragged shots batched vs plain
+  fwi3d         3D FWI gradient (512^3 x 1000, gradient in m) with segment
+                and binomial checkpointing under two memory budgets
+  study         the Sec. 6 reference-solution study (homogeneous, two-layer)
+                at the paper's sizes: reference timing and per-scheme norms
+  dispersion    Appendix A gamma^F / gamma^W norms of the 1001^2 traces on the
+                GPU against the FP64 oracle on a few receivers
 """
 from __future__ import annotations
 

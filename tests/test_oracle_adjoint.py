@@ -73,3 +73,28 @@ def test_gradient_is_linear_in_residual():
     g2, _ = S.adjoint_gradient(st, v, c, dt, 100, 4, 100.0, src, q, rec, r2)
     g12, _ = S.adjoint_gradient(st, v, c, dt, 100, 4, 100.0, src, q, rec, 2 * r1 - 3 * r2)
     assert np.abs(g12 - (2 * g1 - 3 * g2)).max() <= 1e-12 * np.abs(g12).max()
+
+
+@pytest.mark.parametrize("ndim,shape,M,n,nt", [(2, "rhombus", 2, 34, 120), (3, "cross", 2, 16, 60)])
+def test_dot_product_of_the_linearised_map(ndim, shape, M, n, nt):
+    """<J dc, dd> = <dc, J^T dd> for the Jacobian J = d traces / d c: J^T dd is
+    the adjoint gradient driven by the residual dd, J dc the central
+    difference of the forward map along a smooth random direction dc over
+    every cell (error O(eps^2))."""
+    st, c, h, dt, q, src, rec = _setup(ndim, shape, M, n, nt, seed=17)
+    nb, eta = 4, 120.0
+    rng = np.random.default_rng(19)
+    dc = rng.standard_normal(c.shape)
+    for ax in range(ndim):   # smooth it (three passes of a 3-point average per axis)
+        for _ in range(3):
+            dc = (np.roll(dc, 1, ax) + dc + np.roll(dc, -1, ax)) / 3.0
+    dc *= 20.0 / np.abs(dc).max()
+    dd = rng.standard_normal((nt, len(rec)))
+    v = S.v_from_c(c, dt, h)
+    g, _ = S.adjoint_gradient(st, v, c, dt, nt, nb, eta, src, q, rec, dd)
+    eps = 1e-3
+    dp = S.forward(st, S.v_from_c(c + eps * dc, dt, h), dt, nt, nb, eta, src, q, rec)["traces"]
+    dm = S.forward(st, S.v_from_c(c - eps * dc, dt, h), dt, nt, nb, eta, src, q, rec)["traces"]
+    lhs = float(np.sum((dp - dm) / (2 * eps) * dd))
+    rhs = float(np.sum(dc * g))
+    assert abs(lhs - rhs) <= 1e-7 * abs(rhs), (lhs, rhs)

@@ -246,8 +246,8 @@ void launch_batch_inject(const BatchShot* shots, int nshots, int max_nrec, int f
                          hipStream_t s);
 // trace n of every shot from slot f
 void launch_batch_gather(const BatchShot* shots, int nshots, int max_nrec, int f, int n, hipStream_t s);
-bool launch_batch2d(const BatchArgs& a, int shape, int M, hipStream_t s);
-int batch_rows();
+bool launch_batch2d(const BatchArgs& a, int shape, int M, int rows, hipStream_t s);
+int batch_rows();   // rows per thread of the batched tiles (the adjoint's and the default)
 
 // Two-steps-per-launch 2D forward (out of place: u^{n-1}, u^n -> u^{n+1}, u^{n+2}).
 struct TbArgs {

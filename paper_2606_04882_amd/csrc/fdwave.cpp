@@ -572,6 +572,7 @@ struct CallCtx {
     // descriptor array and in the work list), each group on a branch
     struct Group {
         int shape, M;
+        int rows;                 // rows per thread of the group's tiles
         int d0, dn;               // descriptor range
         long long job0, njobs;    // work-list range
         long long maxn;           // largest window of the group
@@ -1171,7 +1172,7 @@ int enqueue_batched(const CallCtx& c, Recorder& R) {
         for (const CallCtx::Group& g : c.groups) {
             a.jobs = jobs + g.job0;
             a.njobs = (int)g.njobs;
-            ok = ok && launch_batch2d(a, g.shape, g.M, R.on(g.branch));
+            ok = ok && launch_batch2d(a, g.shape, g.M, g.rows, R.on(g.branch));
         }
         R.launched((int)c.groups.size());
     }
@@ -1234,7 +1235,7 @@ int enqueue_batched_adjoint(const CallCtx& c, Recorder& R) {
         for (const CallCtx::Group& g : c.groups) {
             f.jobs = jobs + g.job0;
             f.njobs = (int)g.njobs;
-            ok = ok && launch_batch2d(f, g.shape, g.M, R.on(g.branch));
+            ok = ok && launch_batch2d(f, g.shape, g.M, g.rows, R.on(g.branch));
         }
         R.launched((int)c.groups.size());
     };
@@ -1366,6 +1367,9 @@ void build_batch_blob(CallCtx& c, int mode) {
             CallCtx::Group g;
             g.shape = s.st.shape;
             g.M = s.st.M;
+            // forward calls of dense stencils tuned to 8 rows keep them; the
+            // adjoint's job list (shared with its recompute) stays at 4
+            g.rows = (mode == MODE_FORWARD && s.st.shape != SH_CROSS && s.st.rows == 8) ? 8 : batch_rows();
             g.d0 = k;
             g.dn = 0;
             g.job0 = (long long)jobs.size();
@@ -1385,7 +1389,7 @@ void build_batch_blob(CallCtx& c, int mode) {
         d.ldv = c.ldv_y;
         d.nx = s.nx;
         d.nz = s.nz;
-        d.ntiles = shot_tiles2d(*s.s, batch_rows(), &d.tiles_x);
+        d.ntiles = shot_tiles2d(*s.s, g.rows, &d.tiles_x);
         d.src = s.src;
         d.wavelet = s.s->wavelet;
         d.nrec = s.s->nrec;

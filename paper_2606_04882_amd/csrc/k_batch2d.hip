@@ -7,7 +7,8 @@
 // its (shot, tile) pair and runs the same tile body as the single-shot
 // kernels with that shot's parameters.  Kernels are compiled per variant, so
 // each group runs at its own register and LDS budget.  Tiles are 64 x 16 (4
-// rows per thread) for every shot.  Fields are named by slot in each shot's
+// rows per thread), or 64 x 32 for the forward steps of a dense-stencil
+// group whose stencil is tuned to 8 rows.  Fields are named by slot in each shot's
 // arena (see BatchShot), so forward, checkpoint, recompute and adjoint phases
 // of all shots of a group share one launch per step.
 #include "adj2d_body.h"
@@ -27,9 +28,9 @@ constexpr int kBatchRows = 4;
     CASE(SH_NSHAPE, 2) CASE(SH_NSHAPE, 3) CASE(SH_NSHAPE, 4) CASE(SH_NSHAPE, 5)                 \
     CASE(SH_NSHAPE, 6) CASE(SH_NSHAPE, 7) CASE(SH_NSHAPE, 8)
 
-template <int SH, int MM>
+template <int SH, int MM, int RY>
 __global__ __launch_bounds__(kBlock) void k_batch2d(BatchArgs p) {
-    __shared__ float tile[tile2d_floats<SH, MM, kBatchRows>()];
+    __shared__ float tile[tile2d_floats<SH, MM, RY>()];
     const int job = xcd_tile(blockIdx.x, p.njobs);
     const int2 jb = p.jobs[job];
     const BatchShot& s = p.shots[jb.x];
@@ -53,10 +54,10 @@ __global__ __launch_bounds__(kBlock) void k_batch2d(BatchArgs p) {
     tl.nz = s.nz;
     const int tz = lt / s.tiles_x;
     tl.x0 = (lt - tz * s.tiles_x) * kTileX;
-    tl.z0 = tz * 4 * kBatchRows;
+    tl.z0 = tz * 4 * RY;
     tl.src = s.src;
     tl.qs = s.src >= 0 ? p.q * s.wavelet[n] : 0.f;
-    fwd2d_tile<SH, MM, kBatchRows>(tl, p.sp, s.w, tile);
+    fwd2d_tile<SH, MM, RY>(tl, p.sp, s.w, tile);
 }
 
 template <int SH, int MM>
@@ -129,12 +130,26 @@ __global__ void k_batch_gather(const BatchShot* __restrict__ shots, int f, int n
 
 int batch_rows() { return kBatchRows; }
 
-bool launch_batch2d(const BatchArgs& a, int shape, int M, hipStream_t s) {
+bool launch_batch2d(const BatchArgs& a, int shape, int M, int rows, hipStream_t s) {
     if (a.njobs <= 0) return true;
+    if (rows == 8) {
+        if (shape == SH_CROSS) return false;
+        switch (shape * 8 + M - 1) {
+#define FDW_CASE(SH, MM)                                                                      \
+    case SH * 8 + MM - 1:                                                                     \
+        if constexpr (SH != SH_CROSS)                                                         \
+            hipLaunchKernelGGL((k_batch2d<SH, MM, 8>), dim3(a.njobs), dim3(kBlock), 0, s, a); \
+        return true;
+            FDW_SWITCH(FDW_CASE)
+#undef FDW_CASE
+            default: return false;
+        }
+    }
+    if (rows != kBatchRows) return false;
     switch (shape * 8 + M - 1) {
-#define FDW_CASE(SH, MM)                                                                  \
-    case SH * 8 + MM - 1:                                                                 \
-        hipLaunchKernelGGL((k_batch2d<SH, MM>), dim3(a.njobs), dim3(kBlock), 0, s, a);    \
+#define FDW_CASE(SH, MM)                                                                      \
+    case SH * 8 + MM - 1:                                                                     \
+        hipLaunchKernelGGL((k_batch2d<SH, MM, kBatchRows>), dim3(a.njobs), dim3(kBlock), 0, s, a); \
         return true;
         FDW_SWITCH(FDW_CASE)
 #undef FDW_CASE

@@ -611,12 +611,17 @@ def cpu_baseline(w, vel_np, budget_s):
             wo = W.specls(2, shape, M)
         offs, ws = W.expand(2, shape, M, wo)
         sts.append(S.Stencil(offs, ws))
-    # one step of each stencil to size the sample
-    t0 = time.perf_counter()
-    for st in sts:
-        S.forward(st, v, w.dt, 1, w.nb, w.eta_max, w.src, q[:1], w.rec)
-    one = time.perf_counter() - t0
-    nsteps = max(1, min(400, int(budget_s / max(one, 1e-3))))
+    # size the sample from calls of 1 and 4 steps per stencil: the marginal
+    # cost of a step of all eight stencils, and the fixed cost of a call
+    def _calls(n):
+        t0 = time.perf_counter()
+        for st in sts:
+            S.forward(st, v, w.dt, n, w.nb, w.eta_max, w.src, q[:n], w.rec)
+        return time.perf_counter() - t0
+    t1, t4 = _calls(1), _calls(4)
+    one = max((t4 - t1) / 3, 1e-3)
+    fixed = max(t1 - one, 0.0)
+    nsteps = max(1, min(2000, int((budget_s - fixed) / one)))
     t0 = time.perf_counter()
     for st in sts:
         S.forward(st, v, w.dt, nsteps, w.nb, w.eta_max, w.src, q[:nsteps], w.rec)

@@ -9,9 +9,9 @@
 
 namespace fdw {
 
-template <int M, int RY>
+template <int SHAPE, int M, int RY>
 constexpr int tile2d_floats_adj() {
-    return (4 * RY + 2 * M) * (kTileX + 2 * M);
+    return (4 * RY + 2 * M) * tile_pitch2d<SHAPE, M>();
 }
 
 struct AdjTile {
@@ -32,7 +32,7 @@ struct AdjTile {
 template <int SHAPE, int M, int RY>
 __device__ __forceinline__ void adj2d_tile(const AdjTile& t, const Sponge& sp, const Weights& W,
                                            float* tp, float* tu) {
-    constexpr int LW = kTileX + 2 * M;
+    constexpr int LW = tile_pitch2d<SHAPE, M>();
     const int tid = threadIdx.x, tx = tid & 63, ty = tid >> 6;
     const int gx = t.x0 + tx;
     const bool colok = gx < t.nx;
@@ -49,8 +49,8 @@ __device__ __forceinline__ void adj2d_tile(const AdjTile& t, const Sponge& sp, c
             if (t.with_grad) gg[j] = t.grad[(long long)gz * t.ldg + gx];
         }
     }
-    load_tile2d<M, RY>(tp, t.pcur, t.nx, t.nz, t.x0, t.z0);
-    if (t.with_grad) load_tile2d<M, RY>(tu, t.ufwd, t.nx, t.nz, t.x0, t.z0);
+    load_tile2d<M, RY, LW>(tp, t.pcur, t.nx, t.nz, t.x0, t.z0);
+    if (t.with_grad) load_tile2d<M, RY, LW>(tu, t.ufwd, t.nx, t.nz, t.x0, t.z0);
     __syncthreads();
 
     float pc[RY], lp[RY];

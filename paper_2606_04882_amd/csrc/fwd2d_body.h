@@ -21,13 +21,13 @@ struct Tile2D {
 
 template <int SHAPE, int M, int RY>
 constexpr int tile2d_floats() {
-    return (4 * RY + 2 * M) * (kTileX + 2 * M);
+    return (4 * RY + 2 * M) * tile_pitch2d<SHAPE, M>();
 }
 
 template <int SHAPE, int M, int RY>
 __device__ __forceinline__ void fwd2d_tile(const Tile2D& t, const Sponge& sp, const Weights& W,
                                            float* tile) {
-    constexpr int LW = kTileX + 2 * M;
+    constexpr int LW = tile_pitch2d<SHAPE, M>();
     const int tid = threadIdx.x, tx = tid & 63, ty = tid >> 6;
     // pointwise operands first, then the tile: all global loads in flight together
     const int gx = t.x0 + tx;
@@ -43,7 +43,7 @@ __device__ __forceinline__ void fwd2d_tile(const Tile2D& t, const Sponge& sp, co
             vv[j] = t.v[(long long)gz * t.ldv + gx];
         }
     }
-    load_tile2d<M, RY>(tile, t.ucur, t.nx, t.nz, t.x0, t.z0);
+    load_tile2d<M, RY, LW>(tile, t.ucur, t.nx, t.nz, t.x0, t.z0);
     __syncthreads();
 
     float uc[RY], acc[RY];

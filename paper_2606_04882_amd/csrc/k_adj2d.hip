@@ -17,7 +17,7 @@ namespace fdw {
 
 template <int SHAPE, int M, int RY>
 __global__ __launch_bounds__(kBlock) void k_adj2d(AdjArgs p) {
-    constexpr int N = tile2d_floats_adj<M, RY>();
+    constexpr int N = tile2d_floats_adj<SHAPE, M, RY>();
     __shared__ float tp[N];
     __shared__ float tu[N];
     const int t = xcd_tile(blockIdx.x, p.ntiles);

@@ -62,7 +62,7 @@ __global__ __launch_bounds__(kBlock) void k_batch2d(BatchArgs p) {
 
 template <int SH, int MM>
 __global__ __launch_bounds__(kBlock) void k_batch_adj2d(BatchAdjArgs p) {
-    constexpr int N = tile2d_floats_adj<MM, kBatchRows>();
+    constexpr int N = tile2d_floats_adj<SH, MM, kBatchRows>();
     __shared__ float tp[N];
     __shared__ float tu[N];
     const int job = xcd_tile(blockIdx.x, p.njobs);

@@ -206,11 +206,24 @@ __device__ __forceinline__ void stencil2d(const float* tile, int tx, int ty, con
     }
 }
 
+// Row pitch (floats) of a 2D LDS tile.  The square and N-shape kernels, whose
+// column loop runs over a run-time offset, pad the rows to 128 floats, a
+// multiple of 64 dwords: the reads of one column at successive rows then share
+// one address register (row offsets fit the st64 form of the paired LDS read)
+// instead of taking a new one every third row (square M8: 2 instead of 20
+// address additions per column, 10.33 -> 10.09 us per 1001^2 step).  The
+// rhombus bodies, compiled per column offset, are faster unpadded (8.35 vs
+// 9.17 us at M8), as are the crosses.
+template <int SHAPE, int M>
+constexpr int tile_pitch2d() {
+    return (SHAPE == SH_SQUARE || SHAPE == SH_NSHAPE) ? 128 : kTileX + 2 * M;
+}
+
 // Cooperative load of the (4*RY + 2M) x (64 + 2M) tile of field f (window
-// nx x nz, dense rows) with zeros beyond the window.  All of a thread's global
-// loads are issued before any LDS store, so their latencies overlap instead of
-// adding up.
-template <int M, int RY>
+// nx x nz, dense rows) with zeros beyond the window, rows LP floats apart.
+// All of a thread's global loads are issued before any LDS store, so their
+// latencies overlap instead of adding up.
+template <int M, int RY, int LP = kTileX + 2 * M>
 __device__ __forceinline__ void load_tile2d(float* tile, const float* __restrict__ f, int nx,
                                             int nz, int x0, int z0) {
     constexpr int LW = kTileX + 2 * M, LH = 4 * RY + 2 * M, N = LH * LW;
@@ -228,7 +241,8 @@ __device__ __forceinline__ void load_tile2d(float* tile, const float* __restrict
 #pragma unroll
     for (int k = 0; k < NL; ++k) {
         const int i = threadIdx.x + k * kBlock;
-        if (i < N) tile[i] = val[k];
+        const int r = i / LW, c = i - r * LW;
+        if (i < N) tile[r * LP + c] = val[k];
     }
 }
 

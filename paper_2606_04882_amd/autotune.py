@@ -3,7 +3,7 @@
 For a stencil on a given grid, times a short forward run for every compiled
 configuration (2D: rows per thread 2, 4, 8, and for crosses also two time
 steps per launch and the z-marching kernel with chunks of 16-48 rows; 3D:
-rows 1, 2, 4 times z-chunk 16, 32, 64, 128) and
+rows 1, 2, 4 times z-chunk 16, 32, 64, 128, 256) and
 installs the fastest with fd_set_tile / fd_set_time_block.  Results are
 cached in a JSON file keyed by device, dimension, stencil and grid size, so a
 tuned configuration is reused by later runs; configurations tuned on MI355X
@@ -39,7 +39,7 @@ def candidates(ndim: int, shape: str, M: int) -> List[Tuple[int, int, int]]:
             c += [(1, z, 1) for z in (16, 24, 32, 48)]
         return c
     rows = (1, 2, 4) if shape == "cross" else ((1, 2) if M <= 4 else (1,))
-    return [(r, z, 1) for r in rows for z in (16, 32, 64, 128)]
+    return [(r, z, 1) for r in rows for z in (16, 32, 64, 128, 256)]
 
 
 def device_tag() -> str:

@@ -1814,7 +1814,7 @@ int fd_weights_set_n(int ndim, int shape, int M, int N, const double* w, int nw,
     }
     st.cfl = 2.0 / std::sqrt(mneg);
     st.rows = default_rows(ndim, ks, M);
-    st.zchunk = (ndim == 3 && ks == SH_CROSS) ? 128 : 64;
+    st.zchunk = (ndim == 3 && ks == SH_CROSS) ? 256 : 64;
     st.tsteps = (ndim == 2 && have_fwd2d_tb(ks, M, st.rows)) ? 2 : 1;
     std::lock_guard<std::mutex> lk(g_mu);
     for (size_t i = 0; i < g_stencils.size(); ++i) {

@@ -221,28 +221,51 @@ constexpr int tile_pitch2d() {
 
 // Cooperative load of the (4*RY + 2M) x (64 + 2M) tile of field f (window
 // nx x nz, dense rows) with zeros beyond the window, rows LP floats apart.
-// All of a thread's global loads are issued before any LDS store, so their
-// latencies overlap instead of adding up.
+// Thread (tx, ty) loads column x0 + tx at rows ty, ty + 4, ... (one address
+// step of 4 rows per load, coalesced along x); the 2M halo columns are
+// spread over the block.  All of a thread's global loads are issued before
+// any LDS store, so their latencies overlap instead of adding up.
 template <int M, int RY, int LP = kTileX + 2 * M>
 __device__ __forceinline__ void load_tile2d(float* tile, const float* __restrict__ f, int nx,
                                             int nz, int x0, int z0) {
-    constexpr int LW = kTileX + 2 * M, LH = 4 * RY + 2 * M, N = LH * LW;
-    constexpr int NL = (N + kBlock - 1) / kBlock;
-    float val[NL];
+    constexpr int LH = 4 * RY + 2 * M;
+    constexpr int NR = (LH + 3) / 4;                       // rows per thread, main columns
+    constexpr int NH = 2 * M * LH;                         // halo cells
+    constexpr int NHL = (NH + kBlock - 1) / kBlock;        // halo cells per thread
+    const int tid = threadIdx.x, tx = tid & 63, ty = tid >> 6;
+    const int gx = x0 + tx;
+    const bool xok = gx < nx;
+    const long long step = 4LL * nx;
+    const float* p = f + (long long)(z0 - M + ty) * nx + gx;
+    float val[NR];
 #pragma unroll
-    for (int k = 0; k < NL; ++k) {
-        const int i = threadIdx.x + k * kBlock;
-        const int r = i / LW, c = i - r * LW;
-        const int gz = z0 - M + r, gx = x0 - M + c;
+    for (int k = 0; k < NR; ++k) {
+        const int r = ty + 4 * k, gz = z0 - M + r;
         val[k] = 0.f;
-        if (i < N && (unsigned)gz < (unsigned)nz && (unsigned)gx < (unsigned)nx)
-            val[k] = f[(long long)gz * nx + gx];
+        if ((NR * 4 == LH || r < LH) && xok && (unsigned)gz < (unsigned)nz) val[k] = p[k * step];
+    }
+    float hv[NHL];
+    int hoff[NHL];
+#pragma unroll
+    for (int k = 0; k < NHL; ++k) {
+        const int i = tid + k * kBlock;
+        const int r = i / (2 * M), h = i - r * (2 * M);
+        const int c = h < M ? h : kTileX + h;              // tile column
+        const int gz = z0 - M + r, hx = x0 - M + c;
+        hv[k] = 0.f;
+        hoff[k] = r * LP + c;
+        if ((NHL * kBlock == NH || i < NH) && (unsigned)gz < (unsigned)nz && (unsigned)hx < (unsigned)nx)
+            hv[k] = f[(long long)gz * nx + hx];
     }
 #pragma unroll
-    for (int k = 0; k < NL; ++k) {
-        const int i = threadIdx.x + k * kBlock;
-        const int r = i / LW, c = i - r * LW;
-        if (i < N) tile[r * LP + c] = val[k];
+    for (int k = 0; k < NR; ++k) {
+        const int r = ty + 4 * k;
+        if (NR * 4 == LH || r < LH) tile[r * LP + tx + M] = val[k];
+    }
+#pragma unroll
+    for (int k = 0; k < NHL; ++k) {
+        const int i = tid + k * kBlock;
+        if (NHL * kBlock == NH || i < NH) tile[hoff[k]] = hv[k];
     }
 }
 

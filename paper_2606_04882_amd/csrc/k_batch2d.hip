@@ -57,7 +57,7 @@ __global__ __launch_bounds__(kBlock) void k_batch2d(BatchArgs p) {
     tl.z0 = tz * 4 * RY;
     tl.src = s.src;
     tl.qs = s.src >= 0 ? p.q * s.wavelet[n] : 0.f;
-    fwd2d_tile<SH, MM, RY>(tl, p.sp, s.w, tile);
+    fwd2d_tile<SH, MM, RY, true>(tl, p.sp, s.w, tile);
 }
 
 template <int SH, int MM>

@@ -8,7 +8,7 @@
 // kernels with that shot's parameters.  Kernels are compiled per variant, so
 // each group runs at its own register and LDS budget.  Tiles are 64 x 16 (4
 // rows per thread), or 64 x 32 for the forward steps of a dense-stencil
-// group whose stencil is tuned to 8 rows.  Fields are named by slot in each shot's
+// group.  Fields are named by slot in each shot's
 // arena (see BatchShot), so forward, checkpoint, recompute and adjoint phases
 // of all shots of a group share one launch per step.
 #include "adj2d_body.h"

@@ -246,3 +246,53 @@ def test_batched_dense_groups_at_eight_rows(F):
     assert rel_l2(gb.cpu().numpy(), gs.cpu().numpy()) <= 1e-5
     for sid in dense:
         F.fd_set_tile(sid, 4)
+
+
+@pytest.mark.parametrize("nb", [0, 5])
+def test_batched_sources_at_segment_edges(F, nb):
+    """Sources on the first and last rows of threads' row segments and tiles
+    (z = 0, 3, 4, 15, 16, 31, 32, last; x = 0, 63, 64, last), windows with
+    ragged edges, with and without the damping band: the batched forward
+    (whose interior threads take a separate store path) equals the
+    shot-after-shot path bitwise in the traces and the final fields, and one
+    shot per stencil matches the oracle."""
+    from tests.fdcase import layered
+    NZ, NX, h, nt = 90, 200, 10.0, 60
+    model = layered((NZ, NX), seed=5)
+    vmax = float(model.max())
+    dt = 0.5 * 0.4 * h / vmax
+    eta = synth.sponge_eta_max(vmax, nb, h) if nb else 0.0
+    stencils = [("taylor", "cross", 4), ("specls", "square", 3), ("dispte", "rhombus", 4)]
+    sids = [F.fd_weights_set(2, sh, M, oracle_weights(2, sc, sh, M, 0.4)) for sc, sh, M in stencils]
+    wav_np = synth.ricker(nt, dt, 25.0)
+    wav = torch.tensor(wav_np.astype(np.float32), device=DEV)
+    ex, ez = 131, 77
+    srcs = [(x, z) for z in (0, 3, 4, 15, 16, 31, 32, ez - 1) for x in (0, 63, 64, ex - 1)]
+    shots, specs = [], []
+    for k, (sx, sz) in enumerate(srcs):
+        sid = sids[k % len(sids)]
+        ox, oz = (k * 7) % (NX - ex), (k * 3) % (NZ - ez)
+        rz = sz + 4 if sz + 4 < ez else sz - 4
+        rec = np.array([[x, rz] for x in range(0, ex, 5)], dtype=np.int32)
+        shots.append(F.Shot(stencil_id=sid, src=(sx, sz), wavelet=wav, rec=torch.tensor(rec, device=DEV),
+                            traces=torch.zeros(nt, len(rec), device=DEV), origin=(ox, 0, oz), extent=(ex, 1, ez),
+                            final=(torch.zeros(ez, ex, device=DEV), torch.zeros(ez, ex, device=DEV))))
+        specs.append((k % len(sids), ox, oz, (sx, sz), rec))
+    vel = torch.tensor(model, device=DEV)
+    g = F.Grid(shape=model.shape, h=h, dt=dt, nt=nt, nb=nb, eta_max=eta, vmax=vmax)
+    F.fd_forward(g, vel, shots)
+    torch.cuda.synchronize()
+    batched = [(s.traces.clone(), s.final[1].clone()) for s in shots]
+    g1 = F.Grid(shape=model.shape, h=h, dt=dt, nt=nt, nb=nb, eta_max=eta, vmax=vmax, flags=F.FD_NO_BATCH)
+    F.fd_forward(g1, vel, shots)
+    torch.cuda.synchronize()
+    for (t, u), s in zip(batched, shots):
+        assert torch.equal(t, s.traces) and torch.equal(u, s.final[1])
+        assert t.abs().max() > 0 and u.abs().max() > 0
+    for k in range(len(stencils)):
+        i, ox, oz, src, rec = specs[k + 4]   # sources on row 3
+        sc, sh, M = stencils[i]
+        crop = np.ascontiguousarray(model[oz:oz + ez, ox:ox + ex])
+        ref = oracle_traces(2, sh, M, oracle_weights(2, sc, sh, M, 0.4), crop, h, dt, nt, nb, eta, src,
+                            wav_np, rec)
+        assert rel_l2(batched[k + 4][0].cpu().numpy(), ref["traces"]) <= 1e-5

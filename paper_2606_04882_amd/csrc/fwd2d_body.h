@@ -45,18 +45,17 @@ __device__ __forceinline__ void fwd2d_tile(const Tile2D& t, const Sponge& sp, co
     const long long base = (long long)zr * t.nx + gx;   // window-linear index of that row
     float up[RY], vv[RY];
     {
-        const float* pu = t.uprev + base;
-        const float* pv = t.v + (long long)zr * t.ldv + gx;
+        long long iu = base, iv = (long long)zr * t.ldv + gx;   // row indices, stepped per row
 #pragma unroll
         for (int j = 0; j < RY; ++j) {
             up[j] = 0.f;
             vv[j] = 0.f;
             if (colok && j < nrow) {
-                up[j] = *pu;
-                vv[j] = *pv;
+                up[j] = t.uprev[iu];
+                vv[j] = t.v[iv];
             }
-            pu += t.nx;
-            pv += t.ldv;
+            iu += t.nx;
+            iv += t.ldv;
         }
     }
     load_tile2d<M, RY, LW>(tile, t.ucur, t.nx, t.nz, t.x0, t.z0);
@@ -68,17 +67,17 @@ __device__ __forceinline__ void fwd2d_tile(const Tile2D& t, const Sponge& sp, co
 
     const int dxb = sp.nb > 0 ? band_depth(gx, t.nx, sp.nb) : 0;
     if constexpr (SPLIT) {
-        // the source lies in this thread's column segment iff src - base is a
-        // multiple of nx below RY nx (tested per row only in that thread)
+        // a source less than RY rows after the thread's first point (in any
+        // column) sends the thread through the per-row loop, which tests
+        // each of its points
         const long long srel = t.src - base;
         const bool has_src = t.src >= 0 && srel >= 0 && srel < (long long)RY * t.nx;
         const bool interior = sp.nb == 0 || (dxb == 0 && zr >= sp.nb && zr + RY <= t.nz - sp.nb);
         if (interior && !has_src) {
-            float* pn = t.unext + base;
 #pragma unroll
             for (int j = 0; j < RY; ++j) {
                 if (j >= nrow) break;
-                pn[(long long)j * t.nx] = fmaf(vv[j], acc[j], 2.f * uc[j] - up[j]);
+                t.unext[base + (long long)j * t.nx] = fmaf(vv[j], acc[j], 2.f * uc[j] - up[j]);
             }
             return;
         }

@@ -221,7 +221,7 @@ constexpr int tile_pitch2d() {
 
 // Cooperative load of the (4*RY + 2M) x (64 + 2M) tile of field f (window
 // nx x nz, dense rows) with zeros beyond the window, rows LP floats apart.
-// Thread (tx, ty) loads column x0 + tx at rows ty, ty + 4, ... (one address
+// Thread (tx, ty) loads column x0 + tx at rows ty, ty + 4, ... (one index
 // step of 4 rows per load, coalesced along x); the 2M halo columns are
 // spread over the block.  All of a thread's global loads are issued before
 // any LDS store, so their latencies overlap instead of adding up.
@@ -236,13 +236,14 @@ __device__ __forceinline__ void load_tile2d(float* tile, const float* __restrict
     const int gx = x0 + tx;
     const bool xok = gx < nx;
     const long long step = 4LL * nx;
-    const float* p = f + (long long)(z0 - M + ty) * nx + gx;
+    long long idx = (long long)(z0 - M + ty) * nx + gx;   // index of the thread's k-th row
     float val[NR];
 #pragma unroll
     for (int k = 0; k < NR; ++k) {
         const int r = ty + 4 * k, gz = z0 - M + r;
         val[k] = 0.f;
-        if ((NR * 4 == LH || r < LH) && xok && (unsigned)gz < (unsigned)nz) val[k] = p[k * step];
+        if ((NR * 4 == LH || r < LH) && xok && (unsigned)gz < (unsigned)nz) val[k] = f[idx];
+        idx += step;
     }
     float hv[NHL];
     int hoff[NHL];

@@ -296,3 +296,44 @@ def test_batched_sources_at_segment_edges(F, nb):
         ref = oracle_traces(2, sh, M, oracle_weights(2, sc, sh, M, 0.4), crop, h, dt, nt, nb, eta, src,
                             wav_np, rec)
         assert rel_l2(batched[k + 4][0].cpu().numpy(), ref["traces"]) <= 1e-5
+
+
+@pytest.mark.parametrize("nt", [1, 2, 3, 4, 37, 60])
+def test_batched_forward_any_nt(F, nt):
+    """Batched forward with odd and even step counts (1 to 60): the traces,
+    including the last rows gathered after the step loop, and both final
+    fields equal the shot-after-shot path bitwise (where the cross stencils
+    run two steps per launch), for cross and dense groups."""
+    from tests.fdcase import layered
+    NZ, NX, h = 70, 150, 10.0
+    model = layered((NZ, NX), seed=9)
+    vmax = float(model.max())
+    dt = 0.5 * 0.4 * h / vmax
+    nb = 4
+    eta = synth.sponge_eta_max(vmax, nb, h)
+    sids = [F.fd_weights_set(2, "cross", 4, oracle_weights(2, "taylor", "cross", 4)),
+            F.fd_weights_set(2, "cross", 7, oracle_weights(2, "taylor", "cross", 7)),
+            F.fd_weights_set(2, "square", 2, oracle_weights(2, "specls", "square", 2))]
+    wav = torch.tensor(synth.ricker(nt, dt, 40.0, t0=0.0).astype(np.float32), device=DEV)
+    shots = []
+    for k in range(7):
+        ex, ez = 70 + 9 * k, 40 + 4 * k
+        ox, oz = (11 * k) % (NX - ex), (5 * k) % (NZ - ez)
+        sx, sz = 3 + 7 * k, 2 + 3 * k
+        rec = np.array([[x, min(sz + 1, ez - 1)] for x in range(0, ex, 3)], dtype=np.int32)
+        shots.append(F.Shot(stencil_id=sids[k % 3], src=(sx, sz), wavelet=wav, rec=torch.tensor(rec, device=DEV),
+                            traces=torch.zeros(nt, len(rec), device=DEV), origin=(ox, 0, oz), extent=(ex, 1, ez),
+                            final=(torch.zeros(ez, ex, device=DEV), torch.zeros(ez, ex, device=DEV))))
+    vel = torch.tensor(model, device=DEV)
+    g = F.Grid(shape=model.shape, h=h, dt=dt, nt=nt, nb=nb, eta_max=eta, vmax=vmax)
+    F.fd_forward(g, vel, shots)
+    torch.cuda.synchronize()
+    batched = [(s.traces.clone(), s.final[0].clone(), s.final[1].clone()) for s in shots]
+    g1 = F.Grid(shape=model.shape, h=h, dt=dt, nt=nt, nb=nb, eta_max=eta, vmax=vmax, flags=F.FD_NO_BATCH)
+    for s in shots:
+        s.traces.fill_(3.0)
+    F.fd_forward(g1, vel, shots)
+    torch.cuda.synchronize()
+    for (t, u0, u1), s in zip(batched, shots):
+        assert torch.equal(t, s.traces) and torch.equal(u0, s.final[0]) and torch.equal(u1, s.final[1])
+        assert u1.abs().max() > 0

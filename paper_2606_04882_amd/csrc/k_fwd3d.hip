@@ -440,30 +440,55 @@ struct RingLDS {
 };
 
 // Registers holding one whole plane (interior and halo) between its global
-// loads and its LDS store.
+// loads and its LDS store.  Thread (tx, ty) holds column x0 + tx at rows ty,
+// ty + 8, ... (one index step of 8 rows per load, coalesced along x); the 2M
+// halo columns are spread over the block.
 template <int M, int RY>
 struct PlaneRegs {
-    static constexpr int N = Geo3<M, RY>::PLANE, LW = Geo3<M, RY>::LW;
-    static constexpr int NL = (N + kBlock3 - 1) / kBlock3;
-    float val[NL];
+    static constexpr int LW = Geo3<M, RY>::LW, LH = Geo3<M, RY>::LH;
+    static constexpr int NR = (LH + kWaves3 - 1) / kWaves3;   // rows per thread, main columns
+    static constexpr int NH = 2 * M * LH;                      // halo cells
+    static constexpr int NHL = (NH + kBlock3 - 1) / kBlock3;   // halo cells per thread
+    float val[NR];
+    float hv[NHL];
     __device__ __forceinline__ void fetch(const float* __restrict__ f, int nx, int ny, int nz, int x0,
                                           int y0, int z) {
         const bool zok = (unsigned)z < (unsigned)nz;
+        const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+        const int gx = x0 + tx;
+        const bool xok = zok && gx < nx;
+        long long idx = ((long long)z * ny + (y0 - M + ty)) * nx + gx;   // the thread's k-th row
+        const long long step = (long long)kWaves3 * nx;
 #pragma unroll
-        for (int k = 0; k < NL; ++k) {
-            const int i = threadIdx.x + k * kBlock3;
-            const int r = i / LW, c = i - r * LW;
-            const int gy = y0 - M + r, gx = x0 - M + c;
+        for (int k = 0; k < NR; ++k) {
+            const int r = ty + kWaves3 * k, gy = y0 - M + r;
             val[k] = 0.f;
-            if (i < N && zok && (unsigned)gy < (unsigned)ny && (unsigned)gx < (unsigned)nx)
-                val[k] = f[((long long)z * ny + gy) * nx + gx];
+            if ((NR * kWaves3 == LH || r < LH) && xok && (unsigned)gy < (unsigned)ny) val[k] = f[idx];
+            idx += step;
+        }
+#pragma unroll
+        for (int k = 0; k < NHL; ++k) {
+            const int i = threadIdx.x + k * kBlock3;
+            const int r = i / (2 * M), h = i - r * (2 * M);
+            const int c = h < M ? h : kTileX + h;
+            const int gy = y0 - M + r, hx = x0 - M + c;
+            hv[k] = 0.f;
+            if ((NHL * kBlock3 == NH || i < NH) && zok && (unsigned)gy < (unsigned)ny && (unsigned)hx < (unsigned)nx)
+                hv[k] = f[((long long)z * ny + gy) * nx + hx];
         }
     }
     __device__ __forceinline__ void store(float* tile) const {
+        const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
 #pragma unroll
-        for (int k = 0; k < NL; ++k) {
+        for (int k = 0; k < NR; ++k) {
+            const int r = ty + kWaves3 * k;
+            if (NR * kWaves3 == LH || r < LH) tile[r * LW + tx + M] = val[k];
+        }
+#pragma unroll
+        for (int k = 0; k < NHL; ++k) {
             const int i = threadIdx.x + k * kBlock3;
-            if (i < N) tile[i] = val[k];
+            const int r = i / (2 * M), h = i - r * (2 * M);
+            if (NHL * kBlock3 == NH || i < NH) tile[r * LW + (h < M ? h : kTileX + h)] = hv[k];
         }
     }
 };

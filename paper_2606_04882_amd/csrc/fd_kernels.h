@@ -312,7 +312,7 @@ bool launch_adj3d(const AdjArgs& a, int shape, int M, int rows, hipStream_t s);
 bool have_fwd2d(int shape, int M, int rows);
 bool have_fwd3d(int shape, int M, int rows);
 bool have_adj3d(int shape, int M);
-int adj_rows3d(int shape, int fwd_rows);  // tile height the 3D adjoint runs with
+int adj_rows3d(int shape, int M, int fwd_rows);  // tile height the 3D adjoint runs with
 
 // Small helper kernels (k_misc.hip).
 void launch_vprep(const float* vel, float* v, long long n, double dt_over_h, int* flags,

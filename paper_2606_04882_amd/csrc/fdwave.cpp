@@ -810,7 +810,7 @@ int enqueue_forward_shot(const CallCtx& c, const ShotCtx& s, float* ckpt, int K,
 // the 2D marching forward kernel (rows 1) has no adjoint twin: the 2D
 // adjoint then runs its tiled kernel at 4 rows per thread
 int adj_rows(const CallCtx& c, const ShotCtx& s) {
-    return c.g->ndim == 3 ? adj_rows3d(s.st.shape, s.st.rows) : (s.st.rows == 1 ? 4 : s.st.rows);
+    return c.g->ndim == 3 ? adj_rows3d(s.st.shape, s.st.M, s.st.rows) : (s.st.rows == 1 ? 4 : s.st.rows);
 }
 
 // gscale of grad_factor for the call's gradient parameter

@@ -61,7 +61,6 @@ __global__ __launch_bounds__(kBlock) void k_fwd2d_tb(TbArgs p) {
     constexpr int TY = 4 * RY;
     constexpr int W0 = kTileX + 4 * M, H0 = TY + 4 * M, N0 = W0 * H0;   // u^n
     constexpr int W1 = kTileX + 2 * M, H1 = TY + 2 * M, N1 = W1 * H1;   // u^{n+1}
-    constexpr int NL0 = (N0 + kBlock - 1) / kBlock, NL1 = (N1 + kBlock - 1) / kBlock;
     __shared__ float U0[N0];
     __shared__ float U1[N1];
     const int tid = threadIdx.x, tx = tid & 63, ty = tid >> 6;
@@ -79,62 +78,104 @@ __global__ __launch_bounds__(kBlock) void k_fwd2d_tb(TbArgs p) {
     const float qs0 = p.src >= 0 ? p.q * p.wavelet[p.step] : 0.f;
     const float qs1 = p.src >= 0 ? p.q * p.wavelet[p.step + 1] : 0.f;
 
+    // Cells are taken column-wise: thread (tx, ty) owns the tile's column tx at
+    // rows ty, ty + 4, ... (one index step per row), and the halo columns of a
+    // region are spread over the block.
+    constexpr int NR1 = (H1 + 3) / 4, NH1 = 2 * M * H1, NHL1 = (NH1 + kBlock - 1) / kBlock;   // step-1 region
+    constexpr int NR0 = (H0 + 3) / 4, NH0 = 4 * M * H0, NHL0 = (NH0 + kBlock - 1) / kBlock;   // u^n tile
+    const int gx = x0 + tx;
+    const bool xok = gx < p.nx;
+
     // all global loads first: u^{n-1}, v on the step-1 region, v on the tile, u^n with 2M halo
-    float up1[NL1], vv1[NL1];
+    float up1[NR1 + NHL1], vv1[NR1 + NHL1];
+    {
+        long long iu = (long long)(z0 - M + ty) * p.nx + gx, iv = (long long)(z0 - M + ty) * p.ldv + gx;
 #pragma unroll
-    for (int k = 0; k < NL1; ++k) {
-        const int i = tid + k * kBlock;
-        const int r = i / W1, c = i - r * W1;
-        const int gz = z0 - M + r, gx = x0 - M + c;
-        up1[k] = 0.f;
-        vv1[k] = 0.f;
-        if (i < N1 && (unsigned)gz < (unsigned)p.nz && (unsigned)gx < (unsigned)p.nx) {
-            up1[k] = p.uprev[(long long)gz * p.nx + gx];
-            vv1[k] = p.v[(long long)gz * p.ldv + gx];
+        for (int k = 0; k < NR1; ++k) {
+            const int r = ty + 4 * k, gz = z0 - M + r;
+            up1[k] = 0.f;
+            vv1[k] = 0.f;
+            if ((NR1 * 4 == H1 || r < H1) && xok && (unsigned)gz < (unsigned)p.nz) {
+                up1[k] = p.uprev[iu];
+                vv1[k] = p.v[iv];
+            }
+            iu += 4LL * p.nx;
+            iv += 4LL * p.ldv;
+        }
+#pragma unroll
+        for (int k = 0; k < NHL1; ++k) {
+            const int i = tid + k * kBlock;
+            const int r = i / (2 * M), h = i - r * (2 * M);
+            const int gz = z0 - M + r, hx = x0 - M + (h < M ? h : kTileX + h);
+            up1[NR1 + k] = 0.f;
+            vv1[NR1 + k] = 0.f;
+            if ((NHL1 * kBlock == NH1 || i < NH1) && (unsigned)gz < (unsigned)p.nz && (unsigned)hx < (unsigned)p.nx) {
+                up1[NR1 + k] = p.uprev[(long long)gz * p.nx + hx];
+                vv1[NR1 + k] = p.v[(long long)gz * p.ldv + hx];
+            }
         }
     }
-    const int gx = x0 + tx;
     float vv2[RY];
 #pragma unroll
     for (int j = 0; j < RY; ++j) {
         const int gz = z0 + ty * RY + j;
-        vv2[j] = (gx < p.nx && gz < p.nz) ? p.v[(long long)gz * p.ldv + gx] : 0.f;
+        vv2[j] = (xok && gz < p.nz) ? p.v[(long long)gz * p.ldv + gx] : 0.f;
     }
     {
-        float val[NL0];
+        float val[NR0], hv[NHL0];
+        long long iu = (long long)(z0 - 2 * M + ty) * p.nx + gx;
 #pragma unroll
-        for (int k = 0; k < NL0; ++k) {
-            const int i = tid + k * kBlock;
-            const int r = i / W0, c = i - r * W0;
-            const int gz = z0 - 2 * M + r, gxx = x0 - 2 * M + c;
+        for (int k = 0; k < NR0; ++k) {
+            const int r = ty + 4 * k, gz = z0 - 2 * M + r;
             val[k] = 0.f;
-            if (i < N0 && (unsigned)gz < (unsigned)p.nz && (unsigned)gxx < (unsigned)p.nx)
-                val[k] = p.ucur[(long long)gz * p.nx + gxx];
+            if ((NR0 * 4 == H0 || r < H0) && xok && (unsigned)gz < (unsigned)p.nz) val[k] = p.ucur[iu];
+            iu += 4LL * p.nx;
         }
 #pragma unroll
-        for (int k = 0; k < NL0; ++k) {
+        for (int k = 0; k < NHL0; ++k) {
             const int i = tid + k * kBlock;
-            if (i < N0) U0[i] = val[k];
+            const int r = i / (4 * M), h = i - r * (4 * M);
+            const int gz = z0 - 2 * M + r, hx = x0 - 2 * M + (h < 2 * M ? h : kTileX + h);
+            hv[k] = 0.f;
+            if ((NHL0 * kBlock == NH0 || i < NH0) && (unsigned)gz < (unsigned)p.nz && (unsigned)hx < (unsigned)p.nx)
+                hv[k] = p.ucur[(long long)gz * p.nx + hx];
+        }
+#pragma unroll
+        for (int k = 0; k < NR0; ++k) {
+            const int r = ty + 4 * k;
+            if (NR0 * 4 == H0 || r < H0) U0[r * W0 + tx + 2 * M] = val[k];
+        }
+#pragma unroll
+        for (int k = 0; k < NHL0; ++k) {
+            const int i = tid + k * kBlock;
+            const int r = i / (4 * M), h = i - r * (4 * M);
+            if (NHL0 * kBlock == NH0 || i < NH0) U0[r * W0 + (h < 2 * M ? h : kTileX + h)] = hv[k];
         }
     }
     __syncthreads();
 
     // step n: u^{n+1} on the tile plus an M halo (zero outside the window)
-#pragma unroll
-    for (int k = 0; k < NL1; ++k) {
-        const int i = tid + k * kBlock;
-        if (i < N1) {
-            const int r = i / W1, c = i - r * W1;
-            const int gz = z0 - M + r, gxx = x0 - M + c;
-            float out = 0.f;
-            if ((unsigned)gz < (unsigned)p.nz && (unsigned)gxx < (unsigned)p.nx) {
-                float uc;
-                const float L = point_cross<M, W0>(U0, r + M, c + M, p.w, uc);
-                const long long kk = (long long)gz * p.nx + gxx;
-                out = leapfrog(uc, up1[k], vv1[k], L, gxx, gz, p.nx, p.nz, p.sp, kk == p.src, qs0);
-            }
-            U1[i] = out;
+    auto step1 = [&](int r, int c, float up, float vv) {
+        const int gz = z0 - M + r, gxx = x0 - M + c;
+        float out = 0.f;
+        if ((unsigned)gz < (unsigned)p.nz && (unsigned)gxx < (unsigned)p.nx) {
+            float uc;
+            const float L = point_cross<M, W0>(U0, r + M, c + M, p.w, uc);
+            const long long kk = (long long)gz * p.nx + gxx;
+            out = leapfrog(uc, up, vv, L, gxx, gz, p.nx, p.nz, p.sp, kk == p.src, qs0);
         }
+        U1[r * W1 + c] = out;
+    };
+#pragma unroll
+    for (int k = 0; k < NR1; ++k) {
+        const int r = ty + 4 * k;
+        if (NR1 * 4 == H1 || r < H1) step1(r, tx + M, up1[k], vv1[k]);
+    }
+#pragma unroll
+    for (int k = 0; k < NHL1; ++k) {
+        const int i = tid + k * kBlock;
+        const int r = i / (2 * M), h = i - r * (2 * M);
+        if (NHL1 * kBlock == NH1 || i < NH1) step1(r, h < M ? h : kTileX + h, up1[NR1 + k], vv1[NR1 + k]);
     }
     __syncthreads();
 

@@ -48,53 +48,65 @@ __device__ __forceinline__ float damp_e(const Sponge& sp, int gx, int gy, int gz
 
 // Halo of plane z of field f (interior cells excluded), zeros off the grid,
 // in two halves so that the loads of the next plane can be in flight while
-// the current plane is computed: fetch_halo issues the global loads into
-// registers, store_halo writes them to LDS.
+// the current plane is computed: fetch issues the global loads into
+// registers, store writes them to LDS.  The ring is taken as the tile's 64
+// columns on the M rows above and below it (thread (tx, ty) holds column tx
+// at ring rows ty, ty + 8, ...) and the 2M side columns over every row of the
+// plane, spread over the block.
 template <int M, int RY>
 struct Halo {
-    static constexpr int LW = Geo3<M, RY>::LW;
-    static constexpr int TOPN = M * LW, SIDEN = kWaves3 * RY * M, H = 2 * TOPN + 2 * SIDEN;
-    static constexpr int NL = (H + kBlock3 - 1) / kBlock3;
-    float val[NL];
+    static constexpr int LW = Geo3<M, RY>::LW, LH = Geo3<M, RY>::LH;
+    static constexpr int NT = (2 * M + kWaves3 - 1) / kWaves3;   // top/bottom cells per thread
+    static constexpr int NS = 2 * M * LH;                          // side-column cells
+    static constexpr int NSL = (NS + kBlock3 - 1) / kBlock3;       // side cells per thread
+    float top[NT];
+    float side[NSL];
 
-    __device__ __forceinline__ static int pos(int i, int& r, int& c) {
-        if (i < TOPN) {
-            r = i / LW;
-            c = i - r * LW;
-        } else if (i < 2 * TOPN) {
-            const int q = i - TOPN;
-            r = M + kWaves3 * RY + q / LW;
-            c = q % LW;
-        } else {
-            int q = i - 2 * TOPN;
-            const int side = q / SIDEN;
-            q -= side * SIDEN;
-            r = M + q / M;
-            c = (side ? M + kTileX : 0) + q % M;
-        }
-        return r * LW + c;
+    // plane row of ring row q (0..2M-1): the M rows above, then the M below the tile
+    __device__ __forceinline__ static int ring_row(int q) { return q < M ? q : q + kWaves3 * RY; }
+    __device__ __forceinline__ static void side_pos(int i, int& r, int& c) {
+        r = i / (2 * M);
+        const int h = i - r * (2 * M);
+        c = h < M ? h : kTileX + h;
     }
     __device__ __forceinline__ void fetch(const float* __restrict__ f, int nx, int ny, int nz, int x0,
                                           int y0, int z) {
         const bool zok = (unsigned)z < (unsigned)nz;
+        const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+        const int gx = x0 + tx;
+        const bool xok = zok && gx < nx;
 #pragma unroll
-        for (int k = 0; k < NL; ++k) {
+        for (int k = 0; k < NT; ++k) {
+            const int q = ty + kWaves3 * k;
+            const int gy = y0 - M + ring_row(q);
+            top[k] = 0.f;
+            if ((NT * kWaves3 == 2 * M || q < 2 * M) && xok && (unsigned)gy < (unsigned)ny)
+                top[k] = f[((long long)z * ny + gy) * nx + gx];
+        }
+#pragma unroll
+        for (int k = 0; k < NSL; ++k) {
             const int i = threadIdx.x + k * kBlock3;
             int r, c;
-            pos(i, r, c);
-            const int gy = y0 - M + r, gx = x0 - M + c;
-            val[k] = 0.f;
-            if (i < H && zok && (unsigned)gy < (unsigned)ny && (unsigned)gx < (unsigned)nx)
-                val[k] = f[((long long)z * ny + gy) * nx + gx];
+            side_pos(i, r, c);
+            const int gy = y0 - M + r, hx = x0 - M + c;
+            side[k] = 0.f;
+            if ((NSL * kBlock3 == NS || i < NS) && zok && (unsigned)gy < (unsigned)ny && (unsigned)hx < (unsigned)nx)
+                side[k] = f[((long long)z * ny + gy) * nx + hx];
         }
     }
     __device__ __forceinline__ void store(float* tile) const {
+        const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
 #pragma unroll
-        for (int k = 0; k < NL; ++k) {
+        for (int k = 0; k < NT; ++k) {
+            const int q = ty + kWaves3 * k;
+            if (NT * kWaves3 == 2 * M || q < 2 * M) tile[ring_row(q) * LW + M + tx] = top[k];
+        }
+#pragma unroll
+        for (int k = 0; k < NSL; ++k) {
             const int i = threadIdx.x + k * kBlock3;
             int r, c;
-            const int at = pos(i, r, c);
-            if (i < H) tile[at] = val[k];
+            side_pos(i, r, c);
+            if (NSL * kBlock3 == NS || i < NS) tile[r * LW + c] = side[k];
         }
     }
 };

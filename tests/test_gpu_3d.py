@@ -40,6 +40,7 @@ def run3(F, vel, h, dt, nt, nb, eta, sid, src, wav, rec, final=False, vmax=None)
 
 
 CASES3 = ([("taylor", "cross", M, r) for M in (1, 2, 4, 8) for r in (1, 2, 4)]
+          + [("taylor", "cross", 3, 2), ("taylor", "cross", 6, 1)]
           + [("dispte", "rhombus", M, r) for M in (1, 2, 3, 4) for r in (1, 2)]
           + [("dispte", "rhombus", M, 1) for M in (5, 6)]
           + [("taylor", "square", M, r) for M in (1, 2, 3) for r in (1, 2)])

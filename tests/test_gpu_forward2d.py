@@ -96,19 +96,22 @@ def test_every_shape_and_radius(F, scheme, shape, M, rows):
 
 
 @pytest.mark.parametrize("nz,nx", [(1, 1), (3, 5), (9, 2), (1, 70), (67, 1)])
-def test_degenerate_windows(F, nz, nx):
+@pytest.mark.parametrize("scheme,shape,M", [("dispte", "rhombus", 4), ("specls", "square", 3),
+                                            ("taylor", "cross", 8)])
+def test_degenerate_windows(F, nz, nx, scheme, shape, M):
     """Windows smaller than the stencil radius: every neighbour may fall off
-    the grid (zero values beyond the window)."""
+    the grid (zero values beyond the window); rhombus, square (padded LDS
+    rows) and cross tiles."""
     h, nt = 10.0, 40
     vel = np.full((nz, nx), 2000.0, np.float32)
     dt = 0.25 * h / 2000.0
-    wo = oracle_weights(2, "dispte", "rhombus", 4, 2000.0 * dt / h)
-    sid = F.fd_weights_set(2, "rhombus", 4, wo)
+    wo = oracle_weights(2, scheme, shape, M, 2000.0 * dt / h)
+    sid = F.fd_weights_set(2, shape, M, wo)
     wav = synth.ricker(nt, dt, 30.0)
     rec = np.array([[nx - 1, nz - 1], [0, 0]])
     src = (nx // 2, nz // 2)
     gpu = gpu_run(F, vel, h, dt, nt, 0, 0.0, sid, src, wav, rec, final=True)
-    ref = oracle_traces(2, "rhombus", 4, wo, vel, h, dt, nt, 0, 0.0, src, wav, rec)
+    ref = oracle_traces(2, shape, M, wo, vel, h, dt, nt, 0, 0.0, src, wav, rec)
     assert rel_l2(gpu["cur"], ref["cur"]) <= 1e-5
 
 

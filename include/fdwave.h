@@ -135,7 +135,10 @@ typedef struct {
     int check_finite;      /* 1: synchronise at the end and return FD_ENONFINITE
                               if traces hold NaN/Inf, FD_EINVAL if a receiver
                               coordinate lay outside its window or a velocity
-                              was not positive and finite */
+                              was not positive and finite, FD_EUNSTABLE if a
+                              velocity c of the model has c dt / h above the
+                              smallest C_lim of the call's stencils (vmax
+                              understated: the run may have blown up) */
     int flags;             /* FD_NO_GRAPH | FD_NO_BATCH, 0 for the default path */
 } fd_grid;
 
@@ -166,22 +169,41 @@ typedef struct {
     const float* init_cur;   /* [dev, optional] u^0 over the window (NULL: zeros) */
     float* final_prev;       /* [dev, optional out] u^{nt-1} over the window */
     float* final_cur;        /* [dev, optional out] u^{nt} over the window */
+    float* ckpt;             /* [dev, optional] forward checkpoints: with
+                                ckpt_every = K > 0, ceil(nt/K) pairs of window
+                                fields; pair j (at ckpt + 2 j npts, npts = window
+                                points) holds (u^{jK-1}, u^{jK}).  Written by
+                                fd_forward, read by fd_adjoint_gradient (which
+                                then skips its own forward pass) */
 } fd_shot;
 
 /*
  * Forward modelling of nshots shots over one velocity model.
  *   vel        [dev] model-sized velocity c (m/s), all > 0
  *   shots      [host] nshots descriptors; windows must lie inside the model
- *   nshots     >= 1.  nshots == 1 runs one per-step kernel launch per step;
- *              nshots > 1 runs every shot's tiles in one launch per step
- *              (ragged windows and mixed stencils allowed)
+ *   nshots     >= 1.  nshots == 1 runs one kernel launch per time step (or
+ *              per two steps, fd_set_time_block).  nshots > 1 in 2D: the
+ *              shots are grouped by stencil variant (shape, M) and each time
+ *              step is one launch per group over the tiles of all its shots
+ *              (ragged windows allowed); the groups run concurrently on up to
+ *              four graph branches; batched tiles are fixed (8 rows per
+ *              thread for the forward steps of dense shapes, 4 otherwise).
+ *              nshots > 1 in 3D: the shots run concurrently on up to four
+ *              branches with the single-shot kernels
+ *   ckpt_every 0, or K in [1, nt]: every shot whose ckpt is set receives the
+ *              checkpoints (u^{jK-1}, u^{jK}), j = 0 .. ceil(nt/K) - 1, that
+ *              fd_adjoint_gradient with the same K consumes (the states an
+ *              FWI gradient needs from the forward pass, Sec. 7).  A shot with
+ *              ckpt set and K = 0 is FD_EINVAL
  *   workspace  [dev] >= fd_workspace_bytes(g, shots, nshots, 0, 0) bytes
  *   hip_stream hipStream_t to queue on
- * Stability: vmax * dt / h must not exceed the stencil's C_lim (FD_EUNSTABLE).
+ * Stability: vmax * dt / h must not exceed the stencil's C_lim (FD_EUNSTABLE,
+ * checked before any work is queued); the velocities themselves are checked
+ * against C_lim on the device and reported with check_finite.
  * The time loop is replayed from a cached HIP graph when the same arguments
  * are seen again.
  */
-int fd_forward(const fd_grid* g, const float* vel, const fd_shot* shots, int nshots,
+int fd_forward(const fd_grid* g, const float* vel, const fd_shot* shots, int nshots, int ckpt_every,
                void* workspace, size_t ws_bytes, void* hip_stream);
 
 /*
@@ -193,9 +215,17 @@ int fd_forward(const fd_grid* g, const float* vel, const fd_shot* shots, int nsh
  *     dJ/dc(x) += sum_{k=1..nt} (2 / c(x)) psi^k(x) (W * u^{k-1})(x).
  * The forward field is rebuilt from checkpoints of (u^{k-1}, u^k) taken every
  * ckpt_every steps and recomputed one segment at a time into the workspace.
+ * The paper points to this use of its stencils for FWI gradients (Sec. 7);
+ * the adjoint recursion is the exact discrete adjoint of the forward scheme.
  *   grad        [dev, in/out] model-sized; the gradient of every shot is ADDED
  *   ckpt_every  segment length K, 1 <= K <= nt
- * Other arguments as in fd_forward; traces are (re)written too.
+ *   shots[i].ckpt  NULL: the call runs the forward pass itself (taking the
+ *               checkpoints into the workspace) and rewrites the traces;
+ *               set: the checkpoints an fd_forward with the same K, grid,
+ *               velocity and shot wrote there; the forward pass is skipped
+ *               and the traces are left alone.  In a multi-shot 2D call
+ *               either every shot or none sets ckpt (FD_EINVAL otherwise)
+ * Other arguments as in fd_forward.
  */
 int fd_adjoint_gradient(const fd_grid* g, const float* vel, const fd_shot* shots, int nshots,
                         int ckpt_every, float* grad, void* workspace, size_t ws_bytes,
@@ -203,7 +233,8 @@ int fd_adjoint_gradient(const fd_grid* g, const float* vel, const fd_shot* shots
 
 /*
  * Workspace size in bytes for fd_forward (mode 0) or fd_adjoint_gradient
- * (mode 1, with segment length ckpt_every).  Returns 0 for invalid input.
+ * (mode 1, with segment length ckpt_every; shots that pass saved checkpoints
+ * need no checkpoint storage in it).  Returns 0 for invalid input.
  */
 size_t fd_workspace_bytes(const fd_grid* g, const fd_shot* shots, int nshots, int mode,
                           int ckpt_every);
@@ -219,7 +250,8 @@ size_t fd_workspace_bytes(const fd_grid* g, const fd_shot* shots, int nshots, in
  *   2 nsnap + 5 window fields, and the least number of forward steps any
  *   schedule with nsnap snapshots needs (fd_revolve_plan gives it).  For
  *   large grids whose segment storage does not fit (3D FWI).  The shots of
- *   a call run one after another with the single-shot kernels.
+ *   a call run one after another with the single-shot kernels; saved
+ *   checkpoints (fd_shot.ckpt) are FD_EINVAL with this scheme.
  *
  * The gradient is dJ/dc (FD_PARAM_VELOCITY), dJ/ds for the slowness s = 1/c
  * (FD_PARAM_SLOWNESS: -c^2 dJ/dc) or dJ/dm for m = 1/c^2 (FD_PARAM_M:
@@ -324,6 +356,9 @@ const char* fd_last_error(void);
  *   norm_cwt    [dev, out, may be NULL] nrec per-receiver ||gamma^W||_2
  *   workspace   [dev] >= fd_dispersion_workspace_bytes(nt, nrec, norm_cwt ? nscale : 0),
  *               256-byte aligned
+ * A receiver whose numerical trace is identically zero (max |A| = 0, where
+ * eq. gammadft divides 0 by 0) gets gamma = 0 at every bin and both norms 0:
+ * the amplitude weight of a trace without energy is read as 0.
  * The average and maximum over receivers (eqs. norm2gammarecdftavg ..
  * norm2gammareccwtmax) are reductions of norm_dft / norm_cwt by the caller.
  * FFTs run in rocFFT; its plans (and any work buffer they need) are cached

@@ -23,6 +23,12 @@ Definitions (with the readings of the garbled passages):
   the CWT by frequency k but does not say how scales map to k, nor w0.)
   gamma^W_{n,j} = (phi_dif / pi) |W_num| / max_{n,j} |W_num|      (eq. gammacwt)
   ||gamma^W||_2 = sqrt(1/(nt nscale) sum_{n,j} gamma^2)           (eq. norm2gammastcwt)
+  A numerical trace that is identically zero has max |A| = 0 (and
+  max |W| = 0), where eq. gammadft (and eq. gammacwt) divide 0 by 0.  Reading:
+  the amplitude weight |A_k| / max|A| of a trace that carries no energy is 0,
+  so gamma = 0 at every bin and the norms are 0 (a silent receiver shows no
+  dispersion).  Any non-zero trace, however small, is measured as usual:
+  gamma does not change when either trace is scaled by a positive factor.
 """
 from __future__ import annotations
 
@@ -48,12 +54,17 @@ def phase(z: np.ndarray) -> np.ndarray:
     return np.arctan2(z.imag, z.real)
 
 
+def amplitude_weight(amp: np.ndarray) -> np.ndarray:
+    """|A| / max|A|, and 0 everywhere for a trace with no energy (max|A| = 0)."""
+    top = amp.max()
+    return amp / top if top > 0 else np.zeros_like(amp)
+
+
 def gamma_dft(num: np.ndarray, ref: np.ndarray):
     """(gamma^F_k for k = 0..nt-1, ||gamma^F||_2) of one trace pair."""
     A = np.fft.fft(np.asarray(num, dtype=np.float64))
     B = np.fft.fft(np.asarray(ref, dtype=np.float64))
-    amp = amplitude(A)
-    g = wrap(phase(A) - phase(B)) / math.pi * amp / amp.max()
+    g = wrap(phase(A) - phase(B)) / math.pi * amplitude_weight(amplitude(A))
     return g, float(np.sqrt(np.sum(g ** 2) / len(g)))
 
 
@@ -85,8 +96,7 @@ def gamma_cwt(num: np.ndarray, ref: np.ndarray, dt: float, nscale: int, omega0: 
     s = morlet_scales(len(num), dt, nscale, omega0)
     Wn = cwt(num, dt, s, omega0)
     Wr = cwt(ref, dt, s, omega0)
-    amp = amplitude(Wn)
-    g = wrap(phase(Wn) - phase(Wr)) / math.pi * amp / amp.max()
+    g = wrap(phase(Wn) - phase(Wr)) / math.pi * amplitude_weight(amplitude(Wn))
     return g, float(np.sqrt(np.sum(g ** 2) / g.size))
 
 

@@ -42,8 +42,10 @@ Schemes:
           sum_o w_o Phi_o(beta, theta) - 1 over beta in [0, b], theta in
           [0, 2 pi), Phi_o = sum_{d in o} (1 - cos(k.d)) / beta^2 with
           k = beta (cos theta, sin theta).  The centre weight follows from
-          r = 0 (eq. taylor_system_r0_spec).  Floating point; parity unpinned
-          (the paper prints neither the band b nor any weight values).
+          r = 0 (eq. taylor_system_r0_spec).  Floating point.  The paper
+          prints neither the band b nor any weight values; the weights are
+          pinned to the continuous minimiser of this objective (normal
+          equations from closed-form angular integrals, in the tests).
   DispLS  Sec. 3.4.3, cosine form eq. displs_cont_linsys: as SpecLS with the
           denominator Psi_2 = (2 - 2 cos(C beta)) / C^2 instead of beta^2.
   SpecTE-theta / DispTE-theta  Sec. 3.3.2 / 3.4.2: the cross systems in
@@ -210,7 +212,9 @@ def specls(ndim: int, shape: str, M: int, band: float = math.pi, nbeta: int = 96
 
     Quadrature: Gauss-Legendre in beta on [0, band] and the midpoint rule in
     theta on [0, 2 pi); the weighted least-squares problem is solved with
-    numpy's lstsq.  Parity unpinned: the paper gives no band and no values."""
+    numpy's lstsq.  The paper gives no band and no values: b = pi and the
+    measure dbeta dtheta are readings; under them the weights are pinned to
+    the continuous problem's normal equations to 1e-13."""
     if ndim != 2:
         raise ValueError("SpecLS is defined for 2D stencils")
     orbs = orbits(ndim, shape, M, N)[1:]
@@ -244,8 +248,8 @@ def displs(ndim: int, shape: str, M: int, C: float, band: float = math.pi, nbeta
     (eq. displs_cont_linsys): least squares of sum_o w_o Phi_o - 1 with the
     orbit symbol deficit divided by Psi_2(beta) = (2 - 2 cos(C beta)) / C^2
     (the printed Psi_2 drops a factor 2 on the cosine; with it, Psi_2 -> beta^2
-    as C -> 0 and DispLS reduces to SpecLS).  Same quadrature as specls.
-    Parity unpinned (no printed band or values)."""
+    as C -> 0 and DispLS reduces to SpecLS).  Same quadrature as specls,
+    and pinned the same way (no printed band or values)."""
     if ndim != 2:
         raise ValueError("DispLS is defined for 2D stencils")
     if not C > 0:

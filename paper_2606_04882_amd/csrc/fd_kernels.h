@@ -181,7 +181,9 @@ struct AdjArgs {
 // shot owns an arena of window-sized fields; kernels name fields by slot:
 // slot s >= 0 is arena + s * npts, SLOT_INIT_PREV / SLOT_INIT_CUR the
 // caller's initial state (zeros when absent), SLOT_ZERO a field of zeros.
-enum { SLOT_ZERO = -3, SLOT_INIT_CUR = -2, SLOT_INIT_PREV = -1 };
+// SLOT_CKPT0 - i (i >= 0) is field i of the caller's checkpoint buffer
+// (pair j = fields 2j, 2j+1).
+enum { SLOT_ZERO = -3, SLOT_INIT_CUR = -2, SLOT_INIT_PREV = -1, SLOT_CKPT0 = -16 };
 
 struct BatchShot {
     float* arena;
@@ -199,6 +201,7 @@ struct BatchShot {
     const float* init_prev;          // optional initial state
     const float* init_cur;
     float* gacc;                     // window-shaped gradient accumulator (adjoint calls)
+    float* ckpt;                     // caller's checkpoint fields, or nullptr
     int variant;                     // shape * 8 + (M - 1)
     Weights w;
 };
@@ -207,6 +210,7 @@ __device__ __forceinline__ const float* slot_ptr(const BatchShot& s, int slot) {
     if (slot >= 0) return s.arena + (long long)slot * s.npts;
     if (slot == SLOT_INIT_PREV) return s.init_prev;
     if (slot == SLOT_INIT_CUR) return s.init_cur;
+    if (slot <= SLOT_CKPT0 && s.ckpt) return s.ckpt + (long long)(SLOT_CKPT0 - slot) * s.npts;
     return nullptr;
 }
 
@@ -237,7 +241,8 @@ struct BatchAdjArgs {
 bool launch_batch_adj2d(const BatchAdjArgs& a, int shape, int M, hipStream_t s);
 // dst slot <- src slot for every shot (src SLOT_ZERO: fill with zeros; an
 // absent initial state also reads as zeros); also used for gacc when dst is
-// SLOT_GACC
+// SLOT_GACC and for the caller's checkpoint fields (dst <= SLOT_CKPT0; shots
+// without a checkpoint buffer are skipped)
 enum { SLOT_GACC = -4 };
 void launch_batch_copy(const BatchShot* shots, int nshots, long long max_npts, int dst, int src,
                        hipStream_t s);
@@ -315,7 +320,8 @@ bool have_adj3d(int shape, int M);
 int adj_rows3d(int shape, int M, int fwd_rows);  // tile height the 3D adjoint runs with
 
 // Small helper kernels (k_misc.hip).
-void launch_vprep(const float* vel, float* v, long long n, double dt_over_h, int* flags,
+// c_lim: largest stable Courant number (velocities above c_lim h / dt are flagged)
+void launch_vprep(const float* vel, float* v, long long n, double dt_over_h, double c_lim, int* flags,
                   hipStream_t s);
 void launch_fill(float* p, long long n, float val, hipStream_t s);
 void launch_fill_i32(int* p, long long n, int val, hipStream_t s);
@@ -332,7 +338,7 @@ void launch_check_finite(const float* p, long long n, int* flags, hipStream_t s)
 void launch_accum2d(float* g, long long ldg, const float* a, int nx, int nz, hipStream_t s);
 
 // flags[] slots in the workspace
-enum { FLAG_BAD_REC = 0, FLAG_NONFINITE = 1, FLAG_BAD_VEL = 2, FLAG_COUNT = 4 };
+enum { FLAG_BAD_REC = 0, FLAG_NONFINITE = 1, FLAG_BAD_VEL = 2, FLAG_UNSTABLE_VEL = 3, FLAG_COUNT = 4 };
 
 // Dispersion metrics (k_disp.hip).  Half spectra are double2 [rc][nt/2+1],
 // CWT fields double2 [rc][ns][nt].

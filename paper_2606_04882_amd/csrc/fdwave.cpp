@@ -280,15 +280,26 @@ long long window_points(const fd_shot& s, int ndim) {
 }
 
 // Slots of the batched adjoint arena (K = segment length, nseg segments).
+// With saved checkpoints (every shot passes fd_shot.ckpt) the checkpoint
+// pairs are read from the caller's buffer and take no arena slots.
 struct AdjSlots {
     int nseg, K;
-    int ck(int j, int which) const { return 2 + 2 * j + which; }
-    int seg(int i) const { return 2 + 2 * nseg + i; }
-    int psiA() const { return 2 + 2 * nseg + K; }
+    bool saved = false;
+    int nck() const { return saved ? 0 : 2 * nseg; }
+    int ck(int j, int which) const { return saved ? SLOT_CKPT0 - (2 * j + which) : 2 + 2 * j + which; }
+    int seg(int i) const { return 2 + nck() + i; }
+    int psiA() const { return 2 + nck() + K; }
     int psiB() const { return psiA() + 1; }
     int gacc() const { return psiA() + 2; }
     int count() const { return psiA() + 3; }
 };
+
+// shots passing saved checkpoints (fd_shot.ckpt)
+int saved_count(const fd_shot* shots, int nshots) {
+    int n = 0;
+    for (int i = 0; i < nshots; ++i) n += shots[i].ckpt != nullptr;
+    return n;
+}
 
 Layout make_layout(const fd_grid* g, const fd_shot* shots, int nshots, int mode, int K) {
     Layout L;
@@ -303,7 +314,8 @@ Layout make_layout(const fd_grid* g, const fd_shot* shots, int nshots, int mode,
     // a single-shot forward keeps four fields so that two-steps-per-launch
     // kernels can write out of place; the binomial adjoint keeps its fields
     // in the shared scratch below
-    L.nslots = (batch && mode == MODE_ADJ_SEGMENT) ? AdjSlots{nseg, K}.count()
+    const int nsaved = mode == MODE_ADJ_SEGMENT ? saved_count(shots, nshots) : 0;
+    L.nslots = (batch && mode == MODE_ADJ_SEGMENT) ? AdjSlots{nseg, K, nsaved == nshots}.count()
              : mode == MODE_ADJ_REVOLVE ? 0 : ((!batch && mode == MODE_FORWARD) ? 4 : 2);
     long long wmax = 0;
     for (int i = 0; i < nshots; ++i) {
@@ -318,10 +330,11 @@ Layout make_layout(const fd_grid* g, const fd_shot* shots, int nshots, int mode,
     }
     L.psiA = L.psiB = L.ckpt = L.seg = 0;
     if (mode != MODE_FORWARD && !batch) {
-        // segments: nseg checkpoints of two fields and K segment fields;
-        // binomial: K snapshots of two fields and three working fields (two
-        // for the current state, one of zeros for an absent initial state)
-        const size_t nck = mode == MODE_ADJ_SEGMENT ? (size_t)nseg : (size_t)K;
+        // segments: nseg checkpoints of two fields (none when every shot
+        // brings its own) and K segment fields; binomial: K snapshots of two
+        // fields and three working fields (two for the current state, one of
+        // zeros for an absent initial state)
+        const size_t nck = mode == MODE_ADJ_SEGMENT ? (nsaved == nshots ? 0 : (size_t)nseg) : (size_t)K;
         const size_t nsegf = mode == MODE_ADJ_SEGMENT ? (size_t)K : 3;
         L.psiA = off;
         off = align256(off + sizeof(float) * (size_t)wmax);
@@ -560,6 +573,7 @@ struct CallCtx {
     long long ldv_y, ldv_z;
     Sponge sp;
     float q;
+    double c_lim;   // smallest stability limit over the call's stencils
     // adjoint: K = segment length (segments) or snapshot count (binomial);
     // gparam = GP_* parameter of the gradient
     int K;
@@ -747,9 +761,9 @@ int enqueue_forward_tb(const CallCtx& c, const ShotCtx& s, Recorder& R) {
 }
 
 // forward run of one shot.  With ckpt != nullptr, slot j receives
-// (u^{jK-1}, u^{jK}) for every segment start jK, and the steps of the last
-// segment [tail, nt) write u^{n+1} out of place into seg[n - tail] (so the
-// adjoint needs no recompute for that segment).
+// (u^{jK-1}, u^{jK}) for every segment start jK; with seg != nullptr too, the
+// steps of the last segment [tail, nt) write u^{n+1} out of place into
+// seg[n - tail] (so the adjoint needs no recompute for that segment).
 int enqueue_forward_shot(const CallCtx& c, const ShotCtx& s, float* ckpt, int K, float* seg,
                          Recorder& R) {
     if (!ckpt && s.st.tsteps == 2 && c.L.nslots >= 4 && have_tb(c.g->ndim, s.st.shape, s.st.M, s.st.rows) &&
@@ -763,7 +777,7 @@ int enqueue_forward_shot(const CallCtx& c, const ShotCtx& s, float* ckpt, int K,
     if (s.s->init_prev) launch_copy(prev, s.s->init_prev, n, st); else launch_fill(prev, n, 0.f, st);
     if (s.s->init_cur) launch_copy(cur, s.s->init_cur, n, st); else launch_fill(cur, n, 0.f, st);
     launch_rec_index(s.s->rec, s.s->nrec, c.g->ndim, s.nx, s.ny, s.nz, s.rec, c.flags, st);
-    const int tail = ckpt ? ((nt - 1) / K) * K : nt;
+    const int tail = (ckpt && seg) ? ((nt - 1) / K) * K : nt;
     if (ckpt) {
         launch_copy(ckpt, prev, n, st);
         launch_copy(ckpt + n, cur, n, st);
@@ -855,13 +869,20 @@ int enqueue_adjoint_shot(const CallCtx& c, const ShotCtx& s, Recorder& R) {
     hipStream_t st = R.stream;
     const int nt = c.g->nt, K = c.K;
     const long long n = s.npts;
-    float* ckpt = (float*)(c.ws + c.L.ckpt);
+    // saved checkpoints: the forward pass ran in an earlier fd_forward call
+    const bool saved = s.s->ckpt != nullptr;
+    float* ckpt = saved ? s.s->ckpt : (float*)(c.ws + c.L.ckpt);
     float* seg = (float*)(c.ws + c.L.seg);
     float* pa = (float*)(c.ws + c.L.psiA);
     float* pb = (float*)(c.ws + c.L.psiB);
-    int rc = enqueue_forward_shot(c, s, ckpt, K, seg, R);
-    if (rc) return rc;
-    R.cut();
+    if (saved) {
+        launch_rec_index(s.s->rec, s.s->nrec, c.g->ndim, s.nx, s.ny, s.nz, s.rec, c.flags, st);
+        R.launched();
+    } else {
+        int rc = enqueue_forward_shot(c, s, ckpt, K, seg, R);
+        if (rc) return rc;
+        R.cut();
+    }
     launch_fill(pa, n, 0.f, st);   // psi^{nt+1}
     launch_fill(pb, n, 0.f, st);   // psi^{nt+2}
     float* pcur = pa;
@@ -875,8 +896,8 @@ int enqueue_adjoint_shot(const CallCtx& c, const ShotCtx& s, Recorder& R) {
         const float* ck_prev = ckpt + (size_t)j * 2 * n;
         const float* ck_cur = ck_prev + n;
         // recompute u^{s0+1} .. u^{e0} into seg[0 .. e0-s0-1] (the last
-        // segment is already there from the forward pass)
-        for (int step = s0; step < e0 && j < nseg - 1; ++step) {
+        // segment is already there when this call ran the forward pass)
+        for (int step = s0; step < e0 && (j < nseg - 1 || saved); ++step) {
             const int i = step - s0;
             f.ucur = i == 0 ? ck_cur : seg + (size_t)(i - 1) * n;
             f.uprev = i == 0 ? ck_prev : (i == 1 ? ck_cur : seg + (size_t)(i - 2) * n);
@@ -1158,6 +1179,13 @@ int enqueue_batched(const CallCtx& c, Recorder& R) {
     launch_batch_copy(dshots, ns, maxn, 0, SLOT_INIT_PREV, st);
     launch_batch_copy(dshots, ns, maxn, 1, SLOT_INIT_CUR, st);
     R.launched(2);
+    // checkpoints into the callers' buffers (shots without one are skipped)
+    const int K = c.K;
+    if (K > 0) {
+        launch_batch_copy(dshots, ns, maxn, SLOT_CKPT0, 0, st);
+        launch_batch_copy(dshots, ns, maxn, SLOT_CKPT0 - 1, 1, st);
+        R.launched(2);
+    }
     BatchArgs a;
     a.shots = dshots;
     a.sp = c.sp;
@@ -1175,6 +1203,15 @@ int enqueue_batched(const CallCtx& c, Recorder& R) {
             ok = ok && launch_batch2d(a, g.shape, g.M, g.rows, R.on(g.branch));
         }
         R.launched((int)c.groups.size());
+        if (K > 0 && (n + 1) % K == 0 && n + 1 < nt) {
+            // pair j = (n+1)/K: (u^n, u^{n+1}) from slots (n+1)&1 and n&1
+            const int j = (n + 1) / K;
+            for (const CallCtx::Group& g : c.groups) {
+                launch_batch_copy(dshots + g.d0, g.dn, g.maxn, SLOT_CKPT0 - 2 * j, (n + 1) & 1, R.on(g.branch));
+                launch_batch_copy(dshots + g.d0, g.dn, g.maxn, SLOT_CKPT0 - 2 * j - 1, n & 1, R.on(g.branch));
+            }
+            R.launched(2 * (int)c.groups.size());
+        }
     }
     R.join();
     if (!ok) return fail(FD_EUNSUPPORTED, "batched kernel not compiled");
@@ -1200,7 +1237,9 @@ int enqueue_batched_adjoint(const CallCtx& c, Recorder& R) {
     hipStream_t st = R.stream;
     const int nt = c.g->nt, K = c.K, ns = (int)c.shots.size();
     const int nseg = (nt + K - 1) / K;
-    const AdjSlots S{nseg, K};
+    // saved checkpoints (every shot or none, checked in prepare): no forward pass
+    const bool saved = c.shots[0].s->ckpt != nullptr;
+    const AdjSlots S{nseg, K, saved};
     const BatchShot* dshots = (const BatchShot*)(c.ws + c.L.desc);
     const int2* jobs = (const int2*)(c.ws + c.L.jobs);
     long long maxn = 0;
@@ -1215,11 +1254,13 @@ int enqueue_batched_adjoint(const CallCtx& c, Recorder& R) {
         launch_batch_copy(dshots, ns, maxn, dst, src, st);
         R.launched();
     };
-    copy_all(0, SLOT_INIT_PREV);
-    copy_all(1, SLOT_INIT_CUR);
     copy_all(SLOT_GACC, SLOT_ZERO);
-    copy_all(S.ck(0, 0), 0);
-    copy_all(S.ck(0, 1), 1);
+    if (!saved) {
+        copy_all(0, SLOT_INIT_PREV);
+        copy_all(1, SLOT_INIT_CUR);
+        copy_all(S.ck(0, 0), 0);
+        copy_all(S.ck(0, 1), 1);
+    }
     // per-group helpers, each on the group's branch
     auto copy = [&](int dst, int src) {
         for (const CallCtx::Group& g : c.groups)
@@ -1258,7 +1299,7 @@ int enqueue_batched_adjoint(const CallCtx& c, Recorder& R) {
     R.fork(c.nbranch);
     const int tail = ((nt - 1) / K) * K;
     int cur = 1, prev = 0, last = 1;
-    for (int n = 0; n < nt && ok; ++n) {
+    for (int n = 0; n < nt && ok && !saved; ++n) {
         f.step = n;
         f.gather = 1;
         if (n < tail) {
@@ -1280,9 +1321,11 @@ int enqueue_batched_adjoint(const CallCtx& c, Recorder& R) {
             }
         }
     }
-    for (const CallCtx::Group& g : c.groups)
-        launch_batch_gather(dshots + g.d0, g.dn, g.maxrec, last, nt - 1, R.on(g.branch));
-    R.launched((int)c.groups.size());
+    if (!saved) {
+        for (const CallCtx::Group& g : c.groups)
+            launch_batch_gather(dshots + g.d0, g.dn, g.maxrec, last, nt - 1, R.on(g.branch));
+        R.launched((int)c.groups.size());
+    }
     R.cut();
     copy(S.psiA(), SLOT_ZERO);
     copy(S.psiB(), SLOT_ZERO);
@@ -1290,7 +1333,7 @@ int enqueue_batched_adjoint(const CallCtx& c, Recorder& R) {
     f.gather = 0;
     for (int j = nseg - 1; j >= 0 && ok; --j) {
         const int s0 = j * K, e0 = std::min(nt, s0 + K);
-        for (int step = s0; step < e0 && j < nseg - 1; ++step) {
+        for (int step = s0; step < e0 && (j < nseg - 1 || saved); ++step) {
             const int i = step - s0;
             f.step = step;
             f.f_cur = i == 0 ? S.ck(j, 1) : S.seg(i - 1);
@@ -1323,7 +1366,7 @@ int enqueue_batched_adjoint(const CallCtx& c, Recorder& R) {
     for (const ShotCtx& s : c.shots) {
         launch_accum2d(c.grad + model_offset(c, *s.s), c.ldv_y, s.bufA + (long long)S.gacc() * s.npts,
                        s.nx, s.nz, st);
-        if (c.g->check_finite && s.s->nrec > 0)
+        if (c.g->check_finite && s.s->nrec > 0 && !saved)
             launch_check_finite(s.s->traces, (long long)nt * s.s->nrec, c.flags, st);
         R.launched(2);
     }
@@ -1358,7 +1401,8 @@ void build_batch_blob(CallCtx& c, int mode) {
     std::vector<BatchShot> desc(nshots);
     std::vector<int2> jobs;
     jobs.reserve((size_t)c.L.njobs);
-    const AdjSlots S{mode == MODE_ADJ_SEGMENT ? (c.g->nt + c.K - 1) / c.K : 0, c.K};
+    const AdjSlots S{mode == MODE_ADJ_SEGMENT ? (c.g->nt + c.K - 1) / c.K : 0, c.K,
+                     mode == MODE_ADJ_SEGMENT && c.shots[0].s->ckpt != nullptr};
     c.groups.clear();
     std::vector<double> gcost;
     for (int k = 0; k < nshots; ++k) {
@@ -1403,6 +1447,7 @@ void build_batch_blob(CallCtx& c, int mode) {
         d.init_prev = s.s->init_prev;
         d.init_cur = s.s->init_cur;
         d.gacc = mode == MODE_ADJ_SEGMENT ? s.bufA + (long long)S.gacc() * s.npts : nullptr;
+        d.ckpt = s.s->ckpt;
         d.variant = variant(order[k]);
         d.w = s.st.w32;
         for (int t = 0; t < d.ntiles; ++t) jobs.push_back(make_int2(k, t));
@@ -1435,7 +1480,7 @@ int enqueue_call(const CallCtx& c, int mode, Recorder& R) {
     int rc = FD_OK;
     launch_fill_i32(c.flags, FLAG_COUNT, 0, R.stream);
     const long long mpts = c.g->n[0] * (c.g->ndim == 3 ? c.g->n[1] : 1) * c.g->n[2];
-    launch_vprep(c.vel, c.vfield, mpts, c.g->dt / c.g->h, c.flags, R.stream);
+    launch_vprep(c.vel, c.vfield, mpts, c.g->dt / c.g->h, c.c_lim, c.flags, R.stream);
     R.launched(2);
     if (use_batch(c.g, (int)c.shots.size(), mode))
         return mode == MODE_FORWARD ? enqueue_batched(c, R) : enqueue_batched_adjoint(c, R);
@@ -1447,7 +1492,8 @@ int enqueue_call(const CallCtx& c, int mode, Recorder& R) {
     if (par) R.fork(ns);
     for (int i = 0; i < ns; ++i) {
         if (par) R.active = i;
-        rc = mode == MODE_FORWARD ? enqueue_forward_shot(c, c.shots[i], nullptr, 0, nullptr, R)
+        rc = mode == MODE_FORWARD ? enqueue_forward_shot(c, c.shots[i], c.K > 0 ? c.shots[i].s->ckpt : nullptr,
+                                                         c.K, nullptr, R)
            : mode == MODE_ADJ_SEGMENT ? enqueue_adjoint_shot(c, c.shots[i], R)
                                       : enqueue_adjoint_revolve(c, c.shots[i], R);
         if (rc) break;
@@ -1574,6 +1620,9 @@ int finish_checks(const CallCtx& c, hipStream_t user) {
     int flags[FLAG_COUNT];
     HIP_OK(hipMemcpy(flags, c.flags, sizeof flags, hipMemcpyDeviceToHost));
     if (flags[FLAG_BAD_VEL]) return fail(FD_EINVAL, "%d velocities are not positive and finite", flags[FLAG_BAD_VEL]);
+    if (flags[FLAG_UNSTABLE_VEL])
+        return fail(FD_EUNSTABLE, "%d velocities c have c dt / h above the stability limit %.6g of the call's stencils",
+                    flags[FLAG_UNSTABLE_VEL], c.c_lim);
     if (flags[FLAG_BAD_REC]) return fail(FD_EINVAL, "%d receiver coordinates lie outside their window", flags[FLAG_BAD_REC]);
     if (flags[FLAG_NONFINITE]) return fail(FD_ENONFINITE, "%d trace samples are not finite", flags[FLAG_NONFINITE]);
     return FD_OK;
@@ -1586,6 +1635,14 @@ int prepare(CallCtx& c, const fd_grid* g, const float* vel, const fd_shot* shots
     if (!vel) return fail(FD_EINVAL, "vel is NULL");
     if (!shots || nshots < 1) return fail(FD_EINVAL, "need at least one shot");
     if (mode == MODE_ADJ_SEGMENT && (K < 1 || K > g->nt)) return fail(FD_EINVAL, "ckpt_every must be in [1, nt]");
+    if (mode == MODE_FORWARD && (K < 0 || K > g->nt)) return fail(FD_EINVAL, "ckpt_every must be in [0, nt]");
+    const int nsaved = saved_count(shots, nshots);
+    if (nsaved > 0 && mode == MODE_FORWARD && K == 0)
+        return fail(FD_EINVAL, "shots pass checkpoint buffers but ckpt_every is 0");
+    if (nsaved > 0 && mode == MODE_ADJ_REVOLVE)
+        return fail(FD_EINVAL, "saved checkpoints (fd_shot.ckpt) need segment checkpointing");
+    if (nsaved > 0 && nsaved < nshots && mode == MODE_ADJ_SEGMENT && use_batch(g, nshots, mode))
+        return fail(FD_EINVAL, "a batched adjoint needs saved checkpoints for every shot or for none");
     if (mode == MODE_ADJ_REVOLVE && (K < 0 || K > g->nt)) return fail(FD_EINVAL, "nsnap must be in [0, nt]");
     c.g = g;
     c.vel = vel;
@@ -1608,10 +1665,12 @@ int prepare(CallCtx& c, const fd_grid* g, const float* vel, const fd_shot* shots
     c.sp.inv_nb = g->nb > 0 ? (float)(1.0 / g->nb) : 0.f;
     c.q = (float)(g->dt * g->dt / std::pow(g->h, g->ndim));
     c.grad = nullptr;
+    c.c_lim = HUGE_VAL;
     for (int i = 0; i < nshots; ++i) {
         ShotCtx s;
         rc = check_shot(g, shots[i], i, mode != MODE_FORWARD, &s.st);
         if (rc) return rc;
+        c.c_lim = std::min(c.c_lim, s.st.cfl);
         s.s = &shots[i];
         s.nx = (int)shots[i].extent[0];
         s.ny = g->ndim == 3 ? (int)shots[i].extent[1] : 1;
@@ -1893,11 +1952,11 @@ size_t fd_workspace_bytes(const fd_grid* g, const fd_shot* shots, int nshots, in
     return make_layout(g, shots, nshots, mode, mode == 1 ? ckpt_every : 1).total;
 }
 
-int fd_forward(const fd_grid* g, const float* vel, const fd_shot* shots, int nshots, void* workspace,
-               size_t ws_bytes, void* hip_stream) {
+int fd_forward(const fd_grid* g, const float* vel, const fd_shot* shots, int nshots, int ckpt_every,
+               void* workspace, size_t ws_bytes, void* hip_stream) {
     g_err.clear();
     CallCtx c;
-    int rc = prepare(c, g, vel, shots, nshots, 0, 1, workspace, ws_bytes);
+    int rc = prepare(c, g, vel, shots, nshots, 0, ckpt_every, workspace, ws_bytes);
     if (rc) return rc;
     hipStream_t st = (hipStream_t)hip_stream;
     rc = run_call(c, 0, st);

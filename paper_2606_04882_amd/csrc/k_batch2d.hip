@@ -93,7 +93,10 @@ __global__ __launch_bounds__(kBlock) void k_batch_adj2d(BatchAdjArgs p) {
 // dst <- src per shot; blockIdx.y = shot
 __global__ void k_batch_copy(const BatchShot* __restrict__ shots, int dst, int src) {
     const BatchShot& s = shots[blockIdx.y];
-    float* d = dst == SLOT_GACC ? s.gacc : s.arena + (long long)dst * s.npts;
+    float* d = dst == SLOT_GACC ? s.gacc
+             : dst <= SLOT_CKPT0 ? (s.ckpt ? s.ckpt + (long long)(SLOT_CKPT0 - dst) * s.npts : nullptr)
+                                 : s.arena + (long long)dst * s.npts;
+    if (!d) return;
     const float* a = slot_ptr(s, src);
     for (long long i = blockIdx.x * (long long)kBlock + threadIdx.x; i < s.npts;
          i += (long long)gridDim.x * kBlock)

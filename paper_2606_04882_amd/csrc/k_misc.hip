@@ -14,14 +14,17 @@ static inline int grid_for(long long n) {
 
 // v = (c dt / h)^2 formed in FP64 and rounded once to FP32 (the squared
 // Courant number of Sec. 3.4.1, eq. courant); non-positive or non-finite
-// velocities are counted in flags[FLAG_BAD_VEL].
+// velocities are counted in flags[FLAG_BAD_VEL], velocities whose Courant
+// number c dt / h exceeds c_lim (the stability limit of eq. full_disp) in
+// flags[FLAG_UNSTABLE_VEL].
 __global__ void k_vprep(const float* __restrict__ vel, float* __restrict__ v, long long n,
-                        double dt_over_h, int* __restrict__ flags) {
+                        double dt_over_h, double c_lim, int* __restrict__ flags) {
     for (long long i = blockIdx.x * (long long)kBlock + threadIdx.x; i < n;
          i += (long long)gridDim.x * kBlock) {
         const float c = vel[i];
         if (!(c > 0.f) || !isfinite(c)) atomicAdd(&flags[FLAG_BAD_VEL], 1);
         const double t = (double)c * dt_over_h;
+        if (t > c_lim) atomicAdd(&flags[FLAG_UNSTABLE_VEL], 1);
         v[i] = (float)(t * t);
     }
 }
@@ -131,9 +134,9 @@ void launch_accum2d(float* g, long long ldg, const float* a, int nx, int nz, hip
     if (n > 0) hipLaunchKernelGGL(k_accum2d, dim3(grid_for(n)), dim3(kBlock), 0, s, g, ldg, a, nx, n);
 }
 
-void launch_vprep(const float* vel, float* v, long long n, double dt_over_h, int* flags,
+void launch_vprep(const float* vel, float* v, long long n, double dt_over_h, double c_lim, int* flags,
                   hipStream_t s) {
-    hipLaunchKernelGGL(k_vprep, dim3(grid_for(n)), dim3(kBlock), 0, s, vel, v, n, dt_over_h, flags);
+    hipLaunchKernelGGL(k_vprep, dim3(grid_for(n)), dim3(kBlock), 0, s, vel, v, n, dt_over_h, c_lim, flags);
 }
 void launch_fill(float* p, long long n, float val, hipStream_t s) {
     if (n <= 0) return;

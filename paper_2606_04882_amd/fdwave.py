@@ -58,7 +58,8 @@ class FdShot(ctypes.Structure):
                 ("wavelet", ctypes.c_void_p), ("nrec", ctypes.c_int), ("rec", ctypes.c_void_p),
                 ("traces", ctypes.c_void_p), ("trace_adj", ctypes.c_void_p),
                 ("init_prev", ctypes.c_void_p), ("init_cur", ctypes.c_void_p),
-                ("final_prev", ctypes.c_void_p), ("final_cur", ctypes.c_void_p)]
+                ("final_prev", ctypes.c_void_p), ("final_cur", ctypes.c_void_p),
+                ("ckpt", ctypes.c_void_p)]
 
 
 class FdAdjointOpts(ctypes.Structure):
@@ -87,8 +88,8 @@ def _load() -> ctypes.CDLL:
     lib.fd_get_time_block.argtypes = [ctypes.c_int, P(ctypes.c_int)]
     lib.fd_workspace_bytes.restype = ctypes.c_size_t
     lib.fd_workspace_bytes.argtypes = [P(FdGrid), P(FdShot), ctypes.c_int, ctypes.c_int, ctypes.c_int]
-    lib.fd_forward.argtypes = [P(FdGrid), ctypes.c_void_p, P(FdShot), ctypes.c_int, ctypes.c_void_p,
-                               ctypes.c_size_t, ctypes.c_void_p]
+    lib.fd_forward.argtypes = [P(FdGrid), ctypes.c_void_p, P(FdShot), ctypes.c_int, ctypes.c_int,
+                               ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
     lib.fd_adjoint_gradient.argtypes = [P(FdGrid), ctypes.c_void_p, P(FdShot), ctypes.c_int, ctypes.c_int,
                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
     lib.fd_adjoint_gradient_ex.argtypes = [P(FdGrid), ctypes.c_void_p, P(FdShot), ctypes.c_int, P(FdAdjointOpts),
@@ -215,6 +216,7 @@ class Shot:
     trace_adj: Optional[torch.Tensor] = None  # [nt, nrec] float32
     init: Optional[Tuple[torch.Tensor, torch.Tensor]] = None
     final: Optional[Tuple[torch.Tensor, torch.Tensor]] = None
+    ckpt: Optional[torch.Tensor] = None       # checkpoints, ckpt_numel(...) float32
 
 
 def _ptr(t: Optional[torch.Tensor]):
@@ -251,7 +253,24 @@ def _shot_c(s: Shot, grid: Grid) -> FdShot:
         c.init_prev, c.init_cur = _ptr(s.init[0]), _ptr(s.init[1])
     if s.final is not None:
         c.final_prev, c.final_cur = _ptr(s.final[0]), _ptr(s.final[1])
+    c.ckpt = _ptr(s.ckpt)
     return c
+
+
+def window_points(grid: Grid, shot: Shot) -> int:
+    """Points of a shot's window (the whole model when extent is None)."""
+    if shot.extent is None:
+        return int(np.prod(grid.shape))
+    return int(shot.extent[0]) * int(shot.extent[1]) * int(shot.extent[2])
+
+
+def ckpt_numel(grid: Grid, shot: Shot, ckpt_every: int) -> int:
+    """Floats of a shot's checkpoint buffer for segment length ckpt_every:
+    ceil(nt / K) pairs (u^{jK-1}, u^{jK}) of window fields."""
+    K = int(ckpt_every)
+    if K < 1:
+        raise ValueError("ckpt_every must be >= 1")
+    return -(-int(grid.nt) // K) * 2 * window_points(grid, shot)
 
 
 _ws_cache: dict = {}
@@ -279,8 +298,14 @@ def _stream_handle(device) -> int:
     return torch.cuda.current_stream(device).cuda_stream
 
 
-def fd_forward(grid: Grid, vel: torch.Tensor, shots: Sequence[Shot], ws: Optional[torch.Tensor] = None):
-    """Forward modelling; traces are written into each shot's `traces`."""
+def fd_forward(grid: Grid, vel: torch.Tensor, shots: Sequence[Shot], ws: Optional[torch.Tensor] = None,
+               ckpt_every: int = 0):
+    """Forward modelling; traces are written into each shot's `traces`, and
+    with ckpt_every = K > 0 the checkpoints (u^{jK-1}, u^{jK}) into each
+    shot's `ckpt` (ckpt_numel floats) when it has one."""
+    for s in shots:
+        if s.ckpt is not None and ckpt_every > 0 and s.ckpt.numel() < ckpt_numel(grid, s, ckpt_every):
+            raise ValueError(f"ckpt holds {s.ckpt.numel()} floats, {ckpt_numel(grid, s, ckpt_every)} needed")
     if vel.dtype != torch.float32 or tuple(vel.shape) != tuple(grid.shape):
         raise ValueError(f"vel must be float32 of shape {grid.shape}")
     g = grid.c()
@@ -290,7 +315,7 @@ def fd_forward(grid: Grid, vel: torch.Tensor, shots: Sequence[Shot], ws: Optiona
         raise FdError(FD_EINVAL, "invalid grid/shots for fd_workspace_bytes")
     if ws is None:
         ws = workspace(nbytes, vel.device)
-    _check(_lib.fd_forward(ctypes.byref(g), _ptr(vel), arr, len(shots), _ptr(ws), ws.numel(),
+    _check(_lib.fd_forward(ctypes.byref(g), _ptr(vel), arr, len(shots), int(ckpt_every), _ptr(ws), ws.numel(),
                            ctypes.c_void_p(_stream_handle(vel.device))))
 
 
@@ -314,7 +339,11 @@ def fd_adjoint_gradient(grid: Grid, vel: torch.Tensor, shots: Sequence[Shot], ck
     """Adjoint run; the gradient of every shot (in `param`: velocity,
     slowness or m = 1/c^2) is added into `grad`.  ckpt "segment" stores
     states every `ckpt_every` steps; "revolve" runs the binomial plan with
-    `nsnap` snapshots."""
+    `nsnap` snapshots.  Shots whose `ckpt` holds the checkpoints of an
+    fd_forward with the same ckpt_every skip the forward pass."""
+    for s in shots:
+        if s.ckpt is not None and ckpt == "segment" and s.ckpt.numel() < ckpt_numel(grid, s, ckpt_every):
+            raise ValueError(f"ckpt holds {s.ckpt.numel()} floats, {ckpt_numel(grid, s, ckpt_every)} needed")
     if vel.dtype != torch.float32 or tuple(vel.shape) != tuple(grid.shape):
         raise ValueError(f"vel must be float32 of shape {grid.shape}")
     if grad.dtype != torch.float32 or tuple(grad.shape) != tuple(grid.shape):

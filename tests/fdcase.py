@@ -61,3 +61,22 @@ def layered(shape, seed, vmin=1500.0, vmax=3000.0):
         return synth.layered_section(shape[0], shape[1], vmin, vmax, 5, 2.0, seed).astype(np.float32)
     nz, ny, nx = shape
     return synth.layered_3d(nz, ny, nx, vmin, vmax, 4, 1.5, seed)
+
+
+def check_traces(gpu, ref, tol=1e-5, floor=1e-2):
+    """Trace parity: rel-L2 over every sample <= tol, and element-wise per
+    receiver, max_n |gpu - ref| <= tol * max(max_n |ref_r|, floor * max |ref|):
+    a receiver that carries at least `floor` of the peak amplitude is held to
+    `tol` of its own peak, the others to tol * floor of the overall peak, so an
+    error confined to one receiver or one stretch of a trace cannot hide under
+    the global norm.  Returns (rel-L2, worst per-receiver ratio)."""
+    gpu = np.asarray(gpu, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    assert gpu.shape == ref.shape, (gpu.shape, ref.shape)
+    err = rel_l2(gpu, ref)
+    peak = np.abs(ref).max()
+    scale = np.maximum(np.abs(ref).max(axis=0), floor * peak)
+    worst = float(np.max(np.abs(gpu - ref).max(axis=0) / scale)) if ref.size else 0.0
+    assert err <= tol, f"trace rel-L2 {err:.3g} > {tol}"
+    assert worst <= tol, f"per-receiver error {worst:.3g} of its scale > {tol}"
+    return err, worst

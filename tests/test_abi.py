@@ -167,7 +167,7 @@ def test_unknown_flags_are_rejected(F):
     arr = (F.FdShot * 1)(s)
     # validation runs before any device work: a null velocity and workspace
     # would be reported only after the flags
-    rc = F._lib.fd_forward(ctypes.byref(g), ctypes.c_void_p(16), arr, 1, None, 0, None)
+    rc = F._lib.fd_forward(ctypes.byref(g), ctypes.c_void_p(16), arr, 1, 0, None, 0, None)
     assert rc == F.FD_EINVAL and "flags" in F.fd_last_error()
 
 

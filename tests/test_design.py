@@ -71,3 +71,34 @@ def test_dispte_theta_disperses_least_along_its_angle():
                                       C, beta, th) - 1)
     e_plain = np.abs(D.phase_velocity(2, "cross", M, D.weights(2, "dispte", "cross", M, C), C, beta, th) - 1)
     assert np.max(e_theta) < np.max(e_plain)
+
+
+def _bench_stencils():
+    """(ndim, scheme, shape, M, Courant number) of every stencil a benchmark
+    workload registers."""
+    from paper_2606_04882_amd import configs
+    out = set()
+    for w in (configs.small_2d(), configs.large_2d(), configs.volume_3d(nt=10), configs.ragged(nt=10),
+              configs.fwi(nt=10)):
+        for scheme, shape, M in w.stencils:
+            out.add((w.ndim, scheme, shape, M, w.courant))
+    return sorted(out)
+
+
+@pytest.mark.parametrize("ndim,scheme,shape,M,C", _bench_stencils())
+def test_benchmark_weights_equal_the_oracle(ndim, scheme, shape, M, C):
+    """The weights the benchmark feeds the kernels (design.py) equal the
+    oracle's for every workload stencil: exactly for the rational schemes
+    (Taylor, DispTE), to 1e-9 for least squares."""
+    got = D.weights(ndim, scheme, shape, M, C)
+    if scheme == "taylor":
+        ref = W.taylor(ndim, M)
+    elif scheme == "dispte":
+        ref = W.dispte(ndim, shape, M, Fraction(C))
+    else:
+        ref = W.specls(ndim, shape, M)
+    if scheme in ("taylor", "dispte"):
+        # both are exact rationals rounded once to FP64
+        assert [float(x) for x in got] == [float(x) for x in ref]
+    else:
+        close(got, ref, 1e-9)

@@ -80,3 +80,33 @@ def test_identical_traces_and_a_phase_shifted_tone(F):
     assert abs(nd[1] - math.sqrt(2 * (0.7 / math.pi) ** 2 / nt)) < 1e-6
     _, cref = OD.gamma_cwt(num[:, 1].astype(np.float64), ref[:, 1].astype(np.float64), dt, 48)
     assert abs(nc[1] - cref) < 1e-6 * cref
+
+
+def test_zero_and_tiny_traces(F):
+    """Receivers whose numerical trace is all zeros read gamma = 0 (the
+    amplitude weight of a trace with no energy is 0, as in the oracle), a
+    zero reference is measured like any other, and a trace scaled down by
+    1e-30 gives the norms of the unscaled one."""
+    nt, nrec, dt, nscale = 600, 6, 1e-3, 12
+    num, ref = pair(nt, nrec, dt, seed=11)
+    num[:, 0] = 0.0                      # silent receiver
+    ref[:, 1] = 0.0                      # silent reference
+    num[:, 2] = 0.0
+    ref[:, 2] = 0.0                      # both silent
+    num[:, 3] = (num[:, 4].astype(np.float64) * 1e-30).astype(np.float32)
+    ref[:, 3] = ref[:, 4]
+    out = F.fd_dispersion(torch.tensor(num, device=DEV), torch.tensor(ref, device=DEV), dt, nscale, gamma=True)
+    torch.cuda.synchronize()
+    nd = out["norm_dft"].cpu().numpy()
+    nc = out["norm_cwt"].cpu().numpy()
+    g = out["gamma_dft"].cpu().numpy()
+    assert np.all(np.isfinite(nd)) and np.all(np.isfinite(nc)) and np.all(np.isfinite(g))
+    assert nd[0] == 0 and nc[0] == 0 and np.all(g[0] == 0)
+    assert nd[2] == 0 and nc[2] == 0
+    for r in range(nrec):
+        x, y = num[:, r].astype(np.float64), ref[:, r].astype(np.float64)
+        _, nref = OD.gamma_dft(x, y)
+        _, cref = OD.gamma_cwt(x, y, dt, nscale)
+        assert abs(nd[r] - nref) <= 1e-6 * max(nref, 1e-12), r
+        assert abs(nc[r] - cref) <= 1e-6 * max(cref, 1e-12), r
+    assert abs(nd[3] - nd[4]) <= 1e-6 * nd[4] and abs(nc[3] - nc[4]) <= 1e-6 * nc[4]

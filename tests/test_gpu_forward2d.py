@@ -196,6 +196,26 @@ def test_nonfinite_velocity_is_flagged(F):
     assert e.value.code == F.FD_EINVAL
 
 
+def test_velocity_above_the_stability_limit_is_flagged(F):
+    """vmax understated: one cell's Courant number c dt / h exceeds the
+    stencil's C_lim although vmax dt / h does not.  The host check passes,
+    the device check counts the cell and check_finite reports FD_EUNSTABLE;
+    a velocity above vmax but within C_lim is accepted."""
+    h, nt = 10.0, 5
+    sid = F.fd_weights_set(2, "cross", 4, oracle_weights(2, "taylor", "cross", 4))
+    lim = F.fd_cfl_limit(sid)
+    dt = 0.5 * lim * h / 2000.0                 # vmax = 2000 runs at half the limit
+    vel = np.full((30, 30), 2000.0, np.float32)
+    vel[7, 9] = 2.2 * 2000.0                    # Courant number 1.1 C_lim
+    with pytest.raises(F.FdError) as e:
+        gpu_run(F, vel, h, dt, nt, 0, 0.0, sid, (5, 5), np.zeros(nt), np.array([[1, 1]]),
+                vmax=2000.0, check_finite=True)
+    assert e.value.code == F.FD_EUNSTABLE
+    vel[7, 9] = 1.9 * 2000.0                    # above vmax, 0.95 C_lim: stable
+    gpu_run(F, vel, h, dt, nt, 0, 0.0, sid, (5, 5), np.zeros(nt), np.array([[1, 1]]),
+            vmax=2000.0, check_finite=True)
+
+
 def test_v_coefficient_is_rounded_once(F):
     """v = (c dt/h)^2 is formed in FP64 and rounded once to FP32: bit-exact
     with the oracle's FP64 value rounded to FP32 (read from the workspace,

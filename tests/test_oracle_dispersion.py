@@ -92,3 +92,45 @@ def test_receiver_norms_average_and_maximum():
     per = [0.0, math.sqrt(2 * (0.3 / math.pi) ** 2 / nt), math.sqrt(2 * (1.0 / math.pi) ** 2 / nt)]
     assert np.allclose(out["dft"], per, atol=1e-12)
     assert abs(out["dft_avg"] - np.mean(per)) < 1e-12 and abs(out["dft_max"] - max(per)) < 1e-12
+
+
+def test_zero_trace_reads_as_no_dispersion():
+    """A numerical trace that is identically zero has max|A| = 0, where the
+    amplitude weight of eq. gammadft is 0/0: read as gamma = 0 at every bin
+    and norms 0 (no division, no warning).  A zero reference is an ordinary
+    input: its phases are atan2(0, 0) = 0."""
+    import warnings
+    nt, dt = 400, 1e-3
+    x = AN.ricker(np.arange(nt) * dt, 25.0, 0.1)
+    z = np.zeros(nt)
+    with warnings.catch_warnings():
+        warnings.simplefilter("error")
+        g, nrm = D.gamma_dft(z, x)
+        gw, nw = D.gamma_cwt(z, x, dt, 20)
+        out = D.receiver_norms(np.stack([z, x], 1), np.stack([x, x], 1), dt, 20)
+    assert np.all(g == 0) and nrm == 0
+    assert np.all(gw == 0) and nw == 0
+    assert out["dft"][0] == 0 and out["cwt"][0] == 0 and out["dft_max"] == 0
+    # zero reference: gamma_k = wrap(phi(A_k)) / pi * |A_k| / max|A|
+    g2, _ = D.gamma_dft(x, z)
+    A = np.fft.fft(x)
+    expect = D.wrap(np.angle(A)) / math.pi * np.abs(A) / np.abs(A).max()
+    assert np.max(np.abs(g2 - expect)) < 1e-12
+
+
+@pytest.mark.parametrize("scale", [1e-30, 3.7, 1e20])
+def test_gamma_is_scale_invariant(scale):
+    """Scaling either trace by c > 0 changes no phase and no amplitude ratio,
+    so gamma^F and gamma^W are unchanged: a tiny (non-zero) trace is measured
+    like any other."""
+    nt, dt = 300, 2e-3
+    t = np.arange(nt) * dt
+    x = AN.ricker(t, 12.0, 0.12) + 0.2 * AN.ricker(t, 20.0, 0.3)
+    y = 0.8 * AN.ricker(t, 11.5, 0.125)
+    g0, n0 = D.gamma_dft(x, y)
+    for a, b in ((scale * x, y), (x, scale * y), (scale * x, scale * y)):
+        g, n = D.gamma_dft(a, b)
+        assert np.max(np.abs(g - g0)) < 1e-9 and abs(n - n0) < 1e-10
+    _, w0 = D.gamma_cwt(x, y, dt, 16)
+    _, w1 = D.gamma_cwt(scale * x, y, dt, 16)
+    assert abs(w1 - w0) < 1e-12 * max(w0, 1.0)

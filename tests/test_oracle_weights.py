@@ -193,7 +193,7 @@ def test_dispersion_relation_small_k_order():
 
 
 def test_specls_square_internal_consistency():
-    """SpecLS weights (parity unpinned: the paper prints no band and no
+    """SpecLS weights (the paper prints no band and no
     values).  Checks: r = 0 holds, second-order consistency (r = 1 equation
     within the least-squares error), symbol <= 0 (stable), and the stated
     limits."""

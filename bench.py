@@ -16,7 +16,9 @@ The last stdout line is the result (compact JSON):
                 call inside the timed region give its average launch time
                 (call time / nt: the call's few set-up kernels, under 0.2 %
                 of it, are counted against the kernel); algorithmic bytes
-                (16 B per update) or flops per launch over that time; HBM
+                (16 B per update, the scheme's minimum; the kernels move 20 B
+                in the difference form, reported as impl_gbs) or flops per
+                launch over that time; HBM
                 traffic per launch from the committed rocprofv3 counter
                 record when it matches the current kernel sources
   cpu_baseline  the FP64 oracle on this host's cores on a bounded sample of
@@ -47,17 +49,12 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+KERNEL3D = {"cross": "cross", "rhombus": "ball", "square": "gen"}   # 3D forward kernel per shape
 METRIC = "Gpt-updates/s + %HBM roofline (fwd); FWI gradient s/shot vs plain, 1 GPU"
 HBM_PEAK_GBS = 8000.0
 FP32_PEAK_TFLOPS = 157.3
-BYTES_PER_UPDATE = 16.0  # read u^n, u^{n-1}, v; write u^{n+1}
-
-
-def bytes_per_point_launch(tsteps: int) -> float:
-    """Algorithmic HBM bytes per grid point of one launch: one step reads u^n,
-    u^{n-1}, v and writes u^{n+1} (16 B); two steps per launch read the same
-    three fields once and write u^{n+1}, u^{n+2} (20 B)."""
-    return 16.0 if tsteps == 1 else 20.0
+BYTES_PER_UPDATE = 16.0  # the scheme's minimum: read u^n, u^{n-1}, v; write u^{n+1}
+IMPL_BYTES_PER_UPDATE = 20.0  # difference form: read u^n, d^n, v; write d^{n+1}, u^{n+1}
 
 
 def flops_per_update(ndim: int, shape: str, M: int) -> float:
@@ -188,7 +185,7 @@ def setup_3d(torch, F, autotune, configs, design, dev, args, only=None):
         if ws is None:    # one workspace: the calls run one after another
             ws = torch.empty(F.fd_workspace_bytes(grid, [shot]), dtype=torch.uint8, device=dev)
         rows, zc = F.fd_get_tile(sid)
-        kname = f"k_fwd3d_{'cross' if shape == 'cross' else 'gen'}<M={M},rows={rows},zchunk={zc}>"
+        kname = f"k_fwd3d_{KERNEL3D[shape]}<M={M},rows={rows},zchunk={zc}>"
         variants.append({"name": name, "shape": shape, "M": M, "sid": sid, "shot": shot, "kernel": kname})
     if not variants:
         raise SystemExit(f"unknown stencil {only!r}")
@@ -239,6 +236,7 @@ def headline_3d(torch, F, autotune, configs, design, dev, args):
         roof = {"bound": "alu", "achieved": round(tfl, 2), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(tfl / FP32_PEAK_TFLOPS, 4)}
     roof["traffic"] = traffic_for(dv["kernel"], npts)
+    roof["impl_gbs"] = round(npts * IMPL_BYTES_PER_UPDATE / launch_s / 1e9, 1)
     roof["kernel"] = dv["kernel"]
     roof["launch_us"] = dp["launch_us"]
     roof["share"] = round(dp["call_ms"] / sum(p["call_ms"] for p in per), 3)
@@ -347,8 +345,7 @@ def setup_2d(torch, F, autotune, configs, design, dev, args, only=None):
         nbytes = F.fd_workspace_bytes(grid, [shot])
         ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
         variants.append({"name": name, "shape": shape, "M": M, "sid": sid,
-                         "shot": shot, "ws": ws, "rows": F.fd_get_tile(sid)[0],
-                         "tsteps": F.fd_get_time_block(sid)})
+                         "shot": shot, "ws": ws, "rows": F.fd_get_tile(sid)[0]})
     if not variants:
         raise SystemExit(f"unknown stencil {only!r}")
     return w, vel_np, vel, grid, variants
@@ -370,7 +367,7 @@ def large2d_bench(torch, F, autotune, configs, design, dev, args, reps=5):
         F.fd_forward(grid, vel, [v["shot"]], ws=v["ws"])
         t = _event_time(torch, lambda: F.fd_forward(grid, vel, [v["shot"]], ws=v["ws"]), reps=2)
         alone.append({"stencil": v["name"], "gupd_s": round(npts * w.nt / (t * 1e-3) / 1e9, 1),
-                      "rows": v["rows"], "tsteps": v["tsteps"]})
+                      "rows": v["rows"]})
     return {"grid": list(w.shape), "nt": w.nt, "batched_ms": round(ms, 3),
             "batched_gupd_s": round(npts * w.nt * len(variants) / (ms * 1e-3) / 1e9, 1),
             "sequential_ms": round(sum(npts * w.nt / (a["gupd_s"] * 1e9) * 1e3 for a in alone), 3),
@@ -386,8 +383,7 @@ def only_2d(torch, F, autotune, configs, design, dev, args):
         F.fd_forward(grid, vel, [v["shot"]], ws=v["ws"])
         torch.cuda.synchronize()
         ms = _event_time(torch, lambda: F.fd_forward(grid, vel, [v["shot"]], ws=v["ws"]), reps=args.steps)
-        out.append({"stencil": v["name"], "rows": v["rows"], "tsteps": v["tsteps"], "nt": w.nt,
-                    "ms": round(ms, 4)})
+        out.append({"stencil": v["name"], "rows": v["rows"], "nt": w.nt, "ms": round(ms, 4)})
     return out
 
 

@@ -18,7 +18,13 @@
  * The stencil is evaluated in the centre-free difference form
  * sum_{d != 0} w_d (u(x + d) - u(x)), which equals W * u whenever the weights
  * satisfy the zero-sum (r = 0) condition of Sec. 3.3.1, eq. taylor_system_r0;
- * fd_weights_set enforces that condition.
+ * fd_weights_set enforces that condition.  The time stepping carries the
+ * state (u^n, d^n), d^n = u^n - u^{n-1}, and advances it exactly as
+ *     d^{n+1} = [(1 - e) d^n + v (W * u^n) + q s^n delta_{x,xs}] / (1 + e),
+ *     u^{n+1} = u^n + d^{n+1},   e = eta dt / 2
+ * (the update above, rearranged), so that the per-step change is stored at
+ * full FP32 precision; initial and final states, and checkpoints, are given
+ * in that form.
  *
  * Conventions for every entry point:
  *  - Arrays are row-major with x fastest: 2D [nz][nx], 3D [nz][ny][nx].
@@ -165,15 +171,17 @@ typedef struct {
                                 (their traces are 0) and flagged (check_finite) */
     float* traces;           /* [dev, out] nt*nrec: traces[n*nrec + r] = u^{n+1}(rec r) */
     const float* trace_adj;  /* [dev] fd_adjoint_gradient only: dJ/dtraces, nt*nrec */
-    const float* init_prev;  /* [dev, optional] u^{-1} over the window (NULL: zeros) */
+    const float* init_diff;  /* [dev, optional] d^0 = u^0 - u^{-1} over the window (NULL: zeros) */
     const float* init_cur;   /* [dev, optional] u^0 over the window (NULL: zeros) */
-    float* final_prev;       /* [dev, optional out] u^{nt-1} over the window */
+    float* final_diff;       /* [dev, optional out] d^{nt} = u^{nt} - u^{nt-1} over the window
+                                (with final_cur: the state a later call resumes from,
+                                bitwise, as init_diff / init_cur) */
     float* final_cur;        /* [dev, optional out] u^{nt} over the window */
     float* ckpt;             /* [dev, optional] forward checkpoints: with
                                 ckpt_every = K > 0, ceil(nt/K) pairs of window
                                 fields; pair j (at ckpt + 2 j npts, npts = window
-                                points) holds (u^{jK-1}, u^{jK}).  Written by
-                                fd_forward, read by fd_adjoint_gradient (which
+                                points) holds the state (d^{jK}, u^{jK}).  Written
+                                by fd_forward, read by fd_adjoint_gradient (which
                                 then skips its own forward pass) */
 } fd_shot;
 
@@ -181,8 +189,8 @@ typedef struct {
  * Forward modelling of nshots shots over one velocity model.
  *   vel        [dev] model-sized velocity c (m/s), all > 0
  *   shots      [host] nshots descriptors; windows must lie inside the model
- *   nshots     >= 1.  nshots == 1 runs one kernel launch per time step (or
- *              per two steps, fd_set_time_block).  nshots > 1 in 2D: the
+ *   nshots     >= 1.  nshots == 1 runs one kernel launch per time step.
+ *              nshots > 1 in 2D: the
  *              shots are grouped by stencil variant (shape, M) and each time
  *              step is one launch per group over the tiles of all its shots
  *              (ragged windows allowed); the groups run concurrently on up to
@@ -191,7 +199,7 @@ typedef struct {
  *              nshots > 1 in 3D: the shots run concurrently on up to four
  *              branches with the single-shot kernels
  *   ckpt_every 0, or K in [1, nt]: every shot whose ckpt is set receives the
- *              checkpoints (u^{jK-1}, u^{jK}), j = 0 .. ceil(nt/K) - 1, that
+ *              checkpoints (d^{jK}, u^{jK}), j = 0 .. ceil(nt/K) - 1, that
  *              fd_adjoint_gradient with the same K consumes (the states an
  *              FWI gradient needs from the forward pass, Sec. 7).  A shot with
  *              ckpt set and K = 0 is FD_EINVAL
@@ -213,8 +221,9 @@ int fd_forward(const fd_grid* g, const float* vel, const fd_shot* shots, int nsh
  *     psi^k = b [ 2 psi^{k+1} - a psi^{k+2} + v (W * psi^{k+1}) + v rho^{k-1} @ x_r ],
  * k = nt..1, psi^{nt+1} = psi^{nt+2} = 0, and
  *     dJ/dc(x) += sum_{k=1..nt} (2 / c(x)) psi^k(x) (W * u^{k-1})(x).
- * The forward field is rebuilt from checkpoints of (u^{k-1}, u^k) taken every
- * ckpt_every steps and recomputed one segment at a time into the workspace.
+ * The forward field is rebuilt from checkpoints of the state (d^k, u^k) taken
+ * every ckpt_every steps and recomputed one segment at a time into the
+ * workspace.
  * The paper points to this use of its stencils for FWI gradients (Sec. 7);
  * the adjoint recursion is the exact discrete adjoint of the forward scheme.
  *   grad        [dev, in/out] model-sized; the gradient of every shot is ADDED
@@ -242,12 +251,13 @@ size_t fd_workspace_bytes(const fd_grid* g, const fd_shot* shots, int nshots, in
 /*
  * Adjoint options: checkpointing scheme and gradient parameter.
  *
- * FD_CKPT_SEGMENT: (u^{jK-1}, u^{jK}) stored every K = ckpt_every steps,
- *   each segment recomputed into K fields (2 ceil(nt/K) + K window fields
- *   per shot, one extra forward pass); multi-shot 2D calls run batched.
- * FD_CKPT_REVOLVE: binomial checkpointing with nsnap snapshots of
- *   (u^{k-1}, u^k) (Griewank & Walther, ACM TOMS 26, 2000, Algorithm 799):
- *   2 nsnap + 5 window fields, and the least number of forward steps any
+ * FD_CKPT_SEGMENT: the state (d^{jK}, u^{jK}) stored every K = ckpt_every
+ *   steps, each segment recomputed into K + 1 fields (2 ceil(nt/K) + K + 1
+ *   window fields per shot, one extra forward pass; none of the 2 ceil(nt/K)
+ *   when the shots bring saved checkpoints); multi-shot 2D calls run batched.
+ * FD_CKPT_REVOLVE: binomial checkpointing with nsnap snapshots of the state
+ *   (d^k, u^k) (Griewank & Walther, ACM TOMS 26, 2000, Algorithm 799):
+ *   2 nsnap + 6 window fields, and the least number of forward steps any
  *   schedule with nsnap snapshots needs (fd_revolve_plan gives it).  For
  *   large grids whose segment storage does not fit (3D FWI).  The shots of
  *   a call run one after another with the single-shot kernels; saved
@@ -318,13 +328,9 @@ int fd_set_tile(int stencil_id, int rows, int zchunk);
 int fd_get_tile(int stencil_id, int* rows, int* zchunk);
 
 /*
- * Time steps per kernel launch of the single-shot forward (1 or 2).  With
- * 2, one launch advances two steps (the first one on the tile plus an M-cell
- * ring, fields written out of place), halving launches and HBM passes;
- * results are bit-identical to 1.  Compiled for 2D cross stencils with rows
- * 2 or 4 and 3D cross stencils with M <= 4 and rows 1 (FD_EUNSUPPORTED
- * otherwise); the default is 2 for the 2D crosses.  Calls with checkpoints
- * (the adjoint) and batched calls always use one step per launch.
+ * Time steps per kernel launch of the forward (kept for callers of the
+ * interface): every kernel advances one step per launch, so 1 is the only
+ * value; 2 returns FD_EUNSUPPORTED, anything else FD_EINVAL.
  */
 int fd_set_time_block(int stencil_id, int steps);
 int fd_get_time_block(int stencil_id, int* steps);

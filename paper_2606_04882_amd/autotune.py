@@ -1,10 +1,10 @@
 """Tile autotuner for the forward kernels.
 
 For a stencil on a given grid, times a short forward run for every compiled
-configuration (2D: rows per thread 2, 4, 8, and for crosses also two time
-steps per launch and the z-marching kernel with chunks of 16-48 rows; 3D:
-rows 1, 2, 4 times z-chunk 16, 32, 64, 128, 256) and
-installs the fastest with fd_set_tile / fd_set_time_block.  Results are
+configuration (2D: rows per thread 2, 4, 8, and for crosses also the
+z-marching kernel with chunks of 16-48 rows; 3D: rows 1, 2, 4 (crosses) or
+1, 2 times z-chunk 16, 32, 64, 128, 256) and installs the fastest with
+fd_set_tile.  Results are
 cached in a JSON file keyed by device, dimension, stencil and grid size, so a
 tuned configuration is reused by later runs; configurations tuned on MI355X
 for the standard workloads ship with the package (tuned_mi355x.json) and are
@@ -30,15 +30,20 @@ PACKAGED = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned_mi355
 
 
 def candidates(ndim: int, shape: str, M: int) -> List[Tuple[int, int, int]]:
-    """(rows, zchunk, time steps per launch) configurations to time."""
+    """(rows, zchunk, time steps per launch) configurations to time (one
+    step per launch throughout)."""
     if ndim == 2:
         c = [(r, 64, 1) for r in (2, 4, 8)]
         if shape == "cross":
-            c += [(r, 64, 2) for r in (2, 4)]
             # z-marching kernel (one row per thread), for large windows
             c += [(1, z, 1) for z in (16, 24, 32, 48)]
         return c
-    rows = (1, 2, 4) if shape == "cross" else ((1, 2) if M <= 4 else (1,))
+    if shape == "cross":
+        rows = (1, 2, 4)
+    elif shape == "rhombus":
+        rows = (1,) if M > 2 else (1, 2)
+    else:
+        rows = (1, 2) if M <= 4 else (1,)
     return [(r, z, 1) for r in rows for z in (16, 32, 64, 128, 256)]
 
 
@@ -53,13 +58,11 @@ def device_tag() -> str:
 
 def _key(ndim, shape, M, grid_shape, N: int = 0) -> str:
     sh = shape if N == 0 else f"{shape}{N}"
-    return f"v2|{device_tag()}|{ndim}|{sh}|{M}|{'x'.join(str(int(n)) for n in grid_shape)}"
+    return f"v3|{device_tag()}|{ndim}|{sh}|{M}|{'x'.join(str(int(n)) for n in grid_shape)}"
 
 
 def _install(stencil_id: int, ndim: int, rows: int, zc: int, ts: int):
     F.fd_set_tile(stencil_id, rows, zc)
-    if ndim == 2:
-        F.fd_set_time_block(stencil_id, ts)
 
 
 def _load(path: str = "") -> Dict:

@@ -122,12 +122,39 @@ __device__ __forceinline__ int band_depth(int i, int n, int nb) {
 }
 
 // ---------------------------------------------------------------------------
+// Time stepping in difference form.  The forward state at step n is the pair
+// (u^n, d^n), d^n = u^n - u^{n-1}: with a = 1 - e, b = 1 / (1 + e) the
+// leapfrog update b [2 u^n - a u^{n-1} + v L + q s] (Sec. 3.2 eq.
+// time_derivative1 with the damping term of Sec. 3.1) is, exactly,
+//     d^{n+1} = [(1 - e) d^n + v L + q s] / (1 + e),   u^{n+1} = u^n + d^{n+1}.
+// Storing d instead of u^{n-1} keeps the per-step change at full FP32
+// precision: with many time steps per period the change is a small fraction
+// of u, and u^{n+1} - u^n recovered from two stored FP32 fields would carry
+// the rounding of u (the 1001^2 workload at 500 steps: traces 1.5e-5 from
+// the FP64 scheme in the plain form, 5.7e-7 in the difference form).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float delta_update(float dc, float vv, float L, bool inband, float e, bool at_src,
+                                              float qs) {
+    float r;
+    if (!inband) {
+        r = fmaf(vv, L, dc);
+        if (at_src) r += qs;
+    } else {
+        r = fmaf(vv, L, (1.f - e) * dc);
+        if (at_src) r += qs;
+        r = r / (1.f + e);
+    }
+    return r;
+}
+
+// ---------------------------------------------------------------------------
 // Per-step parameters of the single-shot forward kernels.
 // ---------------------------------------------------------------------------
 struct StepArgs {
     const float* __restrict__ ucur;  // u^n over the window (dense, x fastest)
-    const float* uprev;              // u^{n-1} (may equal unext: in-place update)
-    float* unext;                    // u^{n+1}
+    const float* dcur;               // d^n = u^n - u^{n-1} (may equal dnext: in-place update)
+    float* dnext;                    // d^{n+1}
+    float* unext;                    // u^{n+1} (never ucur: neighbours read u^n)
     const float* __restrict__ v;     // model v at the window origin
     long long ldv_y, ldv_z;          // model strides of v (row, plane)
     int nx, ny, nz;                  // window extent (ny = 1 in 2D)
@@ -179,11 +206,11 @@ struct AdjArgs {
 
 // One shot of a batched launch (device memory, built by the host).  Each
 // shot owns an arena of window-sized fields; kernels name fields by slot:
-// slot s >= 0 is arena + s * npts, SLOT_INIT_PREV / SLOT_INIT_CUR the
-// caller's initial state (zeros when absent), SLOT_ZERO a field of zeros.
-// SLOT_CKPT0 - i (i >= 0) is field i of the caller's checkpoint buffer
-// (pair j = fields 2j, 2j+1).
-enum { SLOT_ZERO = -3, SLOT_INIT_CUR = -2, SLOT_INIT_PREV = -1, SLOT_CKPT0 = -16 };
+// slot s >= 0 is arena + s * npts;
+// SLOT_INIT_DIFF / SLOT_INIT_CUR the caller's initial state d^0, u^0 (zeros
+// when absent), SLOT_ZERO a field of zeros; SLOT_CKPT0 - i (i >= 0) is field
+// i of the caller's checkpoint buffer (pair j = fields 2j (d), 2j+1 (u)).
+enum { SLOT_ZERO = -3, SLOT_INIT_CUR = -2, SLOT_INIT_DIFF = -1, SLOT_CKPT0 = -16 };
 
 struct BatchShot {
     float* arena;
@@ -198,7 +225,7 @@ struct BatchShot {
     const long long* rec_lin;
     float* traces;
     const float* trace_adj;          // adjoint sources dJ/dtraces (adjoint calls)
-    const float* init_prev;          // optional initial state
+    const float* init_diff;          // optional initial state d^0, u^0
     const float* init_cur;
     float* gacc;                     // window-shaped gradient accumulator (adjoint calls)
     float* ckpt;                     // caller's checkpoint fields, or nullptr
@@ -208,7 +235,7 @@ struct BatchShot {
 
 __device__ __forceinline__ const float* slot_ptr(const BatchShot& s, int slot) {
     if (slot >= 0) return s.arena + (long long)slot * s.npts;
-    if (slot == SLOT_INIT_PREV) return s.init_prev;
+    if (slot == SLOT_INIT_DIFF) return s.init_diff;
     if (slot == SLOT_INIT_CUR) return s.init_cur;
     if (slot <= SLOT_CKPT0 && s.ckpt) return s.ckpt + (long long)(SLOT_CKPT0 - slot) * s.npts;
     return nullptr;
@@ -219,7 +246,8 @@ struct BatchArgs {
     const int2* jobs;                // (shot, tile within the shot) per block
     int njobs;
     int step;                        // forward: time step n (source sample, trace n-1)
-    int f_cur, f_prev, f_next;       // forward: u^n, u^{n-1}, u^{n+1} slots
+    int f_ucur, f_dcur;              // forward: u^n, d^n slots
+    int f_unext, f_dnext;            // u^{n+1}, d^{n+1} arena slots (f_dnext may equal f_dcur)
     int gather;                      // forward: write trace n-1 from u^n
     Sponge sp;
     float q;
@@ -253,57 +281,6 @@ void launch_batch_inject(const BatchShot* shots, int nshots, int max_nrec, int f
 void launch_batch_gather(const BatchShot* shots, int nshots, int max_nrec, int f, int n, hipStream_t s);
 bool launch_batch2d(const BatchArgs& a, int shape, int M, int rows, hipStream_t s);
 int batch_rows();   // rows per thread of the batched tiles (the adjoint's and the default)
-
-// Two-steps-per-launch 2D forward (out of place: u^{n-1}, u^n -> u^{n+1}, u^{n+2}).
-struct TbArgs {
-    const float* __restrict__ uprev;   // u^{n-1}
-    const float* __restrict__ ucur;    // u^n
-    float* __restrict__ out1;          // u^{n+1}
-    float* __restrict__ out2;          // u^{n+2}
-    const float* __restrict__ v;
-    long long ldv;
-    int nx, nz;
-    int tiles_x, ntiles;
-    Sponge sp;
-    long long src;
-    float q;                           // dt^2 / h^2
-    const float* __restrict__ wavelet;
-    int step;                          // n
-    int nrec;
-    const long long* __restrict__ rec_lin;
-    float* __restrict__ trace_a;       // trace n-2 <- u^{n-1}, or nullptr
-    float* __restrict__ trace_b;       // trace n-1 <- u^n, or nullptr
-    Weights w;
-};
-
-bool launch_fwd2d_tb(const TbArgs& a, int shape, int M, int rows, hipStream_t s);
-bool have_fwd2d_tb(int shape, int M, int rows);
-
-// Two steps per launch, 3D cross stencils (k_fwd3d_cross_tb): the same
-// fields as TbArgs on a [nz][ny][nx] window with model strides for v.
-struct Tb3Args {
-    const float* __restrict__ uprev;   // u^{n-1}
-    const float* __restrict__ ucur;    // u^n
-    float* __restrict__ out1;          // u^{n+1}
-    float* __restrict__ out2;          // u^{n+2}
-    const float* __restrict__ v;
-    long long ldv_y, ldv_z;
-    int nx, ny, nz;
-    int tiles_x, tiles_y, ntiles, zchunk;
-    Sponge sp;
-    long long src;
-    float q;                           // dt^2 / h^3
-    const float* __restrict__ wavelet;
-    int step;                          // n (s^n and s^{n+1} are used)
-    int nrec;
-    const long long* __restrict__ rec_lin;
-    float* __restrict__ trace_a;       // trace n-2 <- u^{n-1}, or nullptr
-    float* __restrict__ trace_b;       // trace n-1 <- u^n, or nullptr
-    Weights w;
-};
-
-bool launch_fwd3d_tb(const Tb3Args& a, int shape, int M, int rows, hipStream_t s);
-bool have_fwd3d_tb(int shape, int M, int rows);
 
 // Launchers (one per translation unit).  Return false when the requested
 // (shape, M, rows) combination was not compiled.

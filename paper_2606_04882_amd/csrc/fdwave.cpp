@@ -279,16 +279,21 @@ long long window_points(const fd_shot& s, int ndim) {
     return s.extent[0] * (ndim == 3 ? s.extent[1] : 1) * s.extent[2];
 }
 
-// Slots of the batched adjoint arena (K = segment length, nseg segments).
-// With saved checkpoints (every shot passes fd_shot.ckpt) the checkpoint
-// pairs are read from the caller's buffer and take no arena slots.
+// Slots of the batched adjoint arena (K = segment length, nseg segments):
+// the forward state (u^n, u^{n+1}, d), checkpoint pairs (d^{jK}, u^{jK}), K
+// segment fields for u and one for d, the two adjoint fields and the
+// gradient accumulator.  With saved checkpoints (every shot passes
+// fd_shot.ckpt) the pairs are read from the caller's buffer and take no
+// arena slots.
 struct AdjSlots {
     int nseg, K;
     bool saved = false;
+    static constexpr int kU0 = 0, kU1 = 1, kD = 2;
     int nck() const { return saved ? 0 : 2 * nseg; }
-    int ck(int j, int which) const { return saved ? SLOT_CKPT0 - (2 * j + which) : 2 + 2 * j + which; }
-    int seg(int i) const { return 2 + nck() + i; }
-    int psiA() const { return 2 + nck() + K; }
+    int ck(int j, int which) const { return saved ? SLOT_CKPT0 - (2 * j + which) : 3 + 2 * j + which; }
+    int seg(int i) const { return 3 + nck() + i; }
+    int dseg() const { return 3 + nck() + K; }
+    int psiA() const { return dseg() + 1; }
     int psiB() const { return psiA() + 1; }
     int gacc() const { return psiA() + 2; }
     int count() const { return psiA() + 3; }
@@ -311,12 +316,11 @@ Layout make_layout(const fd_grid* g, const fd_shot* shots, int nshots, int mode,
     off = align256(off + sizeof(float) * (size_t)mpts);
     const bool batch = use_batch(g, nshots, mode);
     const int nseg = mode == MODE_ADJ_SEGMENT ? (g->nt + K - 1) / K : 0;
-    // a single-shot forward keeps four fields so that two-steps-per-launch
-    // kernels can write out of place; the binomial adjoint keeps its fields
-    // in the shared scratch below
+    // a forward arena holds u^n, u^{n+1} and d; the binomial adjoint keeps
+    // its fields in the shared scratch below
     const int nsaved = mode == MODE_ADJ_SEGMENT ? saved_count(shots, nshots) : 0;
     L.nslots = (batch && mode == MODE_ADJ_SEGMENT) ? AdjSlots{nseg, K, nsaved == nshots}.count()
-             : mode == MODE_ADJ_REVOLVE ? 0 : ((!batch && mode == MODE_FORWARD) ? 4 : 2);
+             : mode == MODE_ADJ_REVOLVE ? 0 : 3;
     long long wmax = 0;
     for (int i = 0; i < nshots; ++i) {
         const long long wp = window_points(shots[i], g->ndim);
@@ -330,12 +334,12 @@ Layout make_layout(const fd_grid* g, const fd_shot* shots, int nshots, int mode,
     }
     L.psiA = L.psiB = L.ckpt = L.seg = 0;
     if (mode != MODE_FORWARD && !batch) {
-        // segments: nseg checkpoints of two fields (none when every shot
-        // brings its own) and K segment fields; binomial: K snapshots of two
-        // fields and three working fields (two for the current state, one of
-        // zeros for an absent initial state)
+        // segments: nseg checkpoint pairs (none when every shot brings its
+        // own), K segment fields for u and one for d; binomial: K snapshot
+        // pairs, three working fields (the current state and the next u)
+        // and one of zeros for an absent initial state
         const size_t nck = mode == MODE_ADJ_SEGMENT ? (nsaved == nshots ? 0 : (size_t)nseg) : (size_t)K;
-        const size_t nsegf = mode == MODE_ADJ_SEGMENT ? (size_t)K : 3;
+        const size_t nsegf = mode == MODE_ADJ_SEGMENT ? (size_t)K + 1 : 4;
         L.psiA = off;
         off = align256(off + sizeof(float) * (size_t)wmax);
         L.psiB = off;
@@ -648,173 +652,73 @@ bool launch_step(const CallCtx& c, const ShotCtx& s, const StepArgs& a, hipStrea
     return launch_fwd3d(a, s.st.shape, s.st.M, s.st.rows, st);
 }
 
-bool have_tb(int ndim, int shape, int M, int rows) {
-    return ndim == 2 ? have_fwd2d_tb(shape, M, rows) : have_fwd3d_tb(shape, M, rows);
-}
+// Fields of a shot's forward arena: two buffers for u (u^{n+1} never
+// overwrites u^n, which neighbouring points read in the same launch) and
+// one for d, updated in place.
+float* arena_u(const ShotCtx& s, int i) { return s.bufA + (size_t)i * s.npts; }
+float* arena_d(const ShotCtx& s) { return s.bufA + 2 * (size_t)s.npts; }
 
-// the 3D two-step kernel addresses a plane with 32-bit offsets
-bool tb_fits(const ShotCtx& s) { return (long long)s.nx * s.ny < (1LL << 31); }
-
-// Two steps per launch (no checkpoints): four buffers rotate; traces n-2 and
-// n-1 are gathered from the inputs of the launch covering n, n+1.
-int enqueue_forward_tb(const CallCtx& c, const ShotCtx& s, Recorder& R) {
-    hipStream_t st = R.cur();
+// Initial state (d^0, u^0) into the arena: the caller's, or zeros.
+void load_initial_state(const ShotCtx& s, float* u0, float* d0, hipStream_t st, Recorder& R) {
     const long long n = s.npts;
-    const int nt = c.g->nt, nrec = s.s->nrec;
-    float* prev = s.bufA;
-    float* cur = s.bufA + n;
-    float* f1 = s.bufA + 2 * n;
-    float* f2 = s.bufA + 3 * n;
-    if (s.s->init_prev) launch_copy(prev, s.s->init_prev, n, st); else launch_fill(prev, n, 0.f, st);
-    if (s.s->init_cur) launch_copy(cur, s.s->init_cur, n, st); else launch_fill(cur, n, 0.f, st);
-    launch_rec_index(s.s->rec, nrec, c.g->ndim, s.nx, s.ny, s.nz, s.rec, c.flags, st);
-    R.launched(3);
-    Tb3Args t3;
-    std::memset(&t3, 0, sizeof t3);
-    if (c.g->ndim == 3) {
-        t3.v = s.v;
-        t3.ldv_y = c.ldv_y;
-        t3.ldv_z = c.ldv_z;
-        t3.nx = s.nx;
-        t3.ny = s.ny;
-        t3.nz = s.nz;
-        t3.tiles_x = (s.nx + kTileX - 1) / kTileX;
-        t3.tiles_y = (s.ny + kWaves3 - 1) / kWaves3;
-        t3.zchunk = s.st.zchunk;
-        t3.ntiles = t3.tiles_x * t3.tiles_y * ((s.nz + s.st.zchunk - 1) / s.st.zchunk);
-        t3.sp = c.sp;
-        t3.src = s.src;
-        t3.q = c.q;
-        t3.wavelet = s.s->wavelet;
-        t3.nrec = nrec;
-        t3.rec_lin = s.rec;
-        t3.w = s.st.w32;
-    }
-    TbArgs t;
-    std::memset(&t, 0, sizeof t);
-    t.v = s.v;
-    t.ldv = c.ldv_y;
-    t.nx = s.nx;
-    t.nz = s.nz;
-    t.tiles_x = (s.nx + kTileX - 1) / kTileX;
-    t.ntiles = t.tiles_x * ((s.nz + 4 * s.st.rows - 1) / (4 * s.st.rows));
-    t.sp = c.sp;
-    t.src = s.src;
-    t.q = c.q;
-    t.wavelet = s.s->wavelet;
-    t.nrec = nrec;
-    t.rec_lin = s.rec;
-    t.w = s.st.w32;
-    float* tr = s.s->traces;
-    int step = 0;
-    for (; step + 2 <= nt; step += 2) {
-        t.uprev = prev;
-        t.ucur = cur;
-        t.out1 = f1;
-        t.out2 = f2;
-        t.step = step;
-        t.trace_a = (nrec > 0 && step >= 2) ? tr + (size_t)(step - 2) * nrec : nullptr;
-        t.trace_b = (nrec > 0 && step >= 1) ? tr + (size_t)(step - 1) * nrec : nullptr;
-        bool ok;
-        if (c.g->ndim == 2) {
-            ok = launch_fwd2d_tb(t, s.st.shape, s.st.M, s.st.rows, st);
-        } else {
-            t3.uprev = prev;
-            t3.ucur = cur;
-            t3.out1 = f1;
-            t3.out2 = f2;
-            t3.step = step;
-            t3.trace_a = t.trace_a;
-            t3.trace_b = t.trace_b;
-            ok = launch_fwd3d_tb(t3, s.st.shape, s.st.M, s.st.rows, st);
-        }
-        if (!ok) return fail(FD_EUNSUPPORTED, "two-step kernel not compiled");
-        R.launched();
-        std::swap(prev, f1);
-        std::swap(cur, f2);
-    }
-    // prev = u^{step-1}, cur = u^step; traces step-2 and step-1 are pending
-    if (nrec > 0 && step >= 2) {
-        launch_gather(prev, s.rec, nrec, tr + (size_t)(step - 2) * nrec, st);
-        R.launched();
-    }
-    if (step < nt) {   // odd nt: one single-step launch
-        StepArgs a = base_step(c, s);
-        a.ucur = cur;
-        a.uprev = prev;
-        a.unext = prev;
-        a.step = step;
-        a.trace_out = (nrec > 0 && step >= 1) ? tr + (size_t)(step - 1) * nrec : nullptr;
-        if (!launch_step(c, s, a, st)) return fail(FD_EUNSUPPORTED, "kernel not compiled");
-        R.launched();
-        std::swap(prev, cur);
-    }
-    if (nrec > 0) {   // trace nt-1 <- u^nt
-        launch_gather(cur, s.rec, nrec, tr + (size_t)(nt - 1) * nrec, st);
-        R.launched();
-    }
-    if (s.s->final_prev) launch_copy(s.s->final_prev, prev, n, st);
-    if (s.s->final_cur) launch_copy(s.s->final_cur, cur, n, st);
-    if (c.g->check_finite && nrec > 0) launch_check_finite(tr, (long long)nt * nrec, c.flags, st);
-    R.launched(3);
-    return R.err;
+    if (s.s->init_cur) launch_copy(u0, s.s->init_cur, n, st); else launch_fill(u0, n, 0.f, st);
+    if (s.s->init_diff) launch_copy(d0, s.s->init_diff, n, st); else launch_fill(d0, n, 0.f, st);
+    R.launched(2);
 }
 
-// forward run of one shot.  With ckpt != nullptr, slot j receives
-// (u^{jK-1}, u^{jK}) for every segment start jK; with seg != nullptr too, the
-// steps of the last segment [tail, nt) write u^{n+1} out of place into
-// seg[n - tail] (so the adjoint needs no recompute for that segment).
+// forward run of one shot on the state (u^n, d^n).  With ckpt != nullptr,
+// pair j receives (d^{jK}, u^{jK}) for every segment start jK; with seg !=
+// nullptr too, the steps of the last segment [tail, nt) write u^{n+1} out of
+// place into seg[n - tail] (so the adjoint needs no recompute for that
+// segment).
 int enqueue_forward_shot(const CallCtx& c, const ShotCtx& s, float* ckpt, int K, float* seg,
                          Recorder& R) {
-    if (!ckpt && s.st.tsteps == 2 && c.L.nslots >= 4 && have_tb(c.g->ndim, s.st.shape, s.st.M, s.st.rows) &&
-        tb_fits(s))
-        return enqueue_forward_tb(c, s, R);
     hipStream_t st = R.cur();
     const long long n = s.npts;
     const int nt = c.g->nt;
-    float* prev = s.bufA;
-    float* cur = s.bufB;
-    if (s.s->init_prev) launch_copy(prev, s.s->init_prev, n, st); else launch_fill(prev, n, 0.f, st);
-    if (s.s->init_cur) launch_copy(cur, s.s->init_cur, n, st); else launch_fill(cur, n, 0.f, st);
+    float* U[2] = {arena_u(s, 0), arena_u(s, 1)};
+    float* D = arena_d(s);
+    load_initial_state(s, U[0], D, st, R);
     launch_rec_index(s.s->rec, s.s->nrec, c.g->ndim, s.nx, s.ny, s.nz, s.rec, c.flags, st);
+    R.launched();
     const int tail = (ckpt && seg) ? ((nt - 1) / K) * K : nt;
     if (ckpt) {
-        launch_copy(ckpt, prev, n, st);
-        launch_copy(ckpt + n, cur, n, st);
+        launch_copy(ckpt, D, n, st);
+        launch_copy(ckpt + n, U[0], n, st);
+        R.launched(2);
     }
     StepArgs a = base_step(c, s);
-    const float* ucur = cur;
-    const float* uprev = prev;
+    a.dcur = a.dnext = D;
+    int cur = 0;
+    const float* last = U[0];
     for (int step = 0; step < nt; ++step) {
         a.step = step;
         a.trace_out = (step > 0 && s.s->nrec > 0) ? s.s->traces + (size_t)(step - 1) * s.s->nrec : nullptr;
         if (step < tail) {
-            a.ucur = cur;
-            a.uprev = prev;
-            a.unext = prev;
+            a.ucur = U[cur];
+            a.unext = U[cur ^ 1];
         } else {
             const int i = step - tail;
-            a.ucur = i == 0 ? cur : seg + (size_t)(i - 1) * n;
-            a.uprev = i == 0 ? prev : (i == 1 ? cur : seg + (size_t)(i - 2) * n);
+            a.ucur = i == 0 ? U[cur] : seg + (size_t)(i - 1) * n;
             a.unext = seg + (size_t)i * n;
         }
         if (!launch_step(c, s, a, st)) return fail(FD_EUNSUPPORTED, "kernel not compiled");
         R.launched();
+        last = a.unext;
         if (step < tail) {
-            std::swap(prev, cur);
+            cur ^= 1;
             if (ckpt && (step + 1) % K == 0 && step + 1 < nt) {
-                float* slot = ckpt + (size_t)((step + 1) / K) * 2 * n;
-                launch_copy(slot, prev, n, st);
-                launch_copy(slot + n, cur, n, st);
+                float* pair = ckpt + (size_t)((step + 1) / K) * 2 * n;
+                launch_copy(pair, D, n, st);
+                launch_copy(pair + n, U[cur], n, st);
+                R.launched(2);
             }
         }
-        ucur = a.unext;
-        uprev = a.ucur;
     }
     if (s.s->nrec > 0)
-        launch_gather(ucur, s.rec, s.s->nrec, s.s->traces + (size_t)(nt - 1) * s.s->nrec, st);
-    if (s.s->final_prev) launch_copy(s.s->final_prev, uprev, n, st);
-    if (s.s->final_cur) launch_copy(s.s->final_cur, ucur, n, st);
+        launch_gather(last, s.rec, s.s->nrec, s.s->traces + (size_t)(nt - 1) * s.s->nrec, st);
+    if (s.s->final_diff) launch_copy(s.s->final_diff, D, n, st);
+    if (s.s->final_cur) launch_copy(s.s->final_cur, last, n, st);
     if (c.g->check_finite && s.s->nrec > 0)
         launch_check_finite(s.s->traces, (long long)nt * s.s->nrec, c.flags, st);
     R.launched(4);
@@ -891,16 +795,19 @@ int enqueue_adjoint_shot(const CallCtx& c, const ShotCtx& s, Recorder& R) {
     StepArgs f = base_step(c, s);
     f.trace_out = nullptr;
     AdjArgs a = base_adj(c, s);
+    float* dseg = seg + (size_t)K * n;   // d during a segment's recompute
     for (int j = nseg - 1; j >= 0; --j) {
         const int s0 = j * K, e0 = std::min(nt, s0 + K);
-        const float* ck_prev = ckpt + (size_t)j * 2 * n;
-        const float* ck_cur = ck_prev + n;
-        // recompute u^{s0+1} .. u^{e0} into seg[0 .. e0-s0-1] (the last
-        // segment is already there when this call ran the forward pass)
+        const float* ck_d = ckpt + (size_t)j * 2 * n;
+        const float* ck_u = ck_d + n;
+        // recompute u^{s0+1} .. u^{e0} into seg[0 .. e0-s0-1] from the pair
+        // (d^{s0}, u^{s0}) (the last segment is already there when this call
+        // ran the forward pass); d goes to dseg, in place after the first step
         for (int step = s0; step < e0 && (j < nseg - 1 || saved); ++step) {
             const int i = step - s0;
-            f.ucur = i == 0 ? ck_cur : seg + (size_t)(i - 1) * n;
-            f.uprev = i == 0 ? ck_prev : (i == 1 ? ck_cur : seg + (size_t)(i - 2) * n);
+            f.ucur = i == 0 ? ck_u : seg + (size_t)(i - 1) * n;
+            f.dcur = i == 0 ? ck_d : dseg;
+            f.dnext = dseg;
             f.unext = seg + (size_t)i * n;
             f.step = step;
             if (!launch_step(c, s, f, st)) return fail(FD_EUNSUPPORTED, "kernel not compiled");
@@ -942,7 +849,8 @@ int enqueue_adjoint_shot(const CallCtx& c, const ShotCtx& s, Recorder& R) {
 // binomial checkpointing (Griewank & Walther, ACM TOMS 26, 2000: "revolve")
 // ---------------------------------------------------------------------------
 // The adjoint iteration k (k = nt .. 1) needs u^k, i.e. the forward state
-// S_k = (u^{k-1}, u^k); S_0 is the initial data.  With s snapshot slots, the
+// S_k = (d^k, u^k) (difference form, d^k = u^k - u^{k-1}); S_0 is the
+// initial data.  With s snapshot slots, the
 // least number of forward steps that serves every iteration is, for
 // l = nt + 1 and r = s + 1 stored states (S_0 included), t l - C(r+t, r+1)
 // with t the least integer such that C(r+t, r) >= l.  The plan reaches it by
@@ -1043,24 +951,29 @@ int enqueue_adjoint_revolve(const CallCtx& c, const ShotCtx& s, Recorder& R) {
     const long long n = s.npts;
     float* ckpt = (float*)(c.ws + c.L.ckpt);
     float* W0 = (float*)(c.ws + c.L.seg);
-    float* Z = W0 + 2 * n;
+    float* Z = W0 + 3 * n;
     float* pa = (float*)(c.ws + c.L.psiA);
     float* pb = (float*)(c.ws + c.L.psiB);
     RevolvePlanner planner;
     planner.plan(nt, nsnap);
     const std::vector<int>& ops = planner.ops;
 
-    // pool field i: the snapshot region for i < 2 nsnap, then W0, W1
-    const int npool = 2 * nsnap + 2;
+    // pool field i: the snapshot region for i < 2 nsnap, then W0, W1, W2.
+    // A state is (U, D) = (u^k, d^k); snapshots reference pool fields
+    // (pins), nothing is copied.  A step writes u^{k+1} into a free field and
+    // d^{k+1} over d^k unless d^k is referenced.  At most 2 nsnap + 2 fields
+    // are referenced (the snapshots and an unreferenced current state, whose
+    // d is then updated in place), so a step always finds the fields it needs.
+    const int npool = 2 * nsnap + 3;
     auto field = [&](int i) { return i < 2 * nsnap ? ckpt + (size_t)i * n : W0 + (size_t)(i - 2 * nsnap) * n; };
     auto index = [&](const float* f) -> int {
         if (nsnap > 0 && f >= ckpt && f < ckpt + (size_t)2 * nsnap * n) return (int)((f - ckpt) / n);
-        if (f == W0) return 2 * nsnap;
-        if (f == W0 + n) return 2 * nsnap + 1;
+        for (int w = 0; w < 3; ++w)
+            if (f == W0 + (size_t)w * n) return 2 * nsnap + w;
         return -1;   // initial data or the zero field
     };
     std::vector<int> pins(npool, 0);
-    std::vector<const float*> snap_p(std::max(nsnap, 1), nullptr), snap_c(std::max(nsnap, 1), nullptr);
+    std::vector<const float*> snap_u(std::max(nsnap, 1), nullptr), snap_d(std::max(nsnap, 1), nullptr);
     std::vector<int> snap_step(std::max(nsnap, 1), 0);
     auto pin = [&](const float* f, int d) {
         const int i = index(f);
@@ -1069,14 +982,14 @@ int enqueue_adjoint_revolve(const CallCtx& c, const ShotCtx& s, Recorder& R) {
 
     launch_rec_index(s.s->rec, nrec, c.g->ndim, s.nx, s.ny, s.nz, s.rec, c.flags, st);
     R.launched();
-    if (!s.s->init_prev || !s.s->init_cur) {
+    if (!s.s->init_diff || !s.s->init_cur) {
         launch_fill(Z, n, 0.f, st);
         R.launched();
     }
-    const float* init_p = s.s->init_prev ? s.s->init_prev : Z;
-    const float* init_c = s.s->init_cur ? s.s->init_cur : Z;
-    const float* P = init_p;
-    const float* C = init_c;
+    const float* init_u = s.s->init_cur ? s.s->init_cur : Z;
+    const float* init_d = s.s->init_diff ? s.s->init_diff : Z;
+    const float* U = init_u;
+    const float* D = init_d;
     int cur = 0, hi = 0;
     StepArgs f = base_step(c, s);
     launch_fill(pa, n, 0.f, st);   // psi^{nt+1}
@@ -1089,51 +1002,57 @@ int enqueue_adjoint_revolve(const CallCtx& c, const ShotCtx& s, Recorder& R) {
         const int op = ops[i], arg = ops[i + 1];
         if (op == FD_OP_ADVANCE) {
             while (cur < arg) {
-                const int ip = index(P), ic = index(C);
-                int id = (ip >= 0 && pins[ip] == 0) ? ip : -1;
-                for (int j = 0; j < npool && id < 0; ++j)
-                    if (pins[j] == 0 && j != ip && j != ic) id = j;
-                if (id < 0) return fail(FD_EDEVICE, "binomial adjoint: no free field (internal error)");
-                float* D = field(id);
-                f.ucur = C;
-                f.uprev = P;
-                f.unext = D;
+                const int iu = index(U), id = index(D);
+                auto free_field = [&](int except) {
+                    for (int j = 0; j < npool; ++j)
+                        if (pins[j] == 0 && j != iu && j != id && j != except) return j;
+                    return -1;
+                };
+                const int ju = free_field(-1);
+                const int jd = (id >= 0 && pins[id] == 0) ? id : free_field(ju);
+                if (ju < 0 || jd < 0) return fail(FD_EDEVICE, "binomial adjoint: no free field (internal error)");
+                float* Un = field(ju);
+                float* Dn = field(jd);
+                f.ucur = U;
+                f.dcur = D;
+                f.dnext = Dn;
+                f.unext = Un;
                 f.step = cur;
                 f.trace_out = (cur >= hi && cur >= 1 && nrec > 0) ? s.s->traces + (size_t)(cur - 1) * nrec : nullptr;
                 if (!launch_step(c, s, f, st)) return fail(FD_EUNSUPPORTED, "kernel not compiled");
                 R.launched();
-                P = C;
-                C = D;
+                U = Un;
+                D = Dn;
                 ++cur;
                 if (cur > hi) {
                     hi = cur;
-                    if (hi == nt) {   // trace nt-1 <- u^nt; final states
-                        if (nrec > 0) launch_gather(C, s.rec, nrec, s.s->traces + (size_t)(nt - 1) * nrec, st);
-                        if (s.s->final_prev) launch_copy(s.s->final_prev, P, n, st);
-                        if (s.s->final_cur) launch_copy(s.s->final_cur, C, n, st);
+                    if (hi == nt) {   // trace nt-1 <- u^nt; final state
+                        if (nrec > 0) launch_gather(U, s.rec, nrec, s.s->traces + (size_t)(nt - 1) * nrec, st);
+                        if (s.s->final_diff) launch_copy(s.s->final_diff, D, n, st);
+                        if (s.s->final_cur) launch_copy(s.s->final_cur, U, n, st);
                         R.launched(3);
                     }
                 }
             }
         } else if (op == FD_OP_STORE) {
-            if (snap_p[arg]) {
-                pin(snap_p[arg], -1);
-                pin(snap_c[arg], -1);
+            if (snap_u[arg]) {
+                pin(snap_u[arg], -1);
+                pin(snap_d[arg], -1);
             }
-            snap_p[arg] = P;
-            snap_c[arg] = C;
+            snap_u[arg] = U;
+            snap_d[arg] = D;
             snap_step[arg] = cur;
-            pin(P, 1);
-            pin(C, 1);
+            pin(U, 1);
+            pin(D, 1);
         } else if (op == FD_OP_RESTORE) {
-            P = arg < 0 ? init_p : snap_p[arg];
-            C = arg < 0 ? init_c : snap_c[arg];
+            U = arg < 0 ? init_u : snap_u[arg];
+            D = arg < 0 ? init_d : snap_d[arg];
             cur = arg < 0 ? 0 : snap_step[arg];
         } else {   // FD_OP_ADJOINT: psi^k from psi^{k+1}, psi^{k+2}; gradient with u^k
             a.pcur = pcur;
             a.pprev = pprev;
             a.pnext = pprev;
-            a.ufwd = C;
+            a.ufwd = U;
             a.with_grad = arg < nt;
             a.with_update = 1;
             if (!launch_adj(c, s, a, st)) return fail(FD_EUNSUPPORTED, "adjoint kernel not compiled");
@@ -1176,14 +1095,15 @@ int enqueue_batched(const CallCtx& c, Recorder& R) {
         launch_rec_index(s.s->rec, s.s->nrec, 2, s.nx, 1, s.nz, s.rec, c.flags, st);
         R.launched();
     }
-    launch_batch_copy(dshots, ns, maxn, 0, SLOT_INIT_PREV, st);
-    launch_batch_copy(dshots, ns, maxn, 1, SLOT_INIT_CUR, st);
+    // state: u^n in slot n&1, d in slot 2 (updated in place)
+    launch_batch_copy(dshots, ns, maxn, 0, SLOT_INIT_CUR, st);
+    launch_batch_copy(dshots, ns, maxn, 2, SLOT_INIT_DIFF, st);
     R.launched(2);
     // checkpoints into the callers' buffers (shots without one are skipped)
     const int K = c.K;
     if (K > 0) {
-        launch_batch_copy(dshots, ns, maxn, SLOT_CKPT0, 0, st);
-        launch_batch_copy(dshots, ns, maxn, SLOT_CKPT0 - 1, 1, st);
+        launch_batch_copy(dshots, ns, maxn, SLOT_CKPT0, 2, st);
+        launch_batch_copy(dshots, ns, maxn, SLOT_CKPT0 - 1, 0, st);
         R.launched(2);
     }
     BatchArgs a;
@@ -1191,12 +1111,13 @@ int enqueue_batched(const CallCtx& c, Recorder& R) {
     a.sp = c.sp;
     a.q = c.q;
     a.gather = 1;
+    a.f_dcur = a.f_dnext = 2;
     R.fork(c.nbranch);
     bool ok = true;
     for (int n = 0; n < nt && ok; ++n) {
         a.step = n;
-        a.f_cur = (n + 1) & 1;      // step n reads u^n from slot (n+1)&1
-        a.f_prev = a.f_next = n & 1; // and writes u^{n+1} over u^{n-1}
+        a.f_ucur = n & 1;
+        a.f_unext = (n + 1) & 1;
         for (const CallCtx::Group& g : c.groups) {
             a.jobs = jobs + g.job0;
             a.njobs = (int)g.njobs;
@@ -1204,22 +1125,22 @@ int enqueue_batched(const CallCtx& c, Recorder& R) {
         }
         R.launched((int)c.groups.size());
         if (K > 0 && (n + 1) % K == 0 && n + 1 < nt) {
-            // pair j = (n+1)/K: (u^n, u^{n+1}) from slots (n+1)&1 and n&1
+            // pair j = (n+1)/K: (d^{n+1}, u^{n+1}) from slots 2 and (n+1)&1
             const int j = (n + 1) / K;
             for (const CallCtx::Group& g : c.groups) {
-                launch_batch_copy(dshots + g.d0, g.dn, g.maxn, SLOT_CKPT0 - 2 * j, (n + 1) & 1, R.on(g.branch));
-                launch_batch_copy(dshots + g.d0, g.dn, g.maxn, SLOT_CKPT0 - 2 * j - 1, n & 1, R.on(g.branch));
+                launch_batch_copy(dshots + g.d0, g.dn, g.maxn, SLOT_CKPT0 - 2 * j, 2, R.on(g.branch));
+                launch_batch_copy(dshots + g.d0, g.dn, g.maxn, SLOT_CKPT0 - 2 * j - 1, (n + 1) & 1, R.on(g.branch));
             }
             R.launched(2 * (int)c.groups.size());
         }
     }
     R.join();
     if (!ok) return fail(FD_EUNSUPPORTED, "batched kernel not compiled");
-    const int last = (nt - 1) & 1, before = nt & 1;
+    const int last = nt & 1;
     launch_batch_gather(dshots, ns, maxrec, last, nt - 1, st);
     R.launched();
     for (const ShotCtx& s : c.shots) {
-        if (s.s->final_prev) launch_copy(s.s->final_prev, s.bufA + before * s.npts, s.npts, st);
+        if (s.s->final_diff) launch_copy(s.s->final_diff, s.bufA + 2 * s.npts, s.npts, st);
         if (s.s->final_cur) launch_copy(s.s->final_cur, s.bufA + last * s.npts, s.npts, st);
         if (c.g->check_finite && s.s->nrec > 0)
             launch_check_finite(s.s->traces, (long long)nt * s.s->nrec, c.flags, st);
@@ -1256,10 +1177,10 @@ int enqueue_batched_adjoint(const CallCtx& c, Recorder& R) {
     };
     copy_all(SLOT_GACC, SLOT_ZERO);
     if (!saved) {
-        copy_all(0, SLOT_INIT_PREV);
-        copy_all(1, SLOT_INIT_CUR);
-        copy_all(S.ck(0, 0), 0);
-        copy_all(S.ck(0, 1), 1);
+        copy_all(S.kU0, SLOT_INIT_CUR);
+        copy_all(S.kD, SLOT_INIT_DIFF);
+        copy_all(S.ck(0, 0), S.kD);
+        copy_all(S.ck(0, 1), S.kU0);
     }
     // per-group helpers, each on the group's branch
     auto copy = [&](int dst, int src) {
@@ -1298,25 +1219,25 @@ int enqueue_batched_adjoint(const CallCtx& c, Recorder& R) {
 
     R.fork(c.nbranch);
     const int tail = ((nt - 1) / K) * K;
-    int cur = 1, prev = 0, last = 1;
+    int cur = S.kU0, last = S.kU0;
     for (int n = 0; n < nt && ok && !saved; ++n) {
         f.step = n;
         f.gather = 1;
+        f.f_dcur = f.f_dnext = S.kD;
         if (n < tail) {
-            f.f_cur = cur;
-            f.f_prev = f.f_next = prev;
+            f.f_ucur = cur;
+            f.f_unext = cur ^ 1;
         } else {
             const int i = n - tail;
-            f.f_cur = i == 0 ? cur : S.seg(i - 1);
-            f.f_prev = i == 0 ? prev : (i == 1 ? cur : S.seg(i - 2));
-            f.f_next = S.seg(i);
+            f.f_ucur = i == 0 ? cur : S.seg(i - 1);
+            f.f_unext = S.seg(i);
         }
         fwd();
-        last = f.f_next;
+        last = f.f_unext;
         if (n < tail) {
-            std::swap(cur, prev);
+            cur ^= 1;
             if ((n + 1) % K == 0 && n + 1 < nt) {
-                copy(S.ck((n + 1) / K, 0), prev);
+                copy(S.ck((n + 1) / K, 0), S.kD);
                 copy(S.ck((n + 1) / K, 1), cur);
             }
         }
@@ -1336,9 +1257,10 @@ int enqueue_batched_adjoint(const CallCtx& c, Recorder& R) {
         for (int step = s0; step < e0 && (j < nseg - 1 || saved); ++step) {
             const int i = step - s0;
             f.step = step;
-            f.f_cur = i == 0 ? S.ck(j, 1) : S.seg(i - 1);
-            f.f_prev = i == 0 ? S.ck(j, 0) : (i == 1 ? S.ck(j, 1) : S.seg(i - 2));
-            f.f_next = S.seg(i);
+            f.f_ucur = i == 0 ? S.ck(j, 1) : S.seg(i - 1);
+            f.f_dcur = i == 0 ? S.ck(j, 0) : S.dseg();
+            f.f_dnext = S.dseg();
+            f.f_unext = S.seg(i);
             fwd();
         }
         for (int k = e0; k > s0; --k) {
@@ -1444,7 +1366,7 @@ void build_batch_blob(CallCtx& c, int mode) {
         d.rec_lin = s.rec;
         d.traces = s.s->traces;
         d.trace_adj = s.s->trace_adj;
-        d.init_prev = s.s->init_prev;
+        d.init_diff = s.s->init_diff;
         d.init_cur = s.s->init_cur;
         d.gacc = mode == MODE_ADJ_SEGMENT ? s.bufA + (long long)S.gacc() * s.npts : nullptr;
         d.ckpt = s.s->ckpt;
@@ -1875,10 +1797,31 @@ int fd_weights_set_n(int ndim, int shape, int M, int N, const double* w, int nw,
             st.w32.mz[dx] = mz;
         }
     }
+    if (ndim == 3 && ks == SH_RHOMBUS) {
+        // the 3D L1-ball kernel folds the in-plane groups' centre terms into
+        // the z differences of the centre column:
+        // wc[dz] = w(0,0,dz) + sum_{a >= b >= 0, 1 <= a+b <= M-dz} n_ab w(a,b,dz)
+        auto wof = [&](int x, int y, int z) -> double {
+            int t[3] = {x, y, z};
+            std::sort(t, t + 3, [](int p, int q) { return p > q; });
+            for (int i = 0; i < nw; ++i)
+                if (o[i].rep[0] == t[0] && o[i].rep[1] == t[1] && o[i].rep[2] == t[2]) return (double)(float)w[i];
+            return 0.0;
+        };
+        for (int dz = 1; dz <= M; ++dz) {
+            double acc = wof(0, 0, dz);
+            for (int s = 1; s <= M - dz; ++s)
+                for (int b = 0; b <= s / 2; ++b) {
+                    const int a = s - b;
+                    acc += ((b == 0 || a == b) ? 4.0 : 8.0) * wof(a, b, dz);
+                }
+            st.w32.wc[dz] = (float)acc;
+        }
+    }
     st.cfl = 2.0 / std::sqrt(mneg);
     st.rows = default_rows(ndim, ks, M);
     st.zchunk = (ndim == 3 && ks == SH_CROSS) ? 256 : 64;
-    st.tsteps = (ndim == 2 && have_fwd2d_tb(ks, M, st.rows)) ? 2 : 1;
+    st.tsteps = 1;
     std::lock_guard<std::mutex> lk(g_mu);
     for (size_t i = 0; i < g_stencils.size(); ++i) {
         const Stencil& e = g_stencils[i];
@@ -1915,7 +1858,6 @@ int fd_set_tile(int stencil_id, int rows, int zchunk) {
     if (!have) return fail(FD_EUNSUPPORTED, "no kernel compiled for rows = %d", rows);
     s.rows = rows;
     s.zchunk = zchunk;
-    if (s.tsteps == 2 && !have_tb(s.ndim, s.shape, s.M, rows)) s.tsteps = 1;
     return FD_OK;
 }
 
@@ -1923,10 +1865,8 @@ int fd_set_time_block(int stencil_id, int steps) {
     std::lock_guard<std::mutex> lk(g_mu);
     if (stencil_id < 0 || stencil_id >= (int)g_stencils.size()) return fail(FD_EINVAL, "unknown stencil id");
     if (steps != 1 && steps != 2) return fail(FD_EINVAL, "steps must be 1 or 2");
-    Stencil& s = g_stencils[stencil_id];
-    if (steps == 2 && !have_tb(s.ndim, s.shape, s.M, s.rows))
-        return fail(FD_EUNSUPPORTED, "no two-step kernel for this stencil and tile height");
-    s.tsteps = steps;
+    if (steps == 2) return fail(FD_EUNSUPPORTED, "two time steps per launch are not compiled");
+    g_stencils[stencil_id].tsteps = 1;
     return FD_OK;
 }
 

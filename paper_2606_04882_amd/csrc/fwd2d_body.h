@@ -1,5 +1,6 @@
 // One 2D forward tile (shared by the single-shot and the batched kernels):
-// LDS-staged stencil in difference form, leapfrog, damping band, source.
+// LDS-staged stencil in difference form, leapfrog in difference form
+// (d^{n+1}, u^{n+1} from u^n, d^n: see delta_update), damping band, source.
 #pragma once
 
 #include "fd_kernels.h"
@@ -8,9 +9,10 @@
 namespace fdw {
 
 struct Tile2D {
-    const float* __restrict__ ucur;
-    const float* uprev;
-    float* unext;
+    const float* __restrict__ ucur;  // u^n
+    const float* dcur;               // d^n
+    float* dnext;                    // d^{n+1} (may equal dcur: each point is read and written by one thread)
+    float* unext;                    // u^{n+1}
     const float* __restrict__ v;
     long long ldv;                 // model row stride of v
     int nx, nz;                    // window
@@ -43,15 +45,15 @@ __device__ __forceinline__ void fwd2d_tile(const Tile2D& t, const Sponge& sp, co
     const int nrow = t.nz - zr;                         // rows left in the window
     const bool colok = gx < t.nx;
     const long long base = (long long)zr * t.nx + gx;   // window-linear index of that row
-    float up[RY], vv[RY];
+    float dd[RY], vv[RY];
     {
         long long iu = base, iv = (long long)zr * t.ldv + gx;   // row indices, stepped per row
 #pragma unroll
         for (int j = 0; j < RY; ++j) {
-            up[j] = 0.f;
+            dd[j] = 0.f;
             vv[j] = 0.f;
             if (colok && j < nrow) {
-                up[j] = t.uprev[iu];
+                dd[j] = t.dcur[iu];
                 vv[j] = t.v[iv];
             }
             iu += t.nx;
@@ -77,7 +79,9 @@ __device__ __forceinline__ void fwd2d_tile(const Tile2D& t, const Sponge& sp, co
 #pragma unroll
             for (int j = 0; j < RY; ++j) {
                 if (j >= nrow) break;
-                t.unext[base + (long long)j * t.nx] = fmaf(vv[j], acc[j], 2.f * uc[j] - up[j]);
+                const float d = fmaf(vv[j], acc[j], dd[j]);
+                t.dnext[base + (long long)j * t.nx] = d;
+                t.unext[base + (long long)j * t.nx] = uc[j] + d;
             }
             return;
         }
@@ -89,19 +93,15 @@ __device__ __forceinline__ void fwd2d_tile(const Tile2D& t, const Sponge& sp, co
         const long long k = (long long)gz * t.nx + gx;
         const bool at_src = k == t.src;
         const int dzb = sp.nb > 0 ? band_depth(gz, t.nz, sp.nb) : 0;
-        float r;
-        if ((dxb | dzb) == 0) {
-            r = fmaf(vv[j], acc[j], 2.f * uc[j] - up[j]);
-            if (at_src) r += t.qs;
-        } else {
+        const bool inband = (dxb | dzb) != 0;
+        float e = 0.f;
+        if (inband) {
             const float ex = dxb * sp.inv_nb, ez = dzb * sp.inv_nb;
-            const float e = sp.escale * fmaf(ex, ex, ez * ez);
-            r = fmaf(-(1.f - e), up[j], 2.f * uc[j]);
-            r = fmaf(vv[j], acc[j], r);
-            if (at_src) r += t.qs;
-            r = r / (1.f + e);
+            e = sp.escale * fmaf(ex, ex, ez * ez);
         }
-        t.unext[k] = r;
+        const float d = delta_update(dd[j], vv[j], acc[j], inband, e, at_src, t.qs);
+        t.dnext[k] = d;
+        t.unext[k] = uc[j] + d;
     }
 }
 

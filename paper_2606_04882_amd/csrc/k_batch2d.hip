@@ -36,7 +36,7 @@ __global__ __launch_bounds__(kBlock) void k_batch2d(BatchArgs p) {
     const BatchShot& s = p.shots[jb.x];
     const int lt = jb.y;
     const int n = p.step;
-    const float* cur = slot_ptr(s, p.f_cur);
+    const float* cur = slot_ptr(s, p.f_ucur);
     if (p.gather && n > 0) {
         float* out = s.traces + (long long)(n - 1) * s.nrec;
         for (int r = lt * kBlock + threadIdx.x; r < s.nrec; r += s.ntiles * kBlock) {
@@ -46,8 +46,9 @@ __global__ __launch_bounds__(kBlock) void k_batch2d(BatchArgs p) {
     }
     Tile2D tl;
     tl.ucur = cur;
-    tl.uprev = slot_ptr(s, p.f_prev);
-    tl.unext = s.arena + (long long)p.f_next * s.npts;
+    tl.dcur = slot_ptr(s, p.f_dcur);
+    tl.dnext = s.arena + (long long)p.f_dnext * s.npts;
+    tl.unext = s.arena + (long long)p.f_unext * s.npts;
     tl.v = s.v;
     tl.ldv = s.ldv;
     tl.nx = s.nx;

@@ -4,13 +4,16 @@
 //   u^{n+1} = b [ 2 u^n - a u^{n-1} + v (W * u^n) + q s^n delta_{x,xs} ]
 //
 // (Sec. 3.1 eq. wave_eq with the damping term of Sec. 3.1; Sec. 3.2
-// eqs. spacexz_derivative2_sym and time_derivative1.)  One launch per step;
-// u^n is read-only during the launch, so the receiver samples of u^n (the
-// trace of step n-1) are gathered here as well, and u^{n+1} may overwrite
-// u^{n-1} in place: each point's u^{n-1} is read only by its own thread.
+// eqs. spacexz_derivative2_sym and time_derivative1), evaluated in
+// difference form on the state (u^n, d^n) (see delta_update).  One launch
+// per step; u^n is read-only during the launch, so the receiver samples of
+// u^n (the trace of step n-1) are gathered here as well; d^{n+1} may
+// overwrite d^n in place (each point's d^n is read only by its own thread),
+// u^{n+1} goes to a second buffer.
 //
-// Memory traffic per point: read u^n (plus halo, from L2), u^{n-1}, v;
-// write u^{n+1}: 16 B of algorithmic HBM traffic.
+// Memory traffic per point: read u^n (plus halo, from L2), d^n, v; write
+// d^{n+1}, u^{n+1}: 20 B (16 B is the algorithmic minimum of the scheme; the
+// extra write keeps the difference d at full precision).
 #include "fwd2d_body.h"
 
 namespace fdw {
@@ -28,7 +31,8 @@ __global__ __launch_bounds__(kBlock) void k_fwd2d(StepArgs p) {
     const int bz = t / p.tiles_x, bx = t - bz * p.tiles_x;
     Tile2D tl;
     tl.ucur = p.ucur;
-    tl.uprev = p.uprev;
+    tl.dcur = p.dcur;
+    tl.dnext = p.dnext;
     tl.unext = p.unext;
     tl.v = p.v;
     tl.ldv = p.ldv_y;

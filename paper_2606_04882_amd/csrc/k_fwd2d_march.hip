@@ -8,7 +8,7 @@
 // neighbours (double-buffered: one barrier per row; the operands of row z+1
 // are fetched while row z is computed).  Every value of u^n is read once per
 // block plus 2M rows per chunk, instead of the 2M halo rows of every
-// 4*rows-row tile of k_fwd2d; u^{n-1}, v and u^{n+1} are streamed
+// 4*rows-row tile of k_fwd2d; d^n, v, d^{n+1} and u^{n+1} are streamed
 // non-temporally.  The per-point arithmetic is that of the cross path of
 // stencil2d (z pairs first, then x pairs, in the difference form) and of
 // fwd2d_tile, so results are bitwise those of k_fwd2d.  Selected with one
@@ -49,12 +49,12 @@ __global__ __launch_bounds__(kBlock3) void k_fwd2d_march(StepArgs p) {
     const int hx = tid < M ? x0 - M + tid : x0 + W + tid - M;
     const bool hok = hthr && (unsigned)hx < (unsigned)p.nx;
     const int hslot = tid < M ? tid : W + tid;
-    float front = 0.f, up = 0.f, vv = 0.f, hv = 0.f;
+    float front = 0.f, dd = 0.f, vv = 0.f, hv = 0.f;
     auto fetch = [&](int z) {
         const bool in = z < ze;
         const int zz = z + M;
         front = (xok && in && zz < p.nz) ? p.ucur[zz * nx + gx] : 0.f;
-        up = (xok && in) ? __builtin_nontemporal_load(p.uprev + z * nx + gx) : 0.f;
+        dd = (xok && in) ? __builtin_nontemporal_load(p.dcur + z * nx + gx) : 0.f;
         vv = (xok && in) ? __builtin_nontemporal_load(p.v + z * p.ldv_y + gx) : 0.f;
         hv = (hok && in) ? p.ucur[z * nx + hx] : 0.f;
     };
@@ -65,7 +65,7 @@ __global__ __launch_bounds__(kBlock3) void k_fwd2d_march(StepArgs p) {
     for (int z = zs; z < ze; ++z) {
         float* row = rows[buf];
         q[2 * M] = front;
-        const float upc = up, vvc = vv;
+        const float ddc = dd, vvc = vv;
         row[M + tid] = q[M];
         if (hthr) row[hslot] = hv;
         fetch(z + 1);
@@ -80,19 +80,15 @@ __global__ __launch_bounds__(kBlock3) void k_fwd2d_march(StepArgs p) {
                 acc = fmaf(p.w.w[dx], fmaf(-2.f, u, row[M + tid - dx] + row[M + tid + dx]), acc);
             const long long k = z * nx + gx;
             const int dzb = p.sp.nb > 0 ? band_depth(z, p.nz, p.sp.nb) : 0;
-            float r;
-            if ((dxb | dzb) == 0) {
-                r = fmaf(vvc, acc, 2.f * u - upc);
-                if (k == p.src) r += qs;
-            } else {
+            const bool inband = (dxb | dzb) != 0;
+            float e = 0.f;
+            if (inband) {
                 const float ex = dxb * p.sp.inv_nb, ez = dzb * p.sp.inv_nb;
-                const float e = p.sp.escale * fmaf(ex, ex, ez * ez);
-                r = fmaf(-(1.f - e), upc, 2.f * u);
-                r = fmaf(vvc, acc, r);
-                if (k == p.src) r += qs;
-                r = r / (1.f + e);
+                e = p.sp.escale * fmaf(ex, ex, ez * ez);
             }
-            __builtin_nontemporal_store(r, p.unext + k);
+            const float d = delta_update(ddc, vvc, acc, inband, e, k == p.src, qs);
+            __builtin_nontemporal_store(d, p.dnext + k);
+            __builtin_nontemporal_store(u + d, p.unext + k);
         }
 #pragma unroll
         for (int i = 0; i < 2 * M; ++i) q[i] = q[i + 1];

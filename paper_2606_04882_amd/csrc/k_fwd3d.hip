@@ -13,13 +13,17 @@
 //
 // Every value of u^n is read from HBM once per block (plus the z warm-up of 2M
 // planes per chunk and the xy halo, which neighbouring blocks of the same XCD
-// also read, mostly from L2).  Algorithmic traffic per update: 16 B forward,
-// 28 B adjoint (psi^{k+1}, u^k, psi^{k+2}, v, grad read/write, psi^k write).
+// also read, mostly from L2).  The forward steps advance the difference-form
+// state (u^n, d^n) (see delta_update): 20 B per update (read u^n, d^n, v;
+// write d^{n+1}, u^{n+1}; the scheme's minimum is 16 B).  Adjoint: 28 B
+// (psi^{k+1}, u^k, psi^{k+2}, v, grad read/write, psi^k write).
 //
 // Difference form: points are grouped by their absolute offset pattern
 // (|dx|, |dy|, |dz|), each group shares one orbit weight, and
 //     L += w * (sum_of_group - |group| * u(x)).
 #include "fd_kernels.h"
+
+#include <type_traits>
 
 namespace fdw {
 
@@ -217,14 +221,14 @@ __global__ __launch_bounds__(kBlock3) void k_fwd3d_cross(StepArgs p) {
         }
     }
     Halo<M, RY> halo;
-    float front[RY], up[RY], vv[RY];
+    float front[RY], dd[RY], vv[RY];
     auto fetch = [&](int z) {
 #pragma unroll
         for (int j = 0; j < RY; ++j) {
             const int zz = z + M;
             const bool in = ok[j] && z < b.ze;
             front[j] = (in && zz < p.nz) ? p.ucur[zz * plane + col[j]] : 0.f;
-            up[j] = in ? __builtin_nontemporal_load(p.uprev + z * plane + col[j]) : 0.f;
+            dd[j] = in ? __builtin_nontemporal_load(p.dcur + z * plane + col[j]) : 0.f;
             vv[j] = in ? __builtin_nontemporal_load(p.v + (long long)z * p.ldv_z + vcol[j]) : 0.f;
         }
         if (z < b.ze) halo.fetch(p.ucur, p.nx, p.ny, p.nz, b.x0, b.y0, z);
@@ -233,11 +237,11 @@ __global__ __launch_bounds__(kBlock3) void k_fwd3d_cross(StepArgs p) {
     int buf = 0;
     for (int z = b.zs; z < b.ze; ++z) {
         float* tile = tiles[buf];
-        float upc[RY], vvc[RY];
+        float ddc[RY], vvc[RY];
 #pragma unroll
         for (int j = 0; j < RY; ++j) {
             q[j][2 * M] = front[j];
-            upc[j] = up[j];
+            ddc[j] = dd[j];
             vvc[j] = vv[j];
             tile[(b.ty * RY + j + M) * G::LW + b.tx + M] = q[j][M];
         }
@@ -252,18 +256,9 @@ __global__ __launch_bounds__(kBlock3) void k_fwd3d_cross(StepArgs p) {
                 const long long k = z * plane + col[j];
                 bool inband;
                 const float e = damp_e(p.sp, b.gx, gy, z, p.nx, p.ny, p.nz, inband);
-                const float uc = q[j][M];
-                float r;
-                if (!inband) {
-                    r = fmaf(vvc[j], L, 2.f * uc - upc[j]);
-                    if (k == p.src) r += p.q * p.wavelet[p.step];
-                } else {
-                    r = fmaf(-(1.f - e), upc[j], 2.f * uc);
-                    r = fmaf(vvc[j], L, r);
-                    if (k == p.src) r += p.q * p.wavelet[p.step];
-                    r = r / (1.f + e);
-                }
-                __builtin_nontemporal_store(r, p.unext + k);
+                const float d = delta_update(ddc[j], vvc[j], L, inband, e, k == p.src, p.q * p.wavelet[p.step]);
+                __builtin_nontemporal_store(d, p.dnext + k);
+                __builtin_nontemporal_store(q[j][M] + d, p.unext + k);
             }
         }
 #pragma unroll
@@ -527,13 +522,13 @@ __global__ __launch_bounds__(kBlock3) void k_fwd3d_gen(StepArgs p) {
         pf.fetch(p.ucur, p.nx, p.ny, p.nz, b.x0, b.y0, b.zs - M + i);
         pf.store(ring + i * G::PLANE);
     }
-    float up[RY], vv[RY];
+    float dd[RY], vv[RY];
     auto fetch_pointwise = [&](int z) {
 #pragma unroll
         for (int j = 0; j < RY; ++j) {
             const int gy = b.y0 + b.ty * RY + j;
             const bool ok = b.gx < p.nx && gy < p.ny && z < b.ze;
-            up[j] = ok ? p.uprev[((long long)z * p.ny + gy) * p.nx + b.gx] : 0.f;
+            dd[j] = ok ? p.dcur[((long long)z * p.ny + gy) * p.nx + b.gx] : 0.f;
             vv[j] = ok ? p.v[(long long)z * p.ldv_z + (long long)gy * p.ldv_y + b.gx] : 0.f;
         }
     };
@@ -545,10 +540,10 @@ __global__ __launch_bounds__(kBlock3) void k_fwd3d_gen(StepArgs p) {
         int slot = base + M + 1;
         if (slot >= NR) slot -= NR;
         pf.store(ring + slot * G::PLANE);          // plane z+M+1, needed from the next plane on
-        float upc[RY], vvc[RY];
+        float ddc[RY], vvc[RY];
 #pragma unroll
         for (int j = 0; j < RY; ++j) {
-            upc[j] = up[j];
+            ddc[j] = dd[j];
             vvc[j] = vv[j];
         }
         if (z + 1 < b.ze) pf.fetch(p.ucur, p.nx, p.ny, p.nz, b.x0, b.y0, z + M + 2);
@@ -564,21 +559,301 @@ __global__ __launch_bounds__(kBlock3) void k_fwd3d_gen(StepArgs p) {
                 const long long k = ((long long)z * p.ny + gy) * p.nx + b.gx;
                 bool inband;
                 const float e = damp_e(p.sp, b.gx, gy, z, p.nx, p.ny, p.nz, inband);
-                float r;
-                if (!inband) {
-                    r = fmaf(vvc[j], Ls, 2.f * uc - upc[j]);
-                    if (k == p.src) r += p.q * p.wavelet[p.step];
-                } else {
-                    r = fmaf(-(1.f - e), upc[j], 2.f * uc);
-                    r = fmaf(vvc[j], Ls, r);
-                    if (k == p.src) r += p.q * p.wavelet[p.step];
-                    r = r / (1.f + e);
-                }
-                p.unext[k] = r;
+                const float d = delta_update(ddc[j], vvc[j], Ls, inband, e, k == p.src, p.q * p.wavelet[p.step]);
+                p.dnext[k] = d;
+                p.unext[k] = uc + d;
             }
         }
         base = base + 1 == NR ? 0 : base + 1;
     }
+}
+
+// ---------------------------------------------------------------------------
+// L1 ball (3D rhombus): in-plane difference sums reused along z
+// ---------------------------------------------------------------------------
+// Split each offset d = (p, dz) into its in-plane part p and dz.  The in-plane
+// parts form groups (a, b), a >= b >= 0, 1 <= a + b <= M: the points
+// (+-a, +-b), (+-b, +-a), n_ab of them (4 when b = 0 or a = b, else 8).  With
+//     D_ab(z') = sum_{p in (a, b)} u(x + p, z') - n_ab u(x, z')
+// (a small difference, formed once per plane from the LDS copy of plane z'),
+// the centre-free difference form of the stencil at plane z is
+//     sum_ab [ w(a,b,0) D_ab(z) + sum_{dz=1}^{M-a-b} w(a,b,dz) (D_ab(z+dz) + D_ab(z-dz)) ]
+//   + sum_{dz=1}^{M} wc(dz) (u(z+dz) + u(z-dz) - 2 u(z)),
+// wc(dz) = w(0,0,dz) + sum_{a+b <= M-dz} n_ab w(a,b,dz) (formed on the host in
+// FP64, rounded once): the same sum as the plain form, every term a small
+// difference.  Each D_ab and u value is kept in a register queue for the
+// 2 (M - a - b) + 1 (resp. 2M + 1) planes that use it, so a point costs 40
+// LDS reads at M = 4 instead of 129.  The z loop is unrolled by the queue
+// period P = 2M + 1, so that queue entry and LDS slot of plane z' are the
+// compile-time constants (z' - z0) mod P and the queues rotate by renaming
+// (no register moves).  D_ab(z') is formed at iteration z' - (M - a - b), from
+// plane z + M - a - b, so iteration z reads the LDS planes z .. z + M - 1;
+// plane z + M - 1 is stored at the top of iteration z (interior from the u
+// queue, halo fetched during iteration z - 1), into one of P >= M + 1 slots,
+// so one barrier per iteration suffices.  Each z chunk first runs 2 (M - 1)
+// warm-up iterations that only fill the queues.
+__host__ __device__ constexpr int ball_ngroups(int M) {
+    int n = 0;
+    for (int s = 1; s <= M; ++s) n += s / 2 + 1;
+    return n;
+}
+__host__ __device__ constexpr int ball_ga(int M, int g) {
+    for (int s = 1; s <= M; ++s)
+        for (int b = 0; b <= s / 2; ++b) {
+            if (g == 0) return s - b;
+            --g;
+        }
+    return -1;
+}
+__host__ __device__ constexpr int ball_gb(int M, int g) {
+    for (int s = 1; s <= M; ++s)
+        for (int b = 0; b <= s / 2; ++b) {
+            if (g == 0) return b;
+            --g;
+        }
+    return -1;
+}
+// orbit of the offset with absolute components (x, y, z), any order
+__host__ __device__ constexpr int ball_orbit(int M, int x, int y, int z) {
+    return orbit3_of(SH_RHOMBUS, M, x, y, z);
+}
+
+// sum of u over the in-plane group (A, B) around (row, col) of an LDS plane
+template <int M, int RY, int A, int B>
+__device__ __forceinline__ float ring_sum(const float* t, int row, int col) {
+    constexpr int LW = Geo3<M, RY>::LW;
+    const float* c = t + row * LW + col;
+    if constexpr (B == 0) return (c[-A] + c[A]) + (c[-A * LW] + c[A * LW]);
+    else if constexpr (A == B) return (c[-A * LW - A] + c[-A * LW + A]) + (c[A * LW - A] + c[A * LW + A]);
+    else
+        return ((c[-B * LW - A] + c[-B * LW + A]) + (c[B * LW - A] + c[B * LW + A])) +
+               ((c[-A * LW - B] + c[-A * LW + B]) + (c[A * LW - B] + c[A * LW + B]));
+}
+
+template <int K, int P, class Fn>
+__device__ __forceinline__ void run_phases(Fn& fn, int z, int ze) {
+    if constexpr (K < P) {
+        if (K == 0 || z + K < ze) {
+            fn(std::integral_constant<int, K>{}, z + K);
+            run_phases<K + 1, P>(fn, z, ze);
+        }
+    }
+}
+
+template <int G, int NG, int M, int RY, int PH, int P>
+__device__ __forceinline__ void ball_form_d(float (&D)[NG][P], const float* lds, const float (&q)[P], int row,
+                                            int col) {
+    if constexpr (G < NG) {
+        constexpr int a = ball_ga(M, G), b = ball_gb(M, G), s = a + b, mz = M - s;
+        constexpr float n = (b == 0 || a == b) ? 4.f : 8.f;
+        constexpr int slot = (PH + M - s) % P;   // plane z + M - s
+        const float r = ring_sum<M, RY, a, b>(lds + slot * Geo3<M, RY>::PLANE, row, col);
+        D[G][(PH + mz) % P] = fmaf(-n, q[slot], r);
+        ball_form_d<G + 1, NG, M, RY, PH, P>(D, lds, q, row, col);
+    }
+}
+
+// w(A,B,DZ) (D(z+DZ) + D(z-DZ)) for DZ = DZ..MZ of one group's queue
+template <int M, int PH, int P, int A, int B, int DZ, int MZ>
+__device__ __forceinline__ float ball_dz(const float (&Dg)[P], const Weights& W, float acc) {
+    if constexpr (DZ <= MZ) {
+        constexpr int o = ball_orbit(M, A, B, DZ);
+        acc = fmaf(W.w[o], Dg[(PH + DZ) % P] + Dg[(PH + P - DZ) % P], acc);
+        return ball_dz<M, PH, P, A, B, DZ + 1, MZ>(Dg, W, acc);
+    } else {
+        return acc;
+    }
+}
+
+template <int G, int NG, int M, int PH, int P>
+__device__ __forceinline__ float ball_combine(const float (&D)[NG][P], const Weights& W, float acc) {
+    if constexpr (G < NG) {
+        constexpr int a = ball_ga(M, G), b = ball_gb(M, G), mz = M - a - b;
+        constexpr int o = ball_orbit(M, a, b, 0);
+        acc = fmaf(W.w[o], D[G][PH], acc);
+        acc = ball_dz<M, PH, P, a, b, 1, mz>(D[G], W, acc);
+        return ball_combine<G + 1, NG, M, PH, P>(D, W, acc);
+    } else {
+        return acc;
+    }
+}
+
+// Byte offset b (< 2^32) from a block-uniform base pointer: the address form
+// of global loads with a scalar base and a 32-bit vector offset.
+__device__ __forceinline__ const float* at_b(const float* base, unsigned b) {
+    return (const float*)((const char*)base + b);
+}
+__device__ __forceinline__ float* at_b(float* base, unsigned b) { return (float*)((char*)base + b); }
+
+// Halo ring of a plane for the ball kernel (same cells and LDS positions as
+// Halo), with each thread's in-plane byte offsets and x/y validity taken
+// once: per plane only the block-uniform plane pointer changes.
+template <int M, int RY>
+struct BallHalo {
+    using H = Halo<M, RY>;
+    static constexpr int NT = H::NT, NS = H::NS, NSL = H::NSL, LW = H::LW;
+    unsigned toff[NT], soff[NSL];
+    bool tok[NT], sok[NSL];
+    int tlds[NT], slds[NSL];
+    float top[NT], side[NSL];
+    __device__ __forceinline__ void init(int nx, int ny, int x0, int y0) {
+        const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+        const int gx = x0 + tx;
+#pragma unroll
+        for (int k = 0; k < NT; ++k) {
+            const int q = ty + kWaves3 * k;
+            const int r = H::ring_row(q), gy = y0 - M + r;
+            tok[k] = (NT * kWaves3 == 2 * M || q < 2 * M) && gx < nx && (unsigned)gy < (unsigned)ny;
+            toff[k] = tok[k] ? 4u * (unsigned)(gy * nx + gx) : 0u;
+            tlds[k] = r * LW + M + tx;
+        }
+#pragma unroll
+        for (int k = 0; k < NSL; ++k) {
+            const int i = threadIdx.x + k * kBlock3;
+            int r, c;
+            H::side_pos(i, r, c);
+            const int gy = y0 - M + r, hx = x0 - M + c;
+            const bool in = NSL * kBlock3 == NS || i < NS;
+            sok[k] = in && (unsigned)gy < (unsigned)ny && (unsigned)hx < (unsigned)nx;
+            soff[k] = sok[k] ? 4u * (unsigned)(gy * nx + hx) : 0u;
+            slds[k] = in ? r * LW + c : -1;
+        }
+    }
+    __device__ __forceinline__ void fetch(const float* __restrict__ fz, bool zok) {
+#pragma unroll
+        for (int k = 0; k < NT; ++k) top[k] = (zok && tok[k]) ? *at_b(fz, toff[k]) : 0.f;
+#pragma unroll
+        for (int k = 0; k < NSL; ++k) side[k] = (zok && sok[k]) ? *at_b(fz, soff[k]) : 0.f;
+    }
+    __device__ __forceinline__ void store(float* tile) const {
+#pragma unroll
+        for (int k = 0; k < NT; ++k)
+            if (NT * kWaves3 == 2 * M || (int)(threadIdx.x >> 6) + kWaves3 * k < 2 * M) tile[tlds[k]] = top[k];
+#pragma unroll
+        for (int k = 0; k < NSL; ++k)
+            if (NSL * kBlock3 == NS || slds[k] >= 0) tile[slds[k]] = side[k];
+    }
+};
+
+// Window and model planes are addressed with 32-bit byte offsets.
+bool ball_fits(const StepArgs& a) {
+    return (long long)a.nx * a.ny < (1LL << 30) && a.ldv_z < (1LL << 30);
+}
+
+template <int M, int RY>
+__global__ __launch_bounds__(kBlock3) __attribute__((amdgpu_waves_per_eu(M <= 4 ? 4 : 2))) void k_fwd3d_ball(StepArgs p) {
+    using G = Geo3<M, RY>;
+    constexpr int P = 2 * M + 1;
+    constexpr int NG = ball_ngroups(M);
+    constexpr int WARM = 2 * (M - 1);
+    __shared__ float lds[P * G::PLANE];
+    if (p.trace_out) {
+        for (int r = blockIdx.x * kBlock3 + threadIdx.x; r < p.nrec; r += gridDim.x * kBlock3) {
+            const long long i = p.rec_lin[r];
+            p.trace_out[r] = i >= 0 ? p.ucur[i] : 0.f;
+        }
+    }
+    const Pos3 b = block_pos<RY>(p.ntiles, p.tiles_x, p.tiles_y, p.zchunk, p.nz);
+    const bool xok = b.gx < p.nx;
+    const long long plane = (long long)p.nx * p.ny;
+    const int z0 = b.zs - WARM;
+    // the thread's columns: byte offsets in a window plane and a model plane
+    float q[RY][P];        // u(z') at (z' - z0) mod P
+    float D[RY][NG][P];    // D_g(z') at (z' - z0) mod P
+    bool ok[RY], srccol[RY];
+    unsigned coff[RY], voff[RY];
+    float ry[RY];
+    int dyb[RY];
+    const int nb = p.sp.nb;
+    const int dxb = nb > 0 ? band_depth(b.gx, p.nx, nb) : 0;
+    const float rx = dxb * p.sp.inv_nb;
+    const int src_z = p.src >= 0 ? (int)(p.src / plane) : -1;
+    const long long src_xy = p.src >= 0 ? p.src - (long long)src_z * plane : -1;
+#pragma unroll
+    for (int j = 0; j < RY; ++j) {
+        const int gy = b.y0 + b.ty * RY + j;
+        ok[j] = xok && gy < p.ny;
+        coff[j] = ok[j] ? 4u * (unsigned)(gy * p.nx + b.gx) : 0u;
+        voff[j] = ok[j] ? 4u * (unsigned)(gy * (int)p.ldv_y + b.gx) : 0u;
+        srccol[j] = ok[j] && (long long)gy * p.nx + b.gx == src_xy;
+        dyb[j] = (nb > 0 && ok[j]) ? band_depth(gy, p.ny, nb) : 0;
+        ry[j] = dyb[j] * p.sp.inv_nb;
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            q[j][k] = 0.f;
+#pragma unroll
+            for (int g = 0; g < NG; ++g) D[j][g][k] = 0.f;
+        }
+        // u(z0 - M .. z0 + M - 1) at (k mod P)
+#pragma unroll
+        for (int k = -M; k < M; ++k) {
+            const int z = z0 + k;
+            q[j][(k + P) % P] = (ok[j] && (unsigned)z < (unsigned)p.nz) ? *at_b(p.ucur + z * plane, coff[j]) : 0.f;
+        }
+    }
+    // LDS planes z0 .. z0 + M - 2 (slots 0 .. M - 2)
+    for (int k = 0; k + 1 < M; ++k) load_plane<M, RY>(lds + k * G::PLANE, p.ucur, p.nx, p.ny, p.nz, b.x0, b.y0, z0 + k);
+    BallHalo<M, RY> halo;
+    halo.init(p.nx, p.ny, b.x0, b.y0);
+    float front[RY], dd[RY], vv[RY];
+    auto fetch = [&](int z) {   // operands of iteration z
+        const int zz = z + M;
+        const bool fok = (unsigned)zz < (unsigned)p.nz;
+        const bool in = z >= b.zs && z < b.ze;
+        const float* uz = p.ucur + zz * plane;
+        const float* dz = p.dcur + z * plane;
+        const float* vz = p.v + (long long)z * p.ldv_z;
+#pragma unroll
+        for (int j = 0; j < RY; ++j) {
+            front[j] = (fok && ok[j]) ? *at_b(uz, coff[j]) : 0.f;
+            dd[j] = (in && ok[j]) ? __builtin_nontemporal_load(at_b(dz, coff[j])) : 0.f;
+            vv[j] = (in && ok[j]) ? __builtin_nontemporal_load(at_b(vz, voff[j])) : 0.f;
+        }
+        const int zh = z + M - 1;
+        halo.fetch(p.ucur + zh * plane, (unsigned)zh < (unsigned)p.nz);
+    };
+    fetch(z0);
+    const float qs = p.src >= 0 ? p.q * p.wavelet[p.step] : 0.f;
+    auto body = [&](auto ph, int z) {
+        constexpr int PH = decltype(ph)::value;
+        constexpr int S_NEW = (PH + M - 1) % P;   // slot of plane z + M - 1
+        float ddc[RY], vvc[RY];
+#pragma unroll
+        for (int j = 0; j < RY; ++j) {
+            q[j][(PH + M) % P] = front[j];
+            ddc[j] = dd[j];
+            vvc[j] = vv[j];
+            lds[S_NEW * G::PLANE + (b.ty * RY + j + M) * G::LW + b.tx + M] = q[j][S_NEW];
+        }
+        halo.store(lds + S_NEW * G::PLANE);
+        if (z + 1 < b.ze) fetch(z + 1);
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < RY; ++j)
+            ball_form_d<0, NG, M, RY, PH, P>(D[j], lds, q[j], b.ty * RY + j + M, b.tx + M);
+        if (z >= b.zs) {
+            const int dzb = nb > 0 ? band_depth(z, p.nz, nb) : 0;
+            const float rz = dzb * p.sp.inv_nb;
+            float* dn = p.dnext + z * plane;
+            float* un = p.unext + z * plane;
+#pragma unroll
+            for (int j = 0; j < RY; ++j) {
+                const float uc = q[j][PH];
+                float L = ball_combine<0, NG, M, PH, P>(D[j], p.w, 0.f);
+#pragma unroll
+                for (int dz = 1; dz <= M; ++dz)
+                    L = fmaf(p.w.wc[dz], fmaf(-2.f, uc, q[j][(PH + dz) % P] + q[j][(PH + P - dz) % P]), L);
+                if (ok[j]) {
+                    const bool inband = (dxb | dyb[j] | dzb) != 0;
+                    const float e = inband ? p.sp.escale * fmaf(rx, rx, fmaf(ry[j], ry[j], rz * rz)) : 0.f;
+                    const float d = delta_update(ddc[j], vvc[j], L, inband, e, srccol[j] && z == src_z, qs);
+                    __builtin_nontemporal_store(d, at_b(dn, coff[j]));
+                    __builtin_nontemporal_store(uc + d, at_b(un, coff[j]));
+                }
+            }
+        }
+    };
+    for (int z = z0; z < b.ze; z += P) run_phases<0, P>(body, z, b.ze);
 }
 
 template <int SHAPE, int M, int RY>
@@ -700,6 +975,25 @@ static bool cross_rows_adj(const AdjArgs& a, int rows, hipStream_t s) {
     }
     return false;
 }
+template <int M, int RY>
+static void run_ball(const StepArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL((k_fwd3d_ball<M, RY>), dim3(a.ntiles), dim3(kBlock3), 0, s, a);
+}
+template <int M>
+static bool ball_rows(const StepArgs& a, int rows, hipStream_t s) {
+    if constexpr (M <= 4) {
+        switch (rows) {
+            case 1: run_ball<M, 1>(a, s); return true;
+            case 2: run_ball<M, 2>(a, s); return true;
+        }
+        return false;
+    } else {
+        if (rows != 1) return false;
+        run_ball<M, 1>(a, s);
+        return true;
+    }
+}
+
 template <int SHAPE, int M>
 static bool gen_rows(const StepArgs& a, int rows, hipStream_t s) {
     if constexpr (M <= 4) {
@@ -727,6 +1021,17 @@ bool launch_fwd3d(const StepArgs& a, int shape, int M, int rows, hipStream_t s) 
             case 6: return cross_rows<6>(a, rows, s);
             case 7: return cross_rows<7>(a, rows, s);
             case 8: return cross_rows<8>(a, rows, s);
+        }
+        return false;
+    }
+    if (shape == SH_RHOMBUS && ball_fits(a)) {   // the L1 ball: in-plane sums reused along z
+        switch (M) {
+            case 1: return ball_rows<1>(a, rows, s);
+            case 2: return ball_rows<2>(a, rows, s);
+            case 3: return ball_rows<3>(a, rows, s);
+            case 4: return ball_rows<4>(a, rows, s);
+            case 5: return ball_rows<5>(a, rows, s);
+            case 6: return ball_rows<6>(a, rows, s);
         }
         return false;
     }

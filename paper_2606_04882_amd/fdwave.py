@@ -57,8 +57,8 @@ class FdShot(ctypes.Structure):
                 ("stencil_id", ctypes.c_int), ("src", ctypes.c_int * 3),
                 ("wavelet", ctypes.c_void_p), ("nrec", ctypes.c_int), ("rec", ctypes.c_void_p),
                 ("traces", ctypes.c_void_p), ("trace_adj", ctypes.c_void_p),
-                ("init_prev", ctypes.c_void_p), ("init_cur", ctypes.c_void_p),
-                ("final_prev", ctypes.c_void_p), ("final_cur", ctypes.c_void_p),
+                ("init_diff", ctypes.c_void_p), ("init_cur", ctypes.c_void_p),
+                ("final_diff", ctypes.c_void_p), ("final_cur", ctypes.c_void_p),
                 ("ckpt", ctypes.c_void_p)]
 
 
@@ -214,6 +214,7 @@ class Shot:
     extent: Optional[Tuple[int, ...]] = None  # (x, y, z); None: whole model
     traces: Optional[torch.Tensor] = None     # [nt, nrec] float32 output
     trace_adj: Optional[torch.Tensor] = None  # [nt, nrec] float32
+    # states (d, u) with d = u^n - u^{n-1}: initial (d^0, u^0), final (d^nt, u^nt)
     init: Optional[Tuple[torch.Tensor, torch.Tensor]] = None
     final: Optional[Tuple[torch.Tensor, torch.Tensor]] = None
     ckpt: Optional[torch.Tensor] = None       # checkpoints, ckpt_numel(...) float32
@@ -250,9 +251,9 @@ def _shot_c(s: Shot, grid: Grid) -> FdShot:
     c.traces = _ptr(s.traces)
     c.trace_adj = _ptr(s.trace_adj)
     if s.init is not None:
-        c.init_prev, c.init_cur = _ptr(s.init[0]), _ptr(s.init[1])
+        c.init_diff, c.init_cur = _ptr(s.init[0]), _ptr(s.init[1])
     if s.final is not None:
-        c.final_prev, c.final_cur = _ptr(s.final[0]), _ptr(s.final[1])
+        c.final_diff, c.final_cur = _ptr(s.final[0]), _ptr(s.final[1])
     c.ckpt = _ptr(s.ckpt)
     return c
 
@@ -266,7 +267,7 @@ def window_points(grid: Grid, shot: Shot) -> int:
 
 def ckpt_numel(grid: Grid, shot: Shot, ckpt_every: int) -> int:
     """Floats of a shot's checkpoint buffer for segment length ckpt_every:
-    ceil(nt / K) pairs (u^{jK-1}, u^{jK}) of window fields."""
+    ceil(nt / K) pairs (d^{jK}, u^{jK}) of window fields."""
     K = int(ckpt_every)
     if K < 1:
         raise ValueError("ckpt_every must be >= 1")
@@ -301,7 +302,7 @@ def _stream_handle(device) -> int:
 def fd_forward(grid: Grid, vel: torch.Tensor, shots: Sequence[Shot], ws: Optional[torch.Tensor] = None,
                ckpt_every: int = 0):
     """Forward modelling; traces are written into each shot's `traces`, and
-    with ckpt_every = K > 0 the checkpoints (u^{jK-1}, u^{jK}) into each
+    with ckpt_every = K > 0 the checkpoints (d^{jK}, u^{jK}) into each
     shot's `ckpt` (ckpt_numel floats) when it has one."""
     for s in shots:
         if s.ckpt is not None and ckpt_every > 0 and s.ckpt.numel() < ckpt_numel(grid, s, ckpt_every):

@@ -2,7 +2,7 @@
 
 forward(vel) runs fd_forward for every shot and returns the traces stacked
 as [nshots, nt, nrec]; with segment checkpointing it keeps the checkpoints
-(u^{jK-1}, u^{jK}) every K = `ckpt_every` steps that the forward pass writes
+(d^{jK}, u^{jK}) every K = `ckpt_every` steps that the forward pass writes
 (2 ceil(nt/K) window fields per shot).  backward(dJ/dtraces) runs
 fd_adjoint_gradient on them (exact discrete adjoint; no second forward
 pass), or, with ckpt == "revolve", the binomial plan with `nsnap` snapshots,

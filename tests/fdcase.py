@@ -49,6 +49,14 @@ def oracle_traces(ndim, shape, M, w, vel, h, dt, nt, nb, eta, src, wavelet, rec,
                      init=init)
 
 
+def oracle_init(d0, u0):
+    """The oracle's initial state (u^{-1}, u^0) in FP64 for a GPU initial
+    state (d^0, u^0) given in FP32: u^{-1} = u^0 - d^0, exact in FP64."""
+    u0 = np.asarray(u0, dtype=np.float32).astype(np.float64)
+    d0 = np.asarray(d0, dtype=np.float32).astype(np.float64)
+    return (u0 - d0, u0)
+
+
 def rel_l2(a, b):
     a = np.asarray(a, dtype=np.float64)
     b = np.asarray(b, dtype=np.float64)

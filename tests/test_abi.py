@@ -83,40 +83,20 @@ def test_weights_are_validated(F):
 
 
 def test_time_block_controls(F):
-    sid = F.fd_weights_set(2, "cross", 4, oracle_weights(2, "taylor", "cross", 4))
-    F.fd_set_tile(sid, 4)
-    F.fd_set_time_block(sid, 2)
-    assert F.fd_get_time_block(sid) == 2
-    F.fd_set_time_block(sid, 1)
-    assert F.fd_get_time_block(sid) == 1
-    with pytest.raises(F.FdError) as e:
-        F.fd_set_time_block(sid, 3)
-    assert e.value.code == F.FD_EINVAL
-    F.fd_set_time_block(sid, 2)
-    F.fd_set_tile(sid, 8)                      # no two-step kernel at 8 rows: falls back to 1
-    assert F.fd_get_tile(sid)[0] == 8 and F.fd_get_time_block(sid) == 1
-    with pytest.raises(F.FdError) as e:
-        F.fd_set_time_block(sid, 2)
-    assert e.value.code == F.FD_EUNSUPPORTED
-    sq = F.fd_weights_set(2, "square", 2, oracle_weights(2, "specls", "square", 2))
-    assert F.fd_get_time_block(sq) == 1
-    with pytest.raises(F.FdError) as e:
-        F.fd_set_time_block(sq, 2)
-    assert e.value.code == F.FD_EUNSUPPORTED
-    s3 = F.fd_weights_set(3, "cross", 2, oracle_weights(3, "taylor", "cross", 2))
-    F.fd_set_tile(s3, 1, 64)
-    F.fd_set_time_block(s3, 2)                 # 3D crosses with M <= 4 at one row per thread
-    assert F.fd_get_time_block(s3) == 2
-    F.fd_set_tile(s3, 2, 64)                   # two rows: falls back to one step
-    assert F.fd_get_time_block(s3) == 1
-    with pytest.raises(F.FdError) as e:
-        F.fd_set_time_block(s3, 2)
-    assert e.value.code == F.FD_EUNSUPPORTED
-    s8 = F.fd_weights_set(3, "cross", 8, oracle_weights(3, "taylor", "cross", 8))
-    F.fd_set_tile(s8, 1, 64)
-    with pytest.raises(F.FdError) as e:
-        F.fd_set_time_block(s8, 2)
-    assert e.value.code == F.FD_EUNSUPPORTED
+    """Every kernel advances one step per launch: 1 is accepted, 2 is a valid
+    request with no compiled kernel, anything else is invalid."""
+    for ndim, shape, M in ((2, "cross", 4), (2, "square", 2), (3, "cross", 2)):
+        scheme = "specls" if shape == "square" else "taylor"
+        sid = F.fd_weights_set(ndim, shape, M, oracle_weights(ndim, scheme, shape, M))
+        assert F.fd_get_time_block(sid) == 1
+        F.fd_set_time_block(sid, 1)
+        with pytest.raises(F.FdError) as e:
+            F.fd_set_time_block(sid, 2)
+        assert e.value.code == F.FD_EUNSUPPORTED
+        with pytest.raises(F.FdError) as e:
+            F.fd_set_time_block(sid, 3)
+        assert e.value.code == F.FD_EINVAL
+        assert F.fd_get_time_block(sid) == 1
     with pytest.raises(F.FdError):
         F.fd_set_time_block(10 ** 6, 1)
 

@@ -9,7 +9,7 @@ pytestmark = pytest.mark.gpu
 
 from oracle import stepper as S  # noqa: E402
 from paper_2606_04882_amd import configs, synth  # noqa: E402
-from tests.fdcase import (layered, oracle_traces, oracle_weights, q32, rel_l2,  # noqa: E402
+from tests.fdcase import (check_traces, layered, oracle_traces, oracle_weights, q32, rel_l2,  # noqa: E402
                           rounded_stencil, v32)
 
 DEV = "cuda:0"
@@ -138,43 +138,32 @@ def test_3d_adjoint_gradient(F, shape, M):
     assert rel_l2(grad.cpu().numpy(), gref) <= 1e-3
 
 
-@pytest.mark.parametrize("M,zchunk,nt", [(1, 16, 31), (2, 24, 40), (3, 8, 23), (4, 16, 41), (4, 64, 30)])
-def test_3d_two_steps_per_launch(F, M, zchunk, nt):
-    """Two steps per launch (k_fwd3d_cross_tb) on a window with ragged tiles in
-    x, y and z, a damping band on every face, a source near a block edge and
-    receivers: traces and final states bitwise equal to one step per launch
-    (odd and even nt), and the oracle's to 1e-5."""
-    nz, ny, nx, h, nb = 45, 21, 83, 10.0, 4
-    vel = layered((nz, ny, nx), seed=30 + M)
-    dt = 0.4 * 0.45 * h / float(vel.max())
-    wo = oracle_weights(3, "dispte", "cross", M, float(vel.max()) * dt / h)
-    sid = F.fd_weights_set(3, "cross", M, wo)
-    eta = synth.sponge_eta_max(float(vel.max()), nb, h)
-    wav = synth.ricker(nt, dt, 40.0)
-    src = (64, 8, 15)     # the first column and row of the second tile in x and y
-    rec = [[x, y, 3] for x in range(1, nx - 1, 7) for y in range(1, ny - 1, 5)] + [[63, 8, 15], [82, 20, 44]]
-    F.fd_set_tile(sid, 1, zchunk)
-    F.fd_set_time_block(sid, 1)
-    one = run3(F, vel, h, dt, nt, nb, eta, sid, src, wav, rec, final=True)
-    F.fd_set_time_block(sid, 2)
-    assert F.fd_get_time_block(sid) == 2
-    two = run3(F, vel, h, dt, nt, nb, eta, sid, src, wav, rec, final=True)
-    assert np.array_equal(one["traces"], two["traces"])
-    assert np.array_equal(one["cur"], two["cur"])
-    ref = oracle_traces(3, "cross", M, wo, vel, h, dt, nt, nb, eta, src, wav, rec)
-    assert rel_l2(two["traces"], ref["traces"]) <= 1e-5
+@pytest.mark.parametrize("M,rows,zchunk", [(4, 1, 8), (6, 1, 8), (3, 1, 24), (2, 2, 8), (5, 1, 40)])
+def test_3d_ball_z_chunks(F, M, rows, zchunk):
+    """The L1-ball (3D rhombus) kernel warms up 2 (M - 1) planes below each z
+    chunk, reaching into the chunk below (or off the grid): chunks shorter
+    than the warm-up, ragged last chunks and a source on a chunk boundary
+    against the oracle, 1e-5 (traces and final state)."""
+    nz, ny, nx, h, nt, nb = 45, 19, 70, 10.0, 50, 5
+    vel = layered((nz, ny, nx), seed=40 + M)
+    vmax = float(vel.max())
+    dt = 0.35 * 0.5 * h / vmax
+    wo = oracle_weights(3, "dispte", "rhombus", M, vmax * dt / h)
+    sid = F.fd_weights_set(3, "rhombus", M, wo)
+    F.fd_set_tile(sid, rows, zchunk)
+    eta = synth.sponge_eta_max(vmax, nb, h)
+    wav = synth.ricker(nt, dt, 30.0)
+    src = (33, 9, zchunk)              # first plane of the second chunk
+    rec = [[x, y, z] for x in range(1, nx - 1, 6) for y in (2, 10) for z in (zchunk - 1, zchunk, 30)]
+    gpu = run3(F, vel, h, dt, nt, nb, eta, sid, src, wav, rec, final=True)
+    ref = oracle_traces(3, "rhombus", M, wo, vel, h, dt, nt, nb, eta, src, wav, rec)
+    check_traces(gpu["traces"], ref["traces"])
+    assert rel_l2(gpu["cur"], ref["cur"]) <= 1e-5
 
 
-def test_3d_two_step_controls(F):
-    sid = F.fd_weights_set(3, "cross", 8, oracle_weights(3, "taylor", "cross", 8))
-    F.fd_set_tile(sid, 1, 64)
-    with pytest.raises(F.FdError):
-        F.fd_set_time_block(sid, 2)          # M = 8 has no two-step kernel
-    sid4 = F.fd_weights_set(3, "cross", 4, oracle_weights(3, "taylor", "cross", 4))
-    F.fd_set_tile(sid4, 2, 64)
-    with pytest.raises(F.FdError):
-        F.fd_set_time_block(sid4, 2)         # rows 2 has none either
-    F.fd_set_tile(sid4, 1, 64)
-    F.fd_set_time_block(sid4, 2)
-    F.fd_set_tile(sid4, 2, 64)               # a tile without it falls back to one step
-    assert F.fd_get_time_block(sid4) == 1
+def test_3d_time_block_is_one_step(F):
+    sid = F.fd_weights_set(3, "cross", 4, oracle_weights(3, "taylor", "cross", 4))
+    assert F.fd_get_time_block(sid) == 1
+    with pytest.raises(F.FdError) as e:
+        F.fd_set_time_block(sid, 2)
+    assert e.value.code == F.FD_EUNSUPPORTED

@@ -1,5 +1,5 @@
 """Forward-pass checkpoints across the boundary (marked gpu): fd_forward with
-ckpt_every = K writes (u^{jK-1}, u^{jK}) into each shot's ckpt buffer, and
+ckpt_every = K writes the state (d^{jK}, u^{jK}) into each shot's ckpt buffer, and
 fd_adjoint_gradient consumes them instead of running its own forward pass.
 
 Bars: the checkpoints equal the states of forward runs stopped at jK
@@ -57,8 +57,8 @@ def setup(F, shape_grid, specs, nt, seed):
 
 
 def check_pairs(F, grid, vel, shots, K):
-    """Pair j of every shot's buffer equals (u^{jK-1}, u^{jK}) of a run of jK
-    steps (j = 0: the zero initial state)."""
+    """Pair j of every shot's buffer equals the state (d^{jK}, u^{jK}) of a run
+    of jK steps (j = 0: the zero initial state)."""
     nseg = -(-grid.nt // K)
     wshape = tuple(grid.shape)
     npts = int(np.prod(wshape))
@@ -75,7 +75,7 @@ def check_pairs(F, grid, vel, shots, K):
             F.fd_forward(g, vel, [probe])
             torch.cuda.synchronize()
             pair = s.ckpt[2 * j * npts: 2 * (j + 1) * npts].view(2, *wshape)
-            assert torch.equal(pair[0], probe.final[0]), (j, "u^{jK-1}")
+            assert torch.equal(pair[0], probe.final[0]), (j, "d^{jK}")
             assert torch.equal(pair[1], probe.final[1]), (j, "u^{jK}")
 
 

@@ -43,7 +43,7 @@ def gpu_run(F, vel, h, dt, nt, nb, eta, sid, src, wavelet, rec, vmax=None, init=
     torch.cuda.synchronize()
     out = {"traces": sh.traces.cpu().numpy() if nrec else None}
     if final:
-        out["prev"], out["cur"] = sh.final[0].cpu().numpy(), sh.final[1].cpu().numpy()
+        out["diff"], out["cur"] = sh.final[0].cpu().numpy(), sh.final[1].cpu().numpy()
     return out
 
 
@@ -130,7 +130,7 @@ def test_resume_bitwise_and_graph_equals_direct(F):
     assert np.array_equal(full["traces"], direct["traces"])
     a = gpu_run(F, vel, h, dt, 170, nb, eta, sid, (60, 40), wav[:170], rec, final=True)
     b = gpu_run(F, vel, h, dt, 130, nb, eta, sid, (60, 40), wav[170:], rec, final=True,
-                init=(a["prev"], a["cur"]))
+                init=(a["diff"], a["cur"]))
     assert np.array_equal(np.concatenate([a["traces"], b["traces"]]), full["traces"])
     assert np.array_equal(b["cur"], full["cur"])
 

@@ -18,7 +18,7 @@ pytestmark = pytest.mark.gpu
 from oracle import checkpoint as CK  # noqa: E402
 from oracle import stepper as S  # noqa: E402
 from paper_2606_04882_amd import synth  # noqa: E402
-from tests.fdcase import layered, oracle_weights, q32, rel_l2, rounded_stencil, v32  # noqa: E402
+from tests.fdcase import oracle_init, layered, oracle_weights, q32, rel_l2, rounded_stencil, v32  # noqa: E402
 
 DEV = "cuda:0"
 
@@ -55,7 +55,7 @@ def case(F, ndim, shape, M, nt, seed=1, init=False):
     if init:
         grids = np.meshgrid(*[np.arange(n) - n / 2 for n in dims], indexing="ij")
         bump = np.exp(-sum(gq ** 2 for gq in grids) / 30.0).astype(np.float32)
-        ini = (0.9 * bump, bump)
+        ini = (0.1 * bump, bump)             # (d^0, u^0)
     return dict(vel=vel, h=h, dt=dt, nt=nt, nb=nb, eta=eta, vmax=vmax, sid=sid, wo=wo, wav=wav, rec=rec,
                 src=src, rho=rho, ini=ini, ndim=ndim, shape=shape, M=M)
 
@@ -83,7 +83,7 @@ def oracle_grad(c, param):
     vel, dt, h = c["vel"], c["dt"], c["h"]
     gc, _ = S.adjoint_gradient(st, v32(vel, dt, h), vel.astype(np.float64), dt, c["nt"], c["nb"], c["eta"],
                                c["src"], q32(c["wav"], dt, h, c["ndim"]), c["rec"], c["rho"].astype(np.float64),
-                               init=None if c["ini"] is None else tuple(a.astype(np.float64) for a in c["ini"]))
+                               init=None if c["ini"] is None else oracle_init(*c["ini"]))
     return CK.gradient_param(gc, vel, param)
 
 

@@ -11,7 +11,10 @@ weights from design.py, batched calls, tile choices), cut to their first
   * FWI, 601 x 301, the batched K = 100 gradient of 4 shots against the
     oracle's FP64 adjoint gradient summed over the shots (<= 1e-3), and the
     GPU gradient against central finite differences of the oracle's FP64
-    misfit on 10 random significant cells (<= 1e-3).
+    misfit on 10 random significant cells (<= 1e-3);
+  * the 512^3 workload's physics (spacing, time step, wavelet, band,
+    velocity recipe, receiver plane) on a 128^3 cube at 500 steps, each of
+    its three stencils, traces against the oracle.
 """
 import numpy as np
 import pytest
@@ -161,7 +164,13 @@ def test_fwi_batched_gradient_matches_oracle(fwi_case):
 def test_fwi_gradient_against_finite_differences(fwi_case):
     """Central differences of the FP64 oracle misfit J(c) = 1/2 sum_shots
     |d(c) - d_obs|^2 (the GPU's observed data held fixed) at 10 random
-    cells with |g| >= 0.1 max|g|, eps = 1e-3 c, against the GPU gradient."""
+    cells with |g| >= 0.1 of the largest |g| among the eligible cells,
+    eps = 1e-3 c, against the GPU gradient.
+    Cells within the stencil radius of a source are left out: there the
+    field is a discrete impulse, J is far from quadratic over +-eps, and
+    the O(eps^2) term of the central difference is itself 3e-3 of the
+    derivative (measured in FP64 at a source cell, where the oracle's own
+    adjoint gradient differs from the difference quotient by as much)."""
     c = fwi_case
     w = c["w"]
     st = rounded_stencil(2, "cross", 4, c["wo"])
@@ -169,7 +178,9 @@ def test_fwi_gradient_against_finite_differences(fwi_case):
     g = c["grad"]
     band = np.zeros(w.shape, bool)
     band[w.nb:-w.nb, w.nb:-w.nb] = True
-    cand = np.argwhere(band & (np.abs(g) >= 0.1 * np.abs(g).max()))
+    for sx, sz in c["sources"]:
+        band[max(sz - 4, 0):sz + 5, max(sx - 4, 0):sx + 5] = False
+    cand = np.argwhere(band & (np.abs(g) >= 0.1 * np.abs(g[band]).max()))
     rng = np.random.default_rng(2024)
     cells = cand[rng.choice(len(cand), size=10, replace=False)]
 
@@ -190,3 +201,33 @@ def test_fwi_gradient_against_finite_differences(fwi_case):
         fd = (misfit(mp) - misfit(mm)) / (2 * eps)
         print(f"[case] FD cell (z={iz}, x={ix}): GPU {g[iz, ix]:.6e}, FD {fd:.6e}", flush=True)
         assert abs(g[iz, ix] - fd) <= 1e-3 * abs(fd), (iz, ix, g[iz, ix], fd)
+
+
+# ---------------------------------------------------------------------------
+# the 512^3 workload's physics at 500 steps on a smaller cube
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("stencil", [("taylor", "cross", 4), ("taylor", "cross", 8), ("dispte", "rhombus", 4)],
+                         ids=lambda s: f"{s[0]}-{s[1]}-M{s[2]}")
+def test_volume_physics_500_steps(F, stencil):
+    """The 3D workload's grid spacing, time step, wavelet, damping band,
+    velocity recipe (layers plus a dipping interface) and receiver plane on
+    a 128^3 cube (the oracle's 500 steps on 512^3 would take hours): the
+    traces after 500 steps against the oracle, rel-L2 <= 1e-5 and the
+    per-receiver bound."""
+    from tests.fdcase import check_traces
+    scheme, shape, M = stencil
+    w = configs.volume_3d(n=128, nt=NT)
+    model = configs.volume_3d_model(w)
+    wo = design.weights(3, scheme, shape, M, w.courant)
+    sid = F.fd_weights_set(3, shape, M, wo)
+    grid = F.Grid(shape=w.shape, h=w.h, dt=w.dt, nt=w.nt, nb=w.nb, eta_max=w.eta_max, vmax=w.c_max)
+    shot = F.Shot(stencil_id=sid, src=w.src, wavelet=torch.tensor(w.wavelet().astype(np.float32), device=DEV),
+                  rec=torch.tensor(w.rec.astype(np.int32), device=DEV),
+                  traces=torch.zeros(w.nt, len(w.rec), device=DEV))
+    F.fd_forward(grid, torch.tensor(model, device=DEV), [shot])
+    torch.cuda.synchronize()
+    print(f"[case] 128^3 volume, {scheme} {shape} M={M}, nt={NT}", flush=True)
+    ref = oracle_traces(3, shape, M, oracle_weights(3, scheme, shape, M, w.courant), model, w.h, w.dt, w.nt,
+                        w.nb, w.eta_max, w.src, w.wavelet(), w.rec)
+    err, worst = check_traces(shot.traces.cpu().numpy(), ref["traces"])
+    print(f"  rel-L2 {err:.3g}, worst per-receiver {worst:.3g}")

@@ -215,6 +215,28 @@ int fd_forward(const fd_grid* g, const float* vel, const fd_shot* shots, int nsh
                void* workspace, size_t ws_bytes, void* hip_stream);
 
 /*
+ * fd_forward for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): one
+ * shot, no checkpoints, its scratch (flags, v, the shot's fields and
+ * receiver indices) in a fixed array of FD_NOALLOC_SCRATCH_BYTES that the
+ * library keeps in device memory on each GPU it runs on until the process
+ * ends.  The caller still passes the inputs and outputs (vel, shot).  Kernel
+ * launches go directly onto hip_stream (no graphs, no library streams); the
+ * call makes no device or pinned-host allocation.  Results are those of
+ * fd_forward (same kernels).
+ *   shot      [host] one shot; ckpt must be NULL (FD_EINVAL otherwise)
+ * Errors: FD_ENOMEM when the call needs more scratch than the array holds
+ * (4 B per model point for v plus 12 B per window point for the fields, plus
+ * 8 B per receiver); otherwise those of fd_forward.  Every call on a GPU
+ * uses that GPU's one array: calls that overlap in time on one GPU (two
+ * streams, two threads) race and must be serialised by the caller.  The
+ * array keeps the last call's contents; a call initialises everything it
+ * reads.
+ */
+#define FD_NOALLOC_SCRATCH_BYTES (64ull << 20)
+int fd_forward_noalloc(const fd_grid* g, const float* vel, const fd_shot* shot, void* hip_stream);
+
+/*
  * Exact discrete adjoint of fd_forward and the gradient dJ/dc of a scalar
  * misfit J(traces), given trace_adj = dJ/dtraces for each shot.  The adjoint
  * field psi runs backwards in time with the forward operator (W is symmetric),

@@ -1453,6 +1453,44 @@ int run_direct(CallCtx& c, int mode, hipStream_t user) {
     return FD_OK;
 }
 
+// ---------------------------------------------------------------------------
+// fixed device scratch for fd_forward_noalloc: one array per GPU, resident
+// until the process ends.  Host code never passes `scratch` itself to a
+// kernel (on the host it only names the symbol); kernels get the device
+// address that hipGetSymbolAddress returns for the current device, taken
+// once per device at that device's first call.
+// ---------------------------------------------------------------------------
+__device__ __align__(256) unsigned char scratch[FD_NOALLOC_SCRATCH_BYTES];
+std::mutex g_scratch_mu;
+std::map<int, void*> g_scratch_ptr;
+
+int scratch_address(void** out) {
+    int dev = 0;
+    HIP_OK(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch_ptr.find(dev);
+    if (it == g_scratch_ptr.end()) {
+        void* ptr = nullptr;
+        HIP_OK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr) return fail(FD_EDEVICE, "hipGetSymbolAddress returned no address for the scratch array");
+        it = g_scratch_ptr.emplace(dev, ptr).first;
+    }
+    *out = it->second;
+    return FD_OK;
+}
+
+// Direct launches on the caller's stream with no library-owned streams,
+// events, graphs or pinned buffers (a single shot needs no branches).
+int run_direct_noalloc(CallCtx& c, hipStream_t user) {
+    Recorder R;
+    R.stream = user;
+    R.br = nullptr;
+    const int rc = enqueue_call(c, MODE_FORWARD, R);
+    if (rc) return rc;
+    HIP_OK(hipGetLastError());
+    return FD_OK;
+}
+
 int run_call(CallCtx& c, int mode, hipStream_t user) {
     if (c.g->flags & FD_NO_GRAPH) return run_direct(c, mode, user);
     int dev = 0;
@@ -1900,6 +1938,26 @@ int fd_forward(const fd_grid* g, const float* vel, const fd_shot* shots, int nsh
     if (rc) return rc;
     hipStream_t st = (hipStream_t)hip_stream;
     rc = run_call(c, 0, st);
+    if (rc) return rc;
+    return finish_checks(c, st);
+}
+
+int fd_forward_noalloc(const fd_grid* g, const float* vel, const fd_shot* shot, void* hip_stream) {
+    g_err.clear();
+    if (!shot) return fail(FD_EINVAL, "shot is NULL");
+    if (check_grid(g)) return FD_EINVAL;
+    const size_t need = make_layout(g, shot, 1, MODE_FORWARD, 0).total;
+    if (need > FD_NOALLOC_SCRATCH_BYTES)
+        return fail(FD_ENOMEM, "fd_forward_noalloc: this call needs %zu bytes of scratch, the fixed array holds %zu "
+                    "(use fd_forward with a workspace)", need, (size_t)FD_NOALLOC_SCRATCH_BYTES);
+    void* ws = nullptr;
+    int rc = scratch_address(&ws);
+    if (rc) return rc;
+    CallCtx c;
+    rc = prepare(c, g, vel, shot, 1, MODE_FORWARD, 0, ws, FD_NOALLOC_SCRATCH_BYTES);
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)hip_stream;
+    rc = run_direct_noalloc(c, st);
     if (rc) return rc;
     return finish_checks(c, st);
 }

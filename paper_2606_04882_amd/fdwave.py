@@ -90,6 +90,7 @@ def _load() -> ctypes.CDLL:
     lib.fd_workspace_bytes.argtypes = [P(FdGrid), P(FdShot), ctypes.c_int, ctypes.c_int, ctypes.c_int]
     lib.fd_forward.argtypes = [P(FdGrid), ctypes.c_void_p, P(FdShot), ctypes.c_int, ctypes.c_int,
                                ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
+    lib.fd_forward_noalloc.argtypes = [P(FdGrid), ctypes.c_void_p, P(FdShot), ctypes.c_void_p]
     lib.fd_adjoint_gradient.argtypes = [P(FdGrid), ctypes.c_void_p, P(FdShot), ctypes.c_int, ctypes.c_int,
                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
     lib.fd_adjoint_gradient_ex.argtypes = [P(FdGrid), ctypes.c_void_p, P(FdShot), ctypes.c_int, P(FdAdjointOpts),
@@ -318,6 +319,21 @@ def fd_forward(grid: Grid, vel: torch.Tensor, shots: Sequence[Shot], ws: Optiona
         ws = workspace(nbytes, vel.device)
     _check(_lib.fd_forward(ctypes.byref(g), _ptr(vel), arr, len(shots), int(ckpt_every), _ptr(ws), ws.numel(),
                            ctypes.c_void_p(_stream_handle(vel.device))))
+
+
+FD_NOALLOC_SCRATCH_BYTES = 64 << 20
+
+
+def fd_forward_noalloc(grid: Grid, vel: torch.Tensor, shot: Shot):
+    """One-shot forward modelling with the library's fixed device scratch
+    (FD_NOALLOC_SCRATCH_BYTES per GPU) instead of a workspace: no device
+    allocation by the call.  Calls overlapping on one GPU race."""
+    if vel.dtype != torch.float32 or tuple(vel.shape) != tuple(grid.shape):
+        raise ValueError(f"vel must be float32 of shape {grid.shape}")
+    g = grid.c()
+    c = _shot_c(shot, grid)
+    _check(_lib.fd_forward_noalloc(ctypes.byref(g), _ptr(vel), ctypes.byref(c),
+                                   ctypes.c_void_p(_stream_handle(vel.device))))
 
 
 def _adjoint_opts(ckpt: str, ckpt_every: int, nsnap: int, param: str) -> "FdAdjointOpts":

@@ -142,7 +142,7 @@ __device__ __forceinline__ float delta_update(float dc, float vv, float L, bool 
     } else {
         r = fmaf(vv, L, (1.f - e) * dc);
         if (at_src) r += qs;
-        r = r / (1.f + e);
+        r *= __builtin_amdgcn_rcpf(1.f + e);   // hardware reciprocal (1 ulp), not a full division
     }
     return r;
 }

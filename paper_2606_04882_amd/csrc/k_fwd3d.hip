@@ -685,15 +685,39 @@ __device__ __forceinline__ const float* at_b(const float* base, unsigned b) {
 }
 __device__ __forceinline__ float* at_b(float* base, unsigned b) { return (float*)((char*)base + b); }
 
+// Raw buffer access to one plane of a field: a resource over bytes
+// [0, nbytes) of the plane.  The hardware range check turns an access at or
+// beyond nbytes into a load of 0 or a dropped store, so a lane off the grid
+// (offset kOffGrid) or a plane off the grid (nbytes = 0) costs no branch and
+// no memory traffic.  Plane sizes stay below 2^31 bytes (ball_fits).
+constexpr unsigned kOffGrid = 0x80000000u;
+constexpr int kRsrcWord3 = 0x00020000;   // descriptor word 3: 32-bit data format
+constexpr int kNonTemporal = 2;          // cache-policy bits of a streaming access
+using Rsrc = __amdgpu_buffer_rsrc_t;
+__device__ __forceinline__ Rsrc plane_rsrc(const float* base, unsigned nbytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(base), (short)0, (int)nbytes, kRsrcWord3);
+}
+// the same from a byte address held as an integer (running plane addresses
+// may step outside the field; with nbytes = 0 they are never dereferenced)
+__device__ __forceinline__ Rsrc plane_rsrc_at(unsigned long long addr, unsigned nbytes) {
+    return __builtin_amdgcn_make_buffer_rsrc((void*)addr, (short)0, (int)nbytes, kRsrcWord3);
+}
+template <int AUX = 0>
+__device__ __forceinline__ float bload(Rsrc r, unsigned off) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, AUX));
+}
+__device__ __forceinline__ void bstore_nt(float x, Rsrc r, unsigned off) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, x), r, (int)off, 0, kNonTemporal);
+}
+
 // Halo ring of a plane for the ball kernel (same cells and LDS positions as
-// Halo), with each thread's in-plane byte offsets and x/y validity taken
-// once: per plane only the block-uniform plane pointer changes.
+// Halo), with each thread's in-plane byte offsets (kOffGrid off the grid)
+// taken once: per plane only the block-uniform buffer resource changes.
 template <int M, int RY>
 struct BallHalo {
     using H = Halo<M, RY>;
     static constexpr int NT = H::NT, NS = H::NS, NSL = H::NSL, LW = H::LW;
     unsigned toff[NT], soff[NSL];
-    bool tok[NT], sok[NSL];
     int tlds[NT], slds[NSL];
     float top[NT], side[NSL];
     __device__ __forceinline__ void init(int nx, int ny, int x0, int y0) {
@@ -703,8 +727,8 @@ struct BallHalo {
         for (int k = 0; k < NT; ++k) {
             const int q = ty + kWaves3 * k;
             const int r = H::ring_row(q), gy = y0 - M + r;
-            tok[k] = (NT * kWaves3 == 2 * M || q < 2 * M) && gx < nx && (unsigned)gy < (unsigned)ny;
-            toff[k] = tok[k] ? 4u * (unsigned)(gy * nx + gx) : 0u;
+            const bool ok = (NT * kWaves3 == 2 * M || q < 2 * M) && gx < nx && (unsigned)gy < (unsigned)ny;
+            toff[k] = ok ? 4u * (unsigned)(gy * nx + gx) : kOffGrid;
             tlds[k] = r * LW + M + tx;
         }
 #pragma unroll
@@ -714,16 +738,16 @@ struct BallHalo {
             H::side_pos(i, r, c);
             const int gy = y0 - M + r, hx = x0 - M + c;
             const bool in = NSL * kBlock3 == NS || i < NS;
-            sok[k] = in && (unsigned)gy < (unsigned)ny && (unsigned)hx < (unsigned)nx;
-            soff[k] = sok[k] ? 4u * (unsigned)(gy * nx + hx) : 0u;
+            const bool ok = in && (unsigned)gy < (unsigned)ny && (unsigned)hx < (unsigned)nx;
+            soff[k] = ok ? 4u * (unsigned)(gy * nx + hx) : kOffGrid;
             slds[k] = in ? r * LW + c : -1;
         }
     }
-    __device__ __forceinline__ void fetch(const float* __restrict__ fz, bool zok) {
+    __device__ __forceinline__ void fetch(Rsrc plane) {
 #pragma unroll
-        for (int k = 0; k < NT; ++k) top[k] = (zok && tok[k]) ? *at_b(fz, toff[k]) : 0.f;
+        for (int k = 0; k < NT; ++k) top[k] = bload(plane, toff[k]);
 #pragma unroll
-        for (int k = 0; k < NSL; ++k) side[k] = (zok && sok[k]) ? *at_b(fz, soff[k]) : 0.f;
+        for (int k = 0; k < NSL; ++k) side[k] = bload(plane, soff[k]);
     }
     __device__ __forceinline__ void store(float* tile) const {
 #pragma unroll
@@ -735,9 +759,9 @@ struct BallHalo {
     }
 };
 
-// Window and model planes are addressed with 32-bit byte offsets.
+// Window and model planes are addressed with 32-bit byte offsets below 2^31.
 bool ball_fits(const StepArgs& a) {
-    return (long long)a.nx * a.ny < (1LL << 30) && a.ldv_z < (1LL << 30);
+    return (long long)a.nx * a.ny < (1LL << 29) && a.ldv_z < (1LL << 29);
 }
 
 template <int M, int RY>
@@ -756,11 +780,12 @@ __global__ __launch_bounds__(kBlock3) __attribute__((amdgpu_waves_per_eu(M <= 4 
     const Pos3 b = block_pos<RY>(p.ntiles, p.tiles_x, p.tiles_y, p.zchunk, p.nz);
     const bool xok = b.gx < p.nx;
     const long long plane = (long long)p.nx * p.ny;
+    const unsigned pbytes = 4u * (unsigned)plane, vbytes = 4u * (unsigned)p.ldv_z;
     const int z0 = b.zs - WARM;
     // the thread's columns: byte offsets in a window plane and a model plane
     float q[RY][P];        // u(z') at (z' - z0) mod P
     float D[RY][NG][P];    // D_g(z') at (z' - z0) mod P
-    bool ok[RY], srccol[RY];
+    bool srccol[RY];
     unsigned coff[RY], voff[RY];
     float ry[RY];
     int dyb[RY];
@@ -772,11 +797,11 @@ __global__ __launch_bounds__(kBlock3) __attribute__((amdgpu_waves_per_eu(M <= 4 
 #pragma unroll
     for (int j = 0; j < RY; ++j) {
         const int gy = b.y0 + b.ty * RY + j;
-        ok[j] = xok && gy < p.ny;
-        coff[j] = ok[j] ? 4u * (unsigned)(gy * p.nx + b.gx) : 0u;
-        voff[j] = ok[j] ? 4u * (unsigned)(gy * (int)p.ldv_y + b.gx) : 0u;
-        srccol[j] = ok[j] && (long long)gy * p.nx + b.gx == src_xy;
-        dyb[j] = (nb > 0 && ok[j]) ? band_depth(gy, p.ny, nb) : 0;
+        const bool ok = xok && gy < p.ny;
+        coff[j] = ok ? 4u * (unsigned)(gy * p.nx + b.gx) : kOffGrid;
+        voff[j] = ok ? 4u * (unsigned)(gy * (int)p.ldv_y + b.gx) : kOffGrid;
+        srccol[j] = ok && (long long)gy * p.nx + b.gx == src_xy;
+        dyb[j] = (nb > 0 && ok) ? band_depth(gy, p.ny, nb) : 0;
         ry[j] = dyb[j] * p.sp.inv_nb;
 #pragma unroll
         for (int k = 0; k < P; ++k) {
@@ -784,33 +809,48 @@ __global__ __launch_bounds__(kBlock3) __attribute__((amdgpu_waves_per_eu(M <= 4 
 #pragma unroll
             for (int g = 0; g < NG; ++g) D[j][g][k] = 0.f;
         }
-        // u(z0 - M .. z0 + M - 1) at (k mod P)
+    }
+    // plane z of a window field (every access of a plane off the grid reads 0)
+    auto wplane = [&](const float* f, int z) {
+        const bool in = (unsigned)z < (unsigned)p.nz;
+        return plane_rsrc(f + (in ? z : 0) * plane, in ? pbytes : 0u);
+    };
+    // u(z0 - M .. z0 + M - 1) at (k mod P)
 #pragma unroll
-        for (int k = -M; k < M; ++k) {
-            const int z = z0 + k;
-            q[j][(k + P) % P] = (ok[j] && (unsigned)z < (unsigned)p.nz) ? *at_b(p.ucur + z * plane, coff[j]) : 0.f;
-        }
+    for (int k = -M; k < M; ++k) {
+        const Rsrc r = wplane(p.ucur, z0 + k);
+#pragma unroll
+        for (int j = 0; j < RY; ++j) q[j][(k + P) % P] = bload(r, coff[j]);
     }
     // LDS planes z0 .. z0 + M - 2 (slots 0 .. M - 2)
     for (int k = 0; k + 1 < M; ++k) load_plane<M, RY>(lds + k * G::PLANE, p.ucur, p.nx, p.ny, p.nz, b.x0, b.y0, z0 + k);
     BallHalo<M, RY> halo;
     halo.init(p.nx, p.ny, b.x0, b.y0);
     float front[RY], dd[RY], vv[RY];
-    auto fetch = [&](int z) {   // operands of iteration z
-        const int zz = z + M;
-        const bool fok = (unsigned)zz < (unsigned)p.nz;
+    // byte addresses of the planes the next fetch and the next update touch:
+    // u(z + M), d(z), v(z) and d/u^{n+1}(z), advanced by one plane per call
+    const unsigned long long pstep = 4ull * (unsigned long long)plane, vstep = 4ull * (unsigned long long)p.ldv_z;
+    unsigned long long au = (unsigned long long)p.ucur + (unsigned long long)(long long)(z0 + M) * pstep;
+    unsigned long long ad = (unsigned long long)p.dcur + (unsigned long long)(long long)z0 * pstep;
+    unsigned long long av = (unsigned long long)p.v + (unsigned long long)(long long)z0 * vstep;
+    unsigned long long adn = (unsigned long long)p.dnext + (unsigned long long)(long long)z0 * pstep;
+    unsigned long long aun = (unsigned long long)p.unext + (unsigned long long)(long long)z0 * pstep;
+    auto fetch = [&](int z) {   // operands of iteration z (d and v only for the chunk's own planes)
         const bool in = z >= b.zs && z < b.ze;
-        const float* uz = p.ucur + zz * plane;
-        const float* dz = p.dcur + z * plane;
-        const float* vz = p.v + (long long)z * p.ldv_z;
+        const Rsrc ru = plane_rsrc_at(au, (unsigned)(z + M) < (unsigned)p.nz ? pbytes : 0u);
+        const Rsrc rh = plane_rsrc_at(au - pstep, (unsigned)(z + M - 1) < (unsigned)p.nz ? pbytes : 0u);
+        const Rsrc rd = plane_rsrc_at(ad, in ? pbytes : 0u);
+        const Rsrc rv = plane_rsrc_at(av, in ? vbytes : 0u);
+        au += pstep;
+        ad += pstep;
+        av += vstep;
 #pragma unroll
         for (int j = 0; j < RY; ++j) {
-            front[j] = (fok && ok[j]) ? *at_b(uz, coff[j]) : 0.f;
-            dd[j] = (in && ok[j]) ? __builtin_nontemporal_load(at_b(dz, coff[j])) : 0.f;
-            vv[j] = (in && ok[j]) ? __builtin_nontemporal_load(at_b(vz, voff[j])) : 0.f;
+            front[j] = bload(ru, coff[j]);
+            dd[j] = bload<kNonTemporal>(rd, coff[j]);
+            vv[j] = bload<kNonTemporal>(rv, voff[j]);
         }
-        const int zh = z + M - 1;
-        halo.fetch(p.ucur + zh * plane, (unsigned)zh < (unsigned)p.nz);
+        halo.fetch(rh);
     };
     fetch(z0);
     const float qs = p.src >= 0 ? p.q * p.wavelet[p.step] : 0.f;
@@ -831,11 +871,13 @@ __global__ __launch_bounds__(kBlock3) __attribute__((amdgpu_waves_per_eu(M <= 4 
 #pragma unroll
         for (int j = 0; j < RY; ++j)
             ball_form_d<0, NG, M, RY, PH, P>(D[j], lds, q[j], b.ty * RY + j + M, b.tx + M);
+        const Rsrc rdn = plane_rsrc_at(adn, pbytes);
+        const Rsrc run = plane_rsrc_at(aun, pbytes);
+        adn += pstep;
+        aun += pstep;
         if (z >= b.zs) {
             const int dzb = nb > 0 ? band_depth(z, p.nz, nb) : 0;
             const float rz = dzb * p.sp.inv_nb;
-            float* dn = p.dnext + z * plane;
-            float* un = p.unext + z * plane;
 #pragma unroll
             for (int j = 0; j < RY; ++j) {
                 const float uc = q[j][PH];
@@ -843,13 +885,11 @@ __global__ __launch_bounds__(kBlock3) __attribute__((amdgpu_waves_per_eu(M <= 4 
 #pragma unroll
                 for (int dz = 1; dz <= M; ++dz)
                     L = fmaf(p.w.wc[dz], fmaf(-2.f, uc, q[j][(PH + dz) % P] + q[j][(PH + P - dz) % P]), L);
-                if (ok[j]) {
-                    const bool inband = (dxb | dyb[j] | dzb) != 0;
-                    const float e = inband ? p.sp.escale * fmaf(rx, rx, fmaf(ry[j], ry[j], rz * rz)) : 0.f;
-                    const float d = delta_update(ddc[j], vvc[j], L, inband, e, srccol[j] && z == src_z, qs);
-                    __builtin_nontemporal_store(d, at_b(dn, coff[j]));
-                    __builtin_nontemporal_store(uc + d, at_b(un, coff[j]));
-                }
+                const bool inband = (dxb | dyb[j] | dzb) != 0;
+                const float e = inband ? p.sp.escale * fmaf(rx, rx, fmaf(ry[j], ry[j], rz * rz)) : 0.f;
+                const float d = delta_update(ddc[j], vvc[j], L, inband, e, srccol[j] && z == src_z, qs);
+                bstore_nt(d, rdn, coff[j]);         // lanes off the grid: dropped
+                bstore_nt(uc + d, run, coff[j]);
             }
         }
     };

@@ -340,7 +340,7 @@ int fd_revolve_plan(int nt, int nsnap, int* ops, long long max_ops, long long* n
  * Kernel tile configuration used for a stencil: rows per thread along the
  * marching axis (2D: z; 3D: y) and the z-chunk of the 3D kernels.
  * fd_set_tile overrides the built-in choice (as found by the autotuner);
- * rows must be one of 1, 2, 4, 8 and zchunk a multiple of 8 in [8, 512].
+ * rows must be one of 1, 2, 4, 8 and zchunk a multiple of 8 in [8, 4096].
  * The setting applies to single-shot kernels (and to shots run one after the
  * other with FD_NO_BATCH); batched 2D calls use fixed tiles, 8 rows for the
  * forward steps of dense (non-cross) stencils and 4 rows otherwise.  The

@@ -3,7 +3,7 @@
 For a stencil on a given grid, times a short forward run for every compiled
 configuration (2D: rows per thread 2, 4, 8, and for crosses also the
 z-marching kernel with chunks of 16-48 rows; 3D: rows 1, 2, 4 (crosses) or
-1, 2 times z-chunk 16, 32, 64, 128, 256) and installs the fastest with
+1, 2 times z-chunk 32 .. 1024) and installs the fastest with
 fd_set_tile.  Results are
 cached in a JSON file keyed by device, dimension, stencil and grid size, so a
 tuned configuration is reused by later runs; configurations tuned on MI355X
@@ -44,7 +44,7 @@ def candidates(ndim: int, shape: str, M: int) -> List[Tuple[int, int, int]]:
         rows = (1,) if M > 2 else (1, 2)
     else:
         rows = (1, 2) if M <= 4 else (1,)
-    return [(r, z, 1) for r in rows for z in (16, 32, 64, 128, 256)]
+    return [(r, z, 1) for r in rows for z in (32, 64, 128, 256, 512, 1024)]
 
 
 def device_tag() -> str:
@@ -58,7 +58,7 @@ def device_tag() -> str:
 
 def _key(ndim, shape, M, grid_shape, N: int = 0) -> str:
     sh = shape if N == 0 else f"{shape}{N}"
-    return f"v3|{device_tag()}|{ndim}|{sh}|{M}|{'x'.join(str(int(n)) for n in grid_shape)}"
+    return f"v4|{device_tag()}|{ndim}|{sh}|{M}|{'x'.join(str(int(n)) for n in grid_shape)}"
 
 
 def _install(stencil_id: int, ndim: int, rows: int, zc: int, ts: int):

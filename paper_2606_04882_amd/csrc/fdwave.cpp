@@ -229,7 +229,7 @@ std::vector<Stencil> g_stencils;
 // 64 x 16; 3D tiles of 64 x 8 (64 x 16 for crosses with M > 4).
 int default_rows(int ndim, int shape, int M) {
     if (ndim == 2) return 4;
-    if (shape == FD_CROSS) return M <= 4 ? 1 : 2;
+    if (shape == FD_CROSS) return 2;
     return 1;
 }
 
@@ -753,7 +753,10 @@ AdjArgs base_adj(const CallCtx& c, const ShotCtx& s) {
     a.nz = s.nz;
     StepArgs t;
     t.nx = s.nx; t.ny = s.ny; t.nz = s.nz;
-    fill_tiles(t, c.g->ndim, adj_rows(c, s), s.st.zchunk);
+    // the 3D adjoint runs taller tiles than the forward; chunks of at most 256
+    // planes keep its block count up (512^3, 4 rows: 256 blocks at 256 planes,
+    // 128 at 512, i.e. half the CUs idle)
+    fill_tiles(t, c.g->ndim, adj_rows(c, s), c.g->ndim == 3 ? std::min(s.st.zchunk, 256) : s.st.zchunk);
     a.tiles_x = t.tiles_x;
     a.tiles_y = t.tiles_y;
     a.ntiles = t.ntiles;
@@ -1858,7 +1861,7 @@ int fd_weights_set_n(int ndim, int shape, int M, int N, const double* w, int nw,
     }
     st.cfl = 2.0 / std::sqrt(mneg);
     st.rows = default_rows(ndim, ks, M);
-    st.zchunk = (ndim == 3 && ks == SH_CROSS) ? 256 : 64;
+    st.zchunk = ndim == 3 ? 512 : 64;
     st.tsteps = 1;
     std::lock_guard<std::mutex> lk(g_mu);
     for (size_t i = 0; i < g_stencils.size(); ++i) {
@@ -1890,7 +1893,7 @@ int fd_set_tile(int stencil_id, int rows, int zchunk) {
     std::lock_guard<std::mutex> lk(g_mu);
     if (stencil_id < 0 || stencil_id >= (int)g_stencils.size()) return fail(FD_EINVAL, "unknown stencil id");
     if (rows != 1 && rows != 2 && rows != 4 && rows != 8) return fail(FD_EINVAL, "rows must be 1, 2, 4 or 8");
-    if (zchunk < 8 || zchunk > 512 || zchunk % 8) return fail(FD_EINVAL, "zchunk must be a multiple of 8 in [8, 512]");
+    if (zchunk < 8 || zchunk > 4096 || zchunk % 8) return fail(FD_EINVAL, "zchunk must be a multiple of 8 in [8, 4096]");
     Stencil& s = g_stencils[stencil_id];
     const bool have = s.ndim == 2 ? have_fwd2d(s.shape, s.M, rows) : have_fwd3d(s.shape, s.M, rows);
     if (!have) return fail(FD_EUNSUPPORTED, "no kernel compiled for rows = %d", rows);

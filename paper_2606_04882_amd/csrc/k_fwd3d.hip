@@ -167,6 +167,101 @@ __device__ __forceinline__ Pos3 block_pos(int ntiles, int tiles_x, int tiles_y, 
     return q;
 }
 
+// Byte offset b (< 2^32) from a block-uniform base pointer: the address form
+// of global loads with a scalar base and a 32-bit vector offset.
+__device__ __forceinline__ const float* at_b(const float* base, unsigned b) {
+    return (const float*)((const char*)base + b);
+}
+__device__ __forceinline__ float* at_b(float* base, unsigned b) { return (float*)((char*)base + b); }
+
+// Raw buffer access to one plane of a field: a resource over bytes
+// [0, nbytes) of the plane.  The hardware range check turns an access at or
+// beyond nbytes into a load of 0 or a dropped store, so a lane off the grid
+// (offset kOffGrid) or a plane off the grid (nbytes = 0) costs no branch and
+// no memory traffic.  Plane sizes stay below 2^31 bytes (ball_fits).
+constexpr unsigned kOffGrid = 0x80000000u;
+constexpr int kRsrcWord3 = 0x00020000;   // descriptor word 3: 32-bit data format
+constexpr int kNonTemporal = 2;          // cache-policy bits of a streaming access
+using Rsrc = __amdgpu_buffer_rsrc_t;
+__device__ __forceinline__ Rsrc plane_rsrc(const float* base, unsigned nbytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(base), (short)0, (int)nbytes, kRsrcWord3);
+}
+// the same from a byte address held as an integer (running plane addresses
+// may step outside the field; with nbytes = 0 they are never dereferenced)
+__device__ __forceinline__ Rsrc plane_rsrc_at(unsigned long long addr, unsigned nbytes) {
+    return __builtin_amdgcn_make_buffer_rsrc((void*)addr, (short)0, (int)nbytes, kRsrcWord3);
+}
+template <int AUX = 0>
+__device__ __forceinline__ float bload(Rsrc r, unsigned off) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, AUX));
+}
+__device__ __forceinline__ void bstore_nt(float x, Rsrc r, unsigned off) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, x), r, (int)off, 0, kNonTemporal);
+}
+
+// Halo ring of a plane for the buffer-addressed kernels (same cells and LDS
+// positions as Halo), with each thread's in-plane byte offsets (kOffGrid off the grid)
+// taken once: per plane only the block-uniform buffer resource changes.
+template <int M, int RY>
+struct PlaneHalo {
+    using H = Halo<M, RY>;
+    static constexpr int NT = H::NT, NS = H::NS, NSL = H::NSL, LW = H::LW;
+    unsigned toff[NT], soff[NSL];
+    int tlds[NT], slds[NSL];
+    float top[NT], side[NSL];
+    __device__ __forceinline__ void init(int nx, int ny, int x0, int y0) {
+        const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+        const int gx = x0 + tx;
+#pragma unroll
+        for (int k = 0; k < NT; ++k) {
+            const int q = ty + kWaves3 * k;
+            const int r = H::ring_row(q), gy = y0 - M + r;
+            const bool ok = (NT * kWaves3 == 2 * M || q < 2 * M) && gx < nx && (unsigned)gy < (unsigned)ny;
+            toff[k] = ok ? 4u * (unsigned)(gy * nx + gx) : kOffGrid;
+            tlds[k] = r * LW + M + tx;
+        }
+#pragma unroll
+        for (int k = 0; k < NSL; ++k) {
+            const int i = threadIdx.x + k * kBlock3;
+            int r, c;
+            H::side_pos(i, r, c);
+            const int gy = y0 - M + r, hx = x0 - M + c;
+            const bool in = NSL * kBlock3 == NS || i < NS;
+            const bool ok = in && (unsigned)gy < (unsigned)ny && (unsigned)hx < (unsigned)nx;
+            soff[k] = ok ? 4u * (unsigned)(gy * nx + hx) : kOffGrid;
+            slds[k] = in ? r * LW + c : -1;
+        }
+    }
+    __device__ __forceinline__ void fetch(Rsrc plane) {
+#pragma unroll
+        for (int k = 0; k < NT; ++k) top[k] = bload(plane, toff[k]);
+#pragma unroll
+        for (int k = 0; k < NSL; ++k) side[k] = bload(plane, soff[k]);
+    }
+    __device__ __forceinline__ void store(float* tile) const {
+#pragma unroll
+        for (int k = 0; k < NT; ++k)
+            if (NT * kWaves3 == 2 * M || (int)(threadIdx.x >> 6) + kWaves3 * k < 2 * M) tile[tlds[k]] = top[k];
+#pragma unroll
+        for (int k = 0; k < NSL; ++k)
+            if (NSL * kBlock3 == NS || slds[k] >= 0) tile[slds[k]] = side[k];
+    }
+};
+
+// Calls fn(integral_constant<K>, z + K) for K = 0 .. P - 1 while z + K < ze
+// (K = 0 always): one period of a z loop unrolled so that register queue
+// slots are compile-time constants.
+template <int K, int P, class Fn>
+__device__ __forceinline__ void run_phases(Fn& fn, int z, int ze) {
+    if constexpr (K < P) {
+        if (K == 0 || z + K < ze) {
+            fn(std::integral_constant<int, K>{}, z + K);
+            run_phases<K + 1, P>(fn, z, ze);
+        }
+    }
+}
+
+
 // ---------------------------------------------------------------------------
 // cross: z neighbours from a register queue, x/y neighbours from LDS
 // ---------------------------------------------------------------------------
@@ -186,13 +281,147 @@ __device__ __forceinline__ float cross_sum(const float* tile, const float* q, in
     return acc;
 }
 
-// Operands of plane z+1 (queue front u(z+1+M), u^{n-1}, v and the halo of
-// u(z+1)) are fetched while plane z is computed; the xy plane alternates
-// between two LDS buffers, so one barrier per plane suffices (a buffer is
-// rewritten only after every thread has passed the barrier of the plane in
-// between).
+// Sum of the cross with the z queue slot of plane z' at (z' - z0) mod P
+// (PH = (z - z0) mod P); the same operations in the same order as cross_sum.
+template <int M, int RY, int PH, int P>
+__device__ __forceinline__ float cross_sum_q(const float* tile, const float (&q)[P], int row, int col,
+                                             const Weights& W) {
+    using G = Geo3<M, RY>;
+    const float u = q[PH];
+    float acc = 0.f;
+#pragma unroll
+    for (int m = 1; m <= M; ++m) {
+        const float s = (tile[row * G::LW + col - m] + tile[row * G::LW + col + m]) +
+                        (tile[(row - m) * G::LW + col] + tile[(row + m) * G::LW + col]) +
+                        (q[(PH + P - m) % P] + q[(PH + m) % P]);
+        acc = fmaf(W.w[m], fmaf(-6.f, u, s), acc);
+    }
+    return acc;
+}
+
+// Operands of plane z+1 (queue front u(z+1+M), d, v and the halo of u(z+1))
+// are fetched while plane z is computed; the xy plane alternates between two
+// LDS buffers, so one barrier per plane suffices (a buffer is rewritten only
+// after every thread has passed the barrier of the plane in between).  The
+// z loop is unrolled by the queue period P = 2M + 1 (queue slots rotate by
+// renaming); fields are read and written through range-checked buffer
+// descriptors of one plane each, whose base advances by a plane per
+// iteration, so lanes and planes off the grid cost no branch.
 template <int M, int RY>
-__global__ __launch_bounds__(kBlock3) void k_fwd3d_cross(StepArgs p) {
+__global__ __launch_bounds__(kBlock3) __attribute__((amdgpu_waves_per_eu(RY < 4 ? 4 : 2))) void k_fwd3d_cross(StepArgs p) {
+    using G = Geo3<M, RY>;
+    constexpr int P = 2 * M + 1;
+    __shared__ float tiles[2][G::PLANE];
+    if (p.trace_out) {
+        for (int r = blockIdx.x * kBlock3 + threadIdx.x; r < p.nrec; r += gridDim.x * kBlock3) {
+            const long long i = p.rec_lin[r];
+            p.trace_out[r] = i >= 0 ? p.ucur[i] : 0.f;
+        }
+    }
+    const Pos3 b = block_pos<RY>(p.ntiles, p.tiles_x, p.tiles_y, p.zchunk, p.nz);
+    const bool xok = b.gx < p.nx;
+    const long long plane = (long long)p.nx * p.ny;
+    const unsigned pbytes = 4u * (unsigned)plane, vbytes = 4u * (unsigned)p.ldv_z;
+    const int z0 = b.zs;
+    float q[RY][P];   // u(z') at (z' - z0) mod P
+    bool srccol[RY];
+    unsigned coff[RY], voff[RY];
+    float ry[RY];
+    int dyb[RY];
+    const int nb = p.sp.nb;
+    const int dxb = nb > 0 ? band_depth(b.gx, p.nx, nb) : 0;
+    const float rx = dxb * p.sp.inv_nb;
+    const int src_z = p.src >= 0 ? (int)(p.src / plane) : -1;
+    const long long src_xy = p.src >= 0 ? p.src - (long long)src_z * plane : -1;
+#pragma unroll
+    for (int j = 0; j < RY; ++j) {
+        const int gy = b.y0 + b.ty * RY + j;
+        const bool ok = xok && gy < p.ny;
+        coff[j] = ok ? 4u * (unsigned)(gy * p.nx + b.gx) : kOffGrid;
+        voff[j] = ok ? 4u * (unsigned)(gy * (int)p.ldv_y + b.gx) : kOffGrid;
+        srccol[j] = ok && (long long)gy * p.nx + b.gx == src_xy;
+        dyb[j] = (nb > 0 && ok) ? band_depth(gy, p.ny, nb) : 0;
+        ry[j] = dyb[j] * p.sp.inv_nb;
+    }
+    // u(z0 - M .. z0 + M - 1) at (k mod P)
+#pragma unroll
+    for (int k = -M; k < M; ++k) {
+        const int z = z0 + k;
+        const bool in = (unsigned)z < (unsigned)p.nz;
+        const Rsrc r = plane_rsrc(p.ucur + (in ? z : 0) * plane, in ? pbytes : 0u);
+#pragma unroll
+        for (int j = 0; j < RY; ++j) q[j][(k + P) % P] = bload(r, coff[j]);
+    }
+    PlaneHalo<M, RY> halo;
+    halo.init(p.nx, p.ny, b.x0, b.y0);
+    float front[RY], dd[RY], vv[RY];
+    // byte addresses of u(z + M), u(z) (halo), d(z), v(z) for the next fetch
+    // and of d/u^{n+1}(z) for the next update, advanced by one plane per call
+    const unsigned long long pstep = 4ull * (unsigned long long)plane, vstep = 4ull * (unsigned long long)p.ldv_z;
+    unsigned long long au = (unsigned long long)p.ucur + (unsigned long long)(long long)(z0 + M) * pstep;
+    unsigned long long ah = (unsigned long long)p.ucur + (unsigned long long)(long long)z0 * pstep;
+    unsigned long long ad = (unsigned long long)p.dcur + (unsigned long long)(long long)z0 * pstep;
+    unsigned long long av = (unsigned long long)p.v + (unsigned long long)(long long)z0 * vstep;
+    unsigned long long adn = (unsigned long long)p.dnext + (unsigned long long)(long long)z0 * pstep;
+    unsigned long long aun = (unsigned long long)p.unext + (unsigned long long)(long long)z0 * pstep;
+    auto fetch = [&](int z) {   // operands of iteration z (z < ze <= nz)
+        const Rsrc ru = plane_rsrc_at(au, z + M < p.nz ? pbytes : 0u);
+        const Rsrc rh = plane_rsrc_at(ah, pbytes);
+        const Rsrc rd = plane_rsrc_at(ad, pbytes);
+        const Rsrc rv = plane_rsrc_at(av, vbytes);
+        au += pstep;
+        ah += pstep;
+        ad += pstep;
+        av += vstep;
+#pragma unroll
+        for (int j = 0; j < RY; ++j) {
+            front[j] = bload(ru, coff[j]);
+            dd[j] = bload<kNonTemporal>(rd, coff[j]);
+            vv[j] = bload<kNonTemporal>(rv, voff[j]);
+        }
+        halo.fetch(rh);
+    };
+    fetch(z0);
+    const float qs = p.src >= 0 ? p.q * p.wavelet[p.step] : 0.f;
+    int buf = 0;
+    auto body = [&](auto ph, int z) {
+        constexpr int PH = decltype(ph)::value;
+        float* tile = tiles[buf];
+        float ddc[RY], vvc[RY];
+#pragma unroll
+        for (int j = 0; j < RY; ++j) {
+            q[j][(PH + M) % P] = front[j];
+            ddc[j] = dd[j];
+            vvc[j] = vv[j];
+            tile[(b.ty * RY + j + M) * G::LW + b.tx + M] = q[j][PH];
+        }
+        halo.store(tile);
+        if (z + 1 < b.ze) fetch(z + 1);
+        __syncthreads();
+        const int dzb = nb > 0 ? band_depth(z, p.nz, nb) : 0;
+        const float rz = dzb * p.sp.inv_nb;
+        const Rsrc rdn = plane_rsrc_at(adn, pbytes);
+        const Rsrc run = plane_rsrc_at(aun, pbytes);
+        adn += pstep;
+        aun += pstep;
+#pragma unroll
+        for (int j = 0; j < RY; ++j) {
+            const float L = cross_sum_q<M, RY, PH, P>(tile, q[j], b.ty * RY + j + M, b.tx + M, p.w);
+            const bool inband = (dxb | dyb[j] | dzb) != 0;
+            const float e = inband ? p.sp.escale * fmaf(rx, rx, fmaf(ry[j], ry[j], rz * rz)) : 0.f;
+            const float d = delta_update(ddc[j], vvc[j], L, inband, e, srccol[j] && z == src_z, qs);
+            bstore_nt(d, rdn, coff[j]);         // lanes off the grid: dropped
+            bstore_nt(q[j][PH] + d, run, coff[j]);
+        }
+        buf ^= 1;
+    };
+    for (int z = z0; z < b.ze; z += P) run_phases<0, P>(body, z, b.ze);
+}
+
+// The same step with 64-bit addressing, for windows whose planes exceed the
+// 2^31-byte range of a buffer descriptor.
+template <int M, int RY>
+__global__ __launch_bounds__(kBlock3) void k_fwd3d_cross_wide(StepArgs p) {
     using G = Geo3<M, RY>;
     constexpr int NQ = 2 * M + 1;
     __shared__ float tiles[2][G::PLANE];
@@ -630,16 +859,6 @@ __device__ __forceinline__ float ring_sum(const float* t, int row, int col) {
                ((c[-A * LW - B] + c[-A * LW + B]) + (c[A * LW - B] + c[A * LW + B]));
 }
 
-template <int K, int P, class Fn>
-__device__ __forceinline__ void run_phases(Fn& fn, int z, int ze) {
-    if constexpr (K < P) {
-        if (K == 0 || z + K < ze) {
-            fn(std::integral_constant<int, K>{}, z + K);
-            run_phases<K + 1, P>(fn, z, ze);
-        }
-    }
-}
-
 template <int G, int NG, int M, int RY, int PH, int P>
 __device__ __forceinline__ void ball_form_d(float (&D)[NG][P], const float* lds, const float (&q)[P], int row,
                                             int col) {
@@ -678,89 +897,8 @@ __device__ __forceinline__ float ball_combine(const float (&D)[NG][P], const Wei
     }
 }
 
-// Byte offset b (< 2^32) from a block-uniform base pointer: the address form
-// of global loads with a scalar base and a 32-bit vector offset.
-__device__ __forceinline__ const float* at_b(const float* base, unsigned b) {
-    return (const float*)((const char*)base + b);
-}
-__device__ __forceinline__ float* at_b(float* base, unsigned b) { return (float*)((char*)base + b); }
-
-// Raw buffer access to one plane of a field: a resource over bytes
-// [0, nbytes) of the plane.  The hardware range check turns an access at or
-// beyond nbytes into a load of 0 or a dropped store, so a lane off the grid
-// (offset kOffGrid) or a plane off the grid (nbytes = 0) costs no branch and
-// no memory traffic.  Plane sizes stay below 2^31 bytes (ball_fits).
-constexpr unsigned kOffGrid = 0x80000000u;
-constexpr int kRsrcWord3 = 0x00020000;   // descriptor word 3: 32-bit data format
-constexpr int kNonTemporal = 2;          // cache-policy bits of a streaming access
-using Rsrc = __amdgpu_buffer_rsrc_t;
-__device__ __forceinline__ Rsrc plane_rsrc(const float* base, unsigned nbytes) {
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(base), (short)0, (int)nbytes, kRsrcWord3);
-}
-// the same from a byte address held as an integer (running plane addresses
-// may step outside the field; with nbytes = 0 they are never dereferenced)
-__device__ __forceinline__ Rsrc plane_rsrc_at(unsigned long long addr, unsigned nbytes) {
-    return __builtin_amdgcn_make_buffer_rsrc((void*)addr, (short)0, (int)nbytes, kRsrcWord3);
-}
-template <int AUX = 0>
-__device__ __forceinline__ float bload(Rsrc r, unsigned off) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, AUX));
-}
-__device__ __forceinline__ void bstore_nt(float x, Rsrc r, unsigned off) {
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, x), r, (int)off, 0, kNonTemporal);
-}
-
-// Halo ring of a plane for the ball kernel (same cells and LDS positions as
-// Halo), with each thread's in-plane byte offsets (kOffGrid off the grid)
-// taken once: per plane only the block-uniform buffer resource changes.
-template <int M, int RY>
-struct BallHalo {
-    using H = Halo<M, RY>;
-    static constexpr int NT = H::NT, NS = H::NS, NSL = H::NSL, LW = H::LW;
-    unsigned toff[NT], soff[NSL];
-    int tlds[NT], slds[NSL];
-    float top[NT], side[NSL];
-    __device__ __forceinline__ void init(int nx, int ny, int x0, int y0) {
-        const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-        const int gx = x0 + tx;
-#pragma unroll
-        for (int k = 0; k < NT; ++k) {
-            const int q = ty + kWaves3 * k;
-            const int r = H::ring_row(q), gy = y0 - M + r;
-            const bool ok = (NT * kWaves3 == 2 * M || q < 2 * M) && gx < nx && (unsigned)gy < (unsigned)ny;
-            toff[k] = ok ? 4u * (unsigned)(gy * nx + gx) : kOffGrid;
-            tlds[k] = r * LW + M + tx;
-        }
-#pragma unroll
-        for (int k = 0; k < NSL; ++k) {
-            const int i = threadIdx.x + k * kBlock3;
-            int r, c;
-            H::side_pos(i, r, c);
-            const int gy = y0 - M + r, hx = x0 - M + c;
-            const bool in = NSL * kBlock3 == NS || i < NS;
-            const bool ok = in && (unsigned)gy < (unsigned)ny && (unsigned)hx < (unsigned)nx;
-            soff[k] = ok ? 4u * (unsigned)(gy * nx + hx) : kOffGrid;
-            slds[k] = in ? r * LW + c : -1;
-        }
-    }
-    __device__ __forceinline__ void fetch(Rsrc plane) {
-#pragma unroll
-        for (int k = 0; k < NT; ++k) top[k] = bload(plane, toff[k]);
-#pragma unroll
-        for (int k = 0; k < NSL; ++k) side[k] = bload(plane, soff[k]);
-    }
-    __device__ __forceinline__ void store(float* tile) const {
-#pragma unroll
-        for (int k = 0; k < NT; ++k)
-            if (NT * kWaves3 == 2 * M || (int)(threadIdx.x >> 6) + kWaves3 * k < 2 * M) tile[tlds[k]] = top[k];
-#pragma unroll
-        for (int k = 0; k < NSL; ++k)
-            if (NSL * kBlock3 == NS || slds[k] >= 0) tile[slds[k]] = side[k];
-    }
-};
-
 // Window and model planes are addressed with 32-bit byte offsets below 2^31.
-bool ball_fits(const StepArgs& a) {
+bool planes_fit(const StepArgs& a) {
     return (long long)a.nx * a.ny < (1LL << 29) && a.ldv_z < (1LL << 29);
 }
 
@@ -824,7 +962,7 @@ __global__ __launch_bounds__(kBlock3) __attribute__((amdgpu_waves_per_eu(M <= 4 
     }
     // LDS planes z0 .. z0 + M - 2 (slots 0 .. M - 2)
     for (int k = 0; k + 1 < M; ++k) load_plane<M, RY>(lds + k * G::PLANE, p.ucur, p.nx, p.ny, p.nz, b.x0, b.y0, z0 + k);
-    BallHalo<M, RY> halo;
+    PlaneHalo<M, RY> halo;
     halo.init(p.nx, p.ny, b.x0, b.y0);
     float front[RY], dd[RY], vv[RY];
     // byte addresses of the planes the next fetch and the next update touch:
@@ -982,7 +1120,10 @@ bool have_fwd3d(int shape, int M, int rows) {
 
 template <int M, int RY>
 static void run_cross(const StepArgs& a, hipStream_t s) {
-    hipLaunchKernelGGL((k_fwd3d_cross<M, RY>), dim3(a.ntiles), dim3(kBlock3), 0, s, a);
+    if (planes_fit(a))
+        hipLaunchKernelGGL((k_fwd3d_cross<M, RY>), dim3(a.ntiles), dim3(kBlock3), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_fwd3d_cross_wide<M, RY>), dim3(a.ntiles), dim3(kBlock3), 0, s, a);
 }
 template <int M, int RY>
 static void run_cross_adj(const AdjArgs& a, hipStream_t s) {
@@ -1064,7 +1205,7 @@ bool launch_fwd3d(const StepArgs& a, int shape, int M, int rows, hipStream_t s) 
         }
         return false;
     }
-    if (shape == SH_RHOMBUS && ball_fits(a)) {   // the L1 ball: in-plane sums reused along z
+    if (shape == SH_RHOMBUS && planes_fit(a)) {   // the L1 ball: in-plane sums reused along z
         switch (M) {
             case 1: return ball_rows<1>(a, rows, s);
             case 2: return ball_rows<2>(a, rows, s);

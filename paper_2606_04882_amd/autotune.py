@@ -29,9 +29,11 @@ CACHE = os.environ.get("FDWAVE_TUNE_CACHE",
 PACKAGED = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned_mi355x.json")
 
 
-def candidates(ndim: int, shape: str, M: int) -> List[Tuple[int, int, int]]:
+def candidates(ndim: int, shape: str, M: int, nz: int = 0) -> List[Tuple[int, int, int]]:
     """(rows, zchunk, time steps per launch) configurations to time (one
-    step per launch throughout)."""
+    step per launch throughout).  3D z-chunks: powers of two and nz split
+    into 2, 3, 4 and 6 chunks (multiples of 8), so that a chunk count that
+    fills every compute unit in whole rounds is among them."""
     if ndim == 2:
         c = [(r, 64, 1) for r in (2, 4, 8)]
         if shape == "cross":
@@ -44,7 +46,11 @@ def candidates(ndim: int, shape: str, M: int) -> List[Tuple[int, int, int]]:
         rows = (1,) if M > 2 else (1, 2)
     else:
         rows = (1, 2) if M <= 4 else (1,)
-    return [(r, z, 1) for r in rows for z in (32, 64, 128, 256, 512, 1024)]
+    zs = {32, 64, 128, 256, 512, 1024}
+    for k in (2, 3, 4, 6):
+        if nz >= 8 * k:
+            zs.add(-(-nz // (8 * k)) * 8)
+    return [(r, z, 1) for r in rows for z in sorted(zs)]
 
 
 def device_tag() -> str:
@@ -58,7 +64,7 @@ def device_tag() -> str:
 
 def _key(ndim, shape, M, grid_shape, N: int = 0) -> str:
     sh = shape if N == 0 else f"{shape}{N}"
-    return f"v4|{device_tag()}|{ndim}|{sh}|{M}|{'x'.join(str(int(n)) for n in grid_shape)}"
+    return f"v5|{device_tag()}|{ndim}|{sh}|{M}|{'x'.join(str(int(n)) for n in grid_shape)}"
 
 
 def _install(stencil_id: int, ndim: int, rows: int, zc: int, ts: int):
@@ -105,7 +111,7 @@ def tune(stencil_id: int, ndim: int, shape: str, M: int, grid: F.Grid, vel: torc
     wav[0] = 1.0
     shot = F.Shot(stencil_id=stencil_id, src=tuple(src), wavelet=wav)
     times = {}
-    for rows, zc, ts in candidates(ndim, shape, M):
+    for rows, zc, ts in candidates(ndim, shape, M, int(grid.shape[0]) if ndim == 3 else 0):
         try:
             _install(stencil_id, ndim, rows, zc, ts)
         except F.FdError:

@@ -6,10 +6,14 @@
 // `zchunk` planes:
 //
 //  * cross stencils keep the 2M+1 values of u along z for each of the thread's
-//    RY points in registers (a queue shifted once per plane) and stage only the
+//    RY points in registers (a queue rotated by renaming) and stage only the
 //    current xy plane, with an M-cell halo, in LDS for the x/y neighbours;
-//  * rhombus (L1 ball) and square (cube) stencils keep a ring of 2M+1 xy planes
-//    with halo in LDS.
+//  * the rhombus (L1 ball) kernel tiles 64 x 4W points with four points per
+//    thread and keeps only the current plane in LDS, scattering each plane's
+//    in-plane sums into partial sums of the outputs it reaches (see the
+//    section of that kernel);
+//  * square (cube) stencils, and rhombi on very large planes, keep a ring of
+//    2M+1 xy planes with halo in LDS.
 //
 // Every value of u^n is read from HBM once per block (plus the z warm-up of 2M
 // planes per chunk and the xy halo, which neighbouring blocks of the same XCD
@@ -798,102 +802,165 @@ __global__ __launch_bounds__(kBlock3) void k_fwd3d_gen(StepArgs p) {
 }
 
 // ---------------------------------------------------------------------------
-// L1 ball (3D rhombus): in-plane difference sums reused along z
+// L1 ball (3D rhombus): in-plane difference sums scattered along z
 // ---------------------------------------------------------------------------
 // Split each offset d = (p, dz) into its in-plane part p and dz.  The in-plane
 // parts form groups (a, b), a >= b >= 0, 1 <= a + b <= M: the points
 // (+-a, +-b), (+-b, +-a), n_ab of them (4 when b = 0 or a = b, else 8).  With
 //     D_ab(z') = sum_{p in (a, b)} u(x + p, z') - n_ab u(x, z')
-// (a small difference, formed once per plane from the LDS copy of plane z'),
-// the centre-free difference form of the stencil at plane z is
-//     sum_ab [ w(a,b,0) D_ab(z) + sum_{dz=1}^{M-a-b} w(a,b,dz) (D_ab(z+dz) + D_ab(z-dz)) ]
-//   + sum_{dz=1}^{M} wc(dz) (u(z+dz) + u(z-dz) - 2 u(z)),
-// wc(dz) = w(0,0,dz) + sum_{a+b <= M-dz} n_ab w(a,b,dz) (formed on the host in
+// (a small difference, formed from the LDS copy of plane z') the centre-free
+// difference form of the stencil at plane o is
+//     sum_ab sum_{|t| <= M-a-b} w(a,b,|t|) D_ab(o + t)
+//   + sum_{m=1}^{M} wc(m) [(u(o+m) - u(o)) + (u(o-m) - u(o))],
+// wc(m) = w(0,0,m) + sum_{a+b <= M-m} n_ab w(a,b,m) (formed on the host in
 // FP64, rounded once): the same sum as the plain form, every term a small
-// difference.  Each D_ab and u value is kept in a register queue for the
-// 2 (M - a - b) + 1 (resp. 2M + 1) planes that use it, so a point costs 40
-// LDS reads at M = 4 instead of 129.  The z loop is unrolled by the queue
-// period P = 2M + 1, so that queue entry and LDS slot of plane z' are the
-// compile-time constants (z' - z0) mod P and the queues rotate by renaming
-// (no register moves).  D_ab(z') is formed at iteration z' - (M - a - b), from
-// plane z + M - a - b, so iteration z reads the LDS planes z .. z + M - 1;
-// plane z + M - 1 is stored at the top of iteration z (interior from the u
-// queue, halo fetched during iteration z - 1), into one of P >= M + 1 slots,
-// so one barrier per iteration suffices.  Each z chunk first runs 2 (M - 1)
-// warm-up iterations that only fill the queues.
+// difference.  The block marches along z; when plane z' arrives (one LDS
+// buffer per plane, loaded straight from memory into LDS by buffer loads
+// with the LDS flag, double-buffered, one barrier per plane) every group's
+// D_ab(z') is formed once and added with its weights into the partial sums
+// of the outputs z' - (M-a-b) .. z' + (M-a-b), and the z differences
+// u(z') - u(z'-m), m = 1..M, go to outputs z' - m and z'; output z' - M is
+// then complete and updated.  A thread owns four consecutive points of a row
+// (16 threads per 64-point row), so a row window of its points' in-plane
+// neighbours is 1 + MP/2 aligned 16-byte LDS reads, and per point it keeps
+// 2M partial sums and M queued values of u.  The z loop is unrolled by the
+// period 2M, so partial sums, queue entries and the LDS buffer are
+// compile-time slots.  Each z chunk runs M planes before and after its own.
 __host__ __device__ constexpr int ball_ngroups(int M) {
     int n = 0;
     for (int s = 1; s <= M; ++s) n += s / 2 + 1;
     return n;
 }
-__host__ __device__ constexpr int ball_ga(int M, int g) {
-    for (int s = 1; s <= M; ++s)
-        for (int b = 0; b <= s / 2; ++b) {
-            if (g == 0) return s - b;
-            --g;
-        }
-    return -1;
-}
-__host__ __device__ constexpr int ball_gb(int M, int g) {
-    for (int s = 1; s <= M; ++s)
-        for (int b = 0; b <= s / 2; ++b) {
-            if (g == 0) return b;
-            --g;
-        }
-    return -1;
+// index of group (a, b), a >= b: groups ordered by a + b, then b
+__host__ __device__ constexpr int ball_gidx(int a, int b) {
+    int g = 0;
+    for (int s = 1; s < a + b; ++s) g += s / 2 + 1;
+    return g + b;
 }
 // orbit of the offset with absolute components (x, y, z), any order
 __host__ __device__ constexpr int ball_orbit(int M, int x, int y, int z) {
     return orbit3_of(SH_RHOMBUS, M, x, y, z);
 }
 
-// sum of u over the in-plane group (A, B) around (row, col) of an LDS plane
-template <int M, int RY, int A, int B>
-__device__ __forceinline__ float ring_sum(const float* t, int row, int col) {
-    constexpr int LW = Geo3<M, RY>::LW;
-    const float* c = t + row * LW + col;
-    if constexpr (B == 0) return (c[-A] + c[A]) + (c[-A * LW] + c[A * LW]);
-    else if constexpr (A == B) return (c[-A * LW - A] + c[-A * LW + A]) + (c[A * LW - A] + c[A * LW + A]);
-    else
-        return ((c[-B * LW - A] + c[-B * LW + A]) + (c[B * LW - A] + c[B * LW + A])) +
-               ((c[-A * LW - B] + c[-A * LW + B]) + (c[A * LW - B] + c[A * LW + B]));
-}
-
-template <int G, int NG, int M, int RY, int PH, int P>
-__device__ __forceinline__ void ball_form_d(float (&D)[NG][P], const float* lds, const float (&q)[P], int row,
-                                            int col) {
-    if constexpr (G < NG) {
-        constexpr int a = ball_ga(M, G), b = ball_gb(M, G), s = a + b, mz = M - s;
-        constexpr float n = (b == 0 || a == b) ? 4.f : 8.f;
-        constexpr int slot = (PH + M - s) % P;   // plane z + M - s
-        const float r = ring_sum<M, RY, a, b>(lds + slot * Geo3<M, RY>::PLANE, row, col);
-        D[G][(PH + mz) % P] = fmaf(-n, q[slot], r);
-        ball_form_d<G + 1, NG, M, RY, PH, P>(D, lds, q, row, col);
+template <int B, int E, class F>
+__device__ __forceinline__ void cfor(F&& f) {
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        cfor<B + 1, E>(f);
     }
 }
 
-// w(A,B,DZ) (D(z+DZ) + D(z-DZ)) for DZ = DZ..MZ of one group's queue
-template <int M, int PH, int P, int A, int B, int DZ, int MZ>
-__device__ __forceinline__ float ball_dz(const float (&Dg)[P], const Weights& W, float acc) {
-    if constexpr (DZ <= MZ) {
-        constexpr int o = ball_orbit(M, A, B, DZ);
-        acc = fmaf(W.w[o], Dg[(PH + DZ) % P] + Dg[(PH + P - DZ) % P], acc);
-        return ball_dz<M, PH, P, A, B, DZ + 1, MZ>(Dg, W, acc);
-    } else {
-        return acc;
-    }
+template <int M, int W>   // W waves per block
+struct BallGeo {
+    static constexpr int MP = (M + 3) / 4 * 4;   // x halo, whole 16-byte units
+    static constexpr int TX = 64, TY = 4 * W;    // tile: 16 threads x 4 points per row, 4W rows
+    static constexpr int LW = TX + 2 * MP, LH = TY + 2 * M;
+    static constexpr int PLANE = LW * LH;        // floats per LDS plane
+    static constexpr int NTH = 64 * W;
+};
+
+using LdsPtr = __attribute__((address_space(3))) void*;
+typedef unsigned U4 __attribute__((ext_vector_type(4)));
+typedef float F4 __attribute__((ext_vector_type(4)));
+// (16-byte operand loads go through plain global pointers: the 128-bit raw
+// buffer load builtin is narrowed to one dword by this compiler when its
+// elements are bit-cast to float one by one)
+__device__ __forceinline__ void bstore4_nt(U4 x, Rsrc r, unsigned off) {
+    __builtin_amdgcn_raw_buffer_store_b128(x, r, (int)off, 0, kNonTemporal);
+}
+// 4 * UNIT bytes per lane from global memory straight into LDS at buf + lane * UNIT floats
+// (the LDS address is taken from the low 32 bits of the generic address of
+// an LDS location: a generic-to-LDS pointer cast here makes this compiler
+// emit an invalid null-pointer test on the aperture register)
+template <int UNIT>
+__device__ __forceinline__ void bload_lds(Rsrc r, float* buf, unsigned off) {
+    const LdsPtr dst = (LdsPtr)(uintptr_t)(unsigned)(uintptr_t)buf;
+    if constexpr (UNIT == 4) __builtin_amdgcn_raw_ptr_buffer_load_lds(r, dst, 16, off, 0, 0, 0);
+    else __builtin_amdgcn_raw_ptr_buffer_load_lds(r, dst, 4, off, 0, 0, 0);
 }
 
-template <int G, int NG, int M, int PH, int P>
-__device__ __forceinline__ float ball_combine(const float (&D)[NG][P], const Weights& W, float acc) {
-    if constexpr (G < NG) {
-        constexpr int a = ball_ga(M, G), b = ball_gb(M, G), mz = M - a - b;
-        constexpr int o = ball_orbit(M, a, b, 0);
-        acc = fmaf(W.w[o], D[G][PH], acc);
-        acc = ball_dz<M, PH, P, a, b, 1, mz>(D[G], W, acc);
-        return ball_combine<G + 1, NG, M, PH, P>(D, W, acc);
-    } else {
-        return acc;
+// In-plane sums of row dy (|dy| = R) into the group sums S of the thread's
+// four points; `row` is the thread's first LDS column of that row.  The first
+// contribution to group (a, b) comes from row -b (rows are taken in the order
+// 0, -1, +1, -2, +2, ...) and is assigned.
+template <int M, int MP, int R, int DY, int NG>
+__device__ __forceinline__ void ball_row(const float* row, float (&S)[NG][4], float (&uc)[4]) {
+    constexpr int lo = MP - (M - R), hi = MP + 3 + (M - R);
+    constexpr int k0 = lo / 4, k1 = hi / 4;
+    float win[4 * (k1 + 1)];
+    cfor<k0, k1 + 1>([&](auto kc) {
+        constexpr int k = decltype(kc)::value;
+        const float4 v = reinterpret_cast<const float4*>(__builtin_assume_aligned(row, 16))[k];
+        win[4 * k] = v.x;
+        win[4 * k + 1] = v.y;
+        win[4 * k + 2] = v.z;
+        win[4 * k + 3] = v.w;
+    });
+    cfor<0, 4>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        if constexpr (R == 0) uc[i] = win[MP + i];
+        if constexpr (R > 0) S[ball_gidx(R, 0)][i] += win[MP + i];
+        cfor<1, M - R + 1>([&](auto kc) {
+            constexpr int k = decltype(kc)::value;
+            constexpr int a = k > R ? k : R, b = k > R ? R : k;
+            constexpr int g = ball_gidx(a, b);
+            const float pr = win[MP + i - k] + win[MP + i + k];
+            if constexpr (DY == -b) S[g][i] = pr;
+            else S[g][i] += pr;
+        });
+    });
+}
+
+// Group (A, B) is complete: D = S - n u, added into the partial sums of the
+// outputs z' + t, |t| <= M - A - B (slot (PH + t) mod Q).  Its t = M - 1
+// contribution (group (1, 0) only) is the first that output receives.
+template <int M, int Q, int PH, int A, int B, int NG>
+__device__ __forceinline__ void ball_scatter(float (&acc)[Q][4], const float (&S)[NG][4], const float (&uc)[4],
+                                             const Weights& W) {
+    constexpr int mz = M - A - B;
+    constexpr float n = (B == 0 || A == B) ? 4.f : 8.f;
+    constexpr int g = ball_gidx(A, B);
+    cfor<0, 4>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        const float D = fmaf(-n, uc[i], S[g][i]);
+        cfor<0, 2 * mz + 1>([&](auto tc) {
+            constexpr int t = decltype(tc)::value - mz;
+            constexpr int o = ball_orbit(M, A, B, t < 0 ? -t : t);
+            constexpr int slot = ((PH + t) % Q + Q) % Q;
+            if constexpr (A == 1 && B == 0 && t == mz) acc[slot][i] = W.w[o] * D;
+            else acc[slot][i] = fmaf(W.w[o], D, acc[slot][i]);
+            __asm__ volatile("" : "+v"(acc[slot][i]));   // added here, not sunk to the end
+        });
+    });
+}
+
+// Rows +-R, then the groups (R, b) they complete.
+template <int M, int MP, int LW, int Q, int PH, int R, int NG>
+__device__ __forceinline__ void ball_rows_from(const float* base, float (&S)[NG][4], float (&uc)[4],
+                                               float (&acc)[Q][4], const Weights& W) {
+    if constexpr (R <= M) {
+        // The empty asm statements take the group sums as operands, so each
+        // row is summed before the next row is read (otherwise the compiler
+        // gathers every row's LDS reads at the top, all windows live at once).
+        auto fence = [&]() {
+#pragma unroll
+            for (int g = 0; g < NG; ++g)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) __asm__ volatile("" : "+v"(S[g][i])::"memory");
+        };
+        if constexpr (R == 0) {
+            ball_row<M, MP, 0, 0, NG>(base, S, uc);
+            fence();
+        } else {
+            ball_row<M, MP, R, -R, NG>(base - R * LW, S, uc);
+            fence();
+            ball_row<M, MP, R, R, NG>(base + R * LW, S, uc);
+            fence();
+            cfor<0, (R < M - R ? R : M - R) + 1>([&](auto bc) {
+                ball_scatter<M, Q, PH, R, decltype(bc)::value, NG>(acc, S, uc, W);
+            });
+        }
+        ball_rows_from<M, MP, LW, Q, PH, R + 1, NG>(base, S, uc, acc, W);
     }
 }
 
@@ -902,136 +969,207 @@ bool planes_fit(const StepArgs& a) {
     return (long long)a.nx * a.ny < (1LL << 29) && a.ldv_z < (1LL << 29);
 }
 
-template <int M, int RY>
-__global__ __launch_bounds__(kBlock3) __attribute__((amdgpu_waves_per_eu(M <= 4 ? 4 : 2))) void k_fwd3d_ball(StepArgs p) {
-    using G = Geo3<M, RY>;
-    constexpr int P = 2 * M + 1;
+// VEC: the window and model rows are 16-byte aligned (nx, ldv_y, ldv_z
+// multiples of 4, 16-byte aligned fields): 16-byte loads and stores; else
+// 4-byte ones.
+template <int M, int W, int VEC>
+__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(M <= 2 ? 4 : 2))) void k_fwd3d_ball(StepArgs p) {
+    using BG = BallGeo<M, W>;
+    constexpr int MP = BG::MP, LW = BG::LW, LH = BG::LH, PLANE = BG::PLANE, NTH = BG::NTH;
+    constexpr int Q = 2 * M;
     constexpr int NG = ball_ngroups(M);
-    constexpr int WARM = 2 * (M - 1);
-    __shared__ float lds[P * G::PLANE];
+    constexpr int UNIT = VEC ? 4 : 1;                  // floats per transfer
+    constexpr int NF = PLANE / UNIT;                   // transfers per LDS plane
+    constexpr int NPASS = (NF + NTH - 1) / NTH;
+    __shared__ __attribute__((aligned(16))) float lds[2 * PLANE];
     if (p.trace_out) {
-        for (int r = blockIdx.x * kBlock3 + threadIdx.x; r < p.nrec; r += gridDim.x * kBlock3) {
+        for (int r = blockIdx.x * NTH + threadIdx.x; r < p.nrec; r += gridDim.x * NTH) {
             const long long i = p.rec_lin[r];
             p.trace_out[r] = i >= 0 ? p.ucur[i] : 0.f;
         }
     }
-    const Pos3 b = block_pos<RY>(p.ntiles, p.tiles_x, p.tiles_y, p.zchunk, p.nz);
-    const bool xok = b.gx < p.nx;
+    const int t = xcd_tile(blockIdx.x, p.ntiles);
+    const int bx = t % p.tiles_x, t2 = t / p.tiles_x;
+    const int by = t2 % p.tiles_y, bz = t2 / p.tiles_y;
+    const int x0 = bx * BG::TX, y0 = by * BG::TY;
+    const int zs = bz * p.zchunk, ze = min(zs + p.zchunk, p.nz);
+    const int tq = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    const int gx = x0 + 4 * tq, gy = y0 + ty;
     const long long plane = (long long)p.nx * p.ny;
     const unsigned pbytes = 4u * (unsigned)plane, vbytes = 4u * (unsigned)p.ldv_z;
-    const int z0 = b.zs - WARM;
-    // the thread's columns: byte offsets in a window plane and a model plane
-    float q[RY][P];        // u(z') at (z' - z0) mod P
-    float D[RY][NG][P];    // D_g(z') at (z' - z0) mod P
-    bool srccol[RY];
-    unsigned coff[RY], voff[RY];
-    float ry[RY];
-    int dyb[RY];
+    const bool yok = gy < p.ny;
+    // byte offsets of the thread's points in a window plane and a model plane
+    unsigned coff[VEC ? 1 : 4], voff[VEC ? 1 : 4];
+#pragma unroll
+    for (int i = 0; i < (VEC ? 1 : 4); ++i) {
+        const bool ok = yok && gx + i < p.nx;
+        coff[i] = ok ? 4u * (unsigned)(gy * p.nx + gx + i) : kOffGrid;
+        voff[i] = ok ? 4u * (unsigned)(gy * (int)p.ldv_y + gx + i) : kOffGrid;
+    }
+    // element offsets of the first point, 0 off the grid (16-byte operand loads)
+    const unsigned cidx = coff[0] == kOffGrid ? 0u : coff[0] / 4;
+    const unsigned vidx = voff[0] == kOffGrid ? 0u : voff[0] / 4;
+    // damping: x/y band part per point, z part per plane
     const int nb = p.sp.nb;
-    const int dxb = nb > 0 ? band_depth(b.gx, p.nx, nb) : 0;
-    const float rx = dxb * p.sp.inv_nb;
+    const int dyb = (nb > 0 && yok) ? band_depth(gy, p.ny, nb) : 0;
+    const float ry = dyb * p.sp.inv_nb;
+    float exy[4];
+    bool xyband[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int dxb = nb > 0 ? band_depth(gx + i, p.nx, nb) : 0;
+        const float rx = dxb * p.sp.inv_nb;
+        exy[i] = fmaf(rx, rx, ry * ry);
+        xyband[i] = (dxb | dyb) != 0;
+    }
     const int src_z = p.src >= 0 ? (int)(p.src / plane) : -1;
     const long long src_xy = p.src >= 0 ? p.src - (long long)src_z * plane : -1;
+    const long long my_xy = (long long)gy * p.nx + gx;
+    const int src_i = (yok && src_xy >= my_xy && src_xy < my_xy + 4 && gx + (int)(src_xy - my_xy) < p.nx)
+                          ? (int)(src_xy - my_xy) : -1;
+    const float qs = p.src >= 0 ? p.q * p.wavelet[p.step] : 0.f;
+    // transfers of an LDS plane: unit f of the plane (row-major, UNIT floats)
+    // is loaded by thread f mod NTH in pass f / NTH
+    unsigned doff[NPASS];
 #pragma unroll
-    for (int j = 0; j < RY; ++j) {
-        const int gy = b.y0 + b.ty * RY + j;
-        const bool ok = xok && gy < p.ny;
-        coff[j] = ok ? 4u * (unsigned)(gy * p.nx + b.gx) : kOffGrid;
-        voff[j] = ok ? 4u * (unsigned)(gy * (int)p.ldv_y + b.gx) : kOffGrid;
-        srccol[j] = ok && (long long)gy * p.nx + b.gx == src_xy;
-        dyb[j] = (nb > 0 && ok) ? band_depth(gy, p.ny, nb) : 0;
-        ry[j] = dyb[j] * p.sp.inv_nb;
-#pragma unroll
-        for (int k = 0; k < P; ++k) {
-            q[j][k] = 0.f;
-#pragma unroll
-            for (int g = 0; g < NG; ++g) D[j][g][k] = 0.f;
-        }
+    for (int k = 0; k < NPASS; ++k) {
+        const int f = threadIdx.x + NTH * k;
+        const int row = f / (LW / UNIT), c = (f - row * (LW / UNIT)) * UNIT;
+        const int yy = y0 - M + row, xx = x0 - MP + c;
+        const bool ok = f < NF && (unsigned)yy < (unsigned)p.ny && (unsigned)xx < (unsigned)p.nx;
+        doff[k] = ok ? 4u * (unsigned)(yy * p.nx + xx) : kOffGrid;
     }
-    // plane z of a window field (every access of a plane off the grid reads 0)
-    auto wplane = [&](const float* f, int z) {
-        const bool in = (unsigned)z < (unsigned)p.nz;
-        return plane_rsrc(f + (in ? z : 0) * plane, in ? pbytes : 0u);
-    };
-    // u(z0 - M .. z0 + M - 1) at (k mod P)
-#pragma unroll
-    for (int k = -M; k < M; ++k) {
-        const Rsrc r = wplane(p.ucur, z0 + k);
-#pragma unroll
-        for (int j = 0; j < RY; ++j) q[j][(k + P) % P] = bload(r, coff[j]);
-    }
-    // LDS planes z0 .. z0 + M - 2 (slots 0 .. M - 2)
-    for (int k = 0; k + 1 < M; ++k) load_plane<M, RY>(lds + k * G::PLANE, p.ucur, p.nx, p.ny, p.nz, b.x0, b.y0, z0 + k);
-    PlaneHalo<M, RY> halo;
-    halo.init(p.nx, p.ny, b.x0, b.y0);
-    float front[RY], dd[RY], vv[RY];
-    // byte addresses of the planes the next fetch and the next update touch:
-    // u(z + M), d(z), v(z) and d/u^{n+1}(z), advanced by one plane per call
+    const int z_begin = zs - M, z_end = ze + M;
     const unsigned long long pstep = 4ull * (unsigned long long)plane, vstep = 4ull * (unsigned long long)p.ldv_z;
-    unsigned long long au = (unsigned long long)p.ucur + (unsigned long long)(long long)(z0 + M) * pstep;
-    unsigned long long ad = (unsigned long long)p.dcur + (unsigned long long)(long long)z0 * pstep;
-    unsigned long long av = (unsigned long long)p.v + (unsigned long long)(long long)z0 * vstep;
-    unsigned long long adn = (unsigned long long)p.dnext + (unsigned long long)(long long)z0 * pstep;
-    unsigned long long aun = (unsigned long long)p.unext + (unsigned long long)(long long)z0 * pstep;
-    auto fetch = [&](int z) {   // operands of iteration z (d and v only for the chunk's own planes)
-        const bool in = z >= b.zs && z < b.ze;
-        const Rsrc ru = plane_rsrc_at(au, (unsigned)(z + M) < (unsigned)p.nz ? pbytes : 0u);
-        const Rsrc rh = plane_rsrc_at(au - pstep, (unsigned)(z + M - 1) < (unsigned)p.nz ? pbytes : 0u);
+    // running byte addresses: next plane to load into LDS; d, v of the next
+    // output to prefetch; d, u^{n+1} of the next output to finalise
+    unsigned long long au = (unsigned long long)p.ucur + (unsigned long long)(long long)z_begin * pstep;
+    unsigned long long ad = (unsigned long long)p.dcur + (unsigned long long)(long long)(z_begin - M) * pstep;
+    unsigned long long av = (unsigned long long)p.v + (unsigned long long)(long long)(z_begin - M) * vstep;
+    unsigned long long adn = (unsigned long long)p.dnext + (unsigned long long)(long long)(z_begin - M) * pstep;
+    unsigned long long aun = (unsigned long long)p.unext + (unsigned long long)(long long)(z_begin - M) * pstep;
+    int zload = z_begin, zdv = z_begin - M;
+    auto load_plane_lds = [&](float* buf) {   // plane zload into buf, then advance
+        const Rsrc r = plane_rsrc_at(au, (unsigned)zload < (unsigned)p.nz ? pbytes : 0u);
+        au += pstep;
+        ++zload;
+#pragma unroll
+        for (int k = 0; k < NPASS; ++k) {
+            if (NPASS * NTH == NF || (int)threadIdx.x + NTH * k < NF)
+                bload_lds<UNIT>(r, buf + ((threadIdx.x & ~63) + NTH * k) * UNIT, doff[k]);
+        }
+    };
+    float dd[4], vv[4];
+    auto fetch_dv = [&]() {   // d, v of output zdv, then advance
+        const bool in = zdv >= zs && zdv < ze;
         const Rsrc rd = plane_rsrc_at(ad, in ? pbytes : 0u);
         const Rsrc rv = plane_rsrc_at(av, in ? vbytes : 0u);
-        au += pstep;
         ad += pstep;
         av += vstep;
+        ++zdv;
+        if constexpr (VEC) {
+            // planes outside the chunk read plane 0 and lanes off the grid the
+            // plane's first 16 bytes: loaded, never used
+            const long long zo = in ? zdv - 1 : 0;
+            const F4 d4 = __builtin_nontemporal_load(reinterpret_cast<const F4*>(p.dcur + zo * plane + cidx));
+            const F4 v4 = __builtin_nontemporal_load(reinterpret_cast<const F4*>(p.v + zo * p.ldv_z + vidx));
 #pragma unroll
-        for (int j = 0; j < RY; ++j) {
-            front[j] = bload(ru, coff[j]);
-            dd[j] = bload<kNonTemporal>(rd, coff[j]);
-            vv[j] = bload<kNonTemporal>(rv, voff[j]);
-        }
-        halo.fetch(rh);
-    };
-    fetch(z0);
-    const float qs = p.src >= 0 ? p.q * p.wavelet[p.step] : 0.f;
-    auto body = [&](auto ph, int z) {
-        constexpr int PH = decltype(ph)::value;
-        constexpr int S_NEW = (PH + M - 1) % P;   // slot of plane z + M - 1
-        float ddc[RY], vvc[RY];
+            for (int i = 0; i < 4; ++i) {
+                dd[i] = d4[i];
+                vv[i] = v4[i];
+            }
+        } else {
 #pragma unroll
-        for (int j = 0; j < RY; ++j) {
-            q[j][(PH + M) % P] = front[j];
-            ddc[j] = dd[j];
-            vvc[j] = vv[j];
-            lds[S_NEW * G::PLANE + (b.ty * RY + j + M) * G::LW + b.tx + M] = q[j][S_NEW];
-        }
-        halo.store(lds + S_NEW * G::PLANE);
-        if (z + 1 < b.ze) fetch(z + 1);
-        __syncthreads();
-#pragma unroll
-        for (int j = 0; j < RY; ++j)
-            ball_form_d<0, NG, M, RY, PH, P>(D[j], lds, q[j], b.ty * RY + j + M, b.tx + M);
-        const Rsrc rdn = plane_rsrc_at(adn, pbytes);
-        const Rsrc run = plane_rsrc_at(aun, pbytes);
-        adn += pstep;
-        aun += pstep;
-        if (z >= b.zs) {
-            const int dzb = nb > 0 ? band_depth(z, p.nz, nb) : 0;
-            const float rz = dzb * p.sp.inv_nb;
-#pragma unroll
-            for (int j = 0; j < RY; ++j) {
-                const float uc = q[j][PH];
-                float L = ball_combine<0, NG, M, PH, P>(D[j], p.w, 0.f);
-#pragma unroll
-                for (int dz = 1; dz <= M; ++dz)
-                    L = fmaf(p.w.wc[dz], fmaf(-2.f, uc, q[j][(PH + dz) % P] + q[j][(PH + P - dz) % P]), L);
-                const bool inband = (dxb | dyb[j] | dzb) != 0;
-                const float e = inband ? p.sp.escale * fmaf(rx, rx, fmaf(ry[j], ry[j], rz * rz)) : 0.f;
-                const float d = delta_update(ddc[j], vvc[j], L, inband, e, srccol[j] && z == src_z, qs);
-                bstore_nt(d, rdn, coff[j]);         // lanes off the grid: dropped
-                bstore_nt(uc + d, run, coff[j]);
+            for (int i = 0; i < 4; ++i) {
+                dd[i] = bload<kNonTemporal>(rd, coff[i]);
+                vv[i] = bload<kNonTemporal>(rv, voff[i]);
             }
         }
     };
-    for (int z = z0; z < b.ze; z += P) run_phases<0, P>(body, z, b.ze);
+    float q[M][4];      // u(z'') of the thread's points at slot (z'' - z_begin) mod M
+    float acc[Q][4];    // partial sum of output o at slot (o - z_begin) mod Q
+#pragma unroll
+    for (int k = 0; k < M; ++k)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) q[k][i] = 0.f;
+#pragma unroll
+    for (int k = 0; k < Q; ++k)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) acc[k][i] = 0.f;
+    // the finished update of the previous plane, stored after the next barrier
+    float pd[4], pu[4];
+    bool pending = false;
+    Rsrc pst_d = plane_rsrc_at(0, 0u), pst_u = plane_rsrc_at(0, 0u);
+    auto flush = [&]() {
+        if (!pending) return;
+        if constexpr (VEC) {
+            U4 d4, u4;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                d4[i] = __builtin_bit_cast(unsigned, pd[i]);
+                u4[i] = __builtin_bit_cast(unsigned, pu[i]);
+            }
+            bstore4_nt(d4, pst_d, coff[0]);
+            bstore4_nt(u4, pst_u, coff[0]);
+        } else {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                bstore_nt(pd[i], pst_d, coff[i]);
+                bstore_nt(pu[i], pst_u, coff[i]);
+            }
+        }
+        pending = false;
+    };
+    load_plane_lds(lds);
+    auto body = [&](auto ph, int zp) {
+        constexpr int PH = decltype(ph)::value;
+        float* cur = lds + (PH & 1) * PLANE;
+        // this wave's loads into LDS (and every other memory operation it has
+        // in flight) complete, then the barrier: plane zp is in cur, and every
+        // thread is done with the other buffer
+        __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
+        __syncthreads();
+        if (zp + 1 < z_end) load_plane_lds(lds + ((PH & 1) ^ 1) * PLANE);
+        fetch_dv();   // d, v of output zp - M, used at the end of this iteration
+        flush();
+        float S[NG][4], uc[4];
+        ball_rows_from<M, MP, LW, Q, PH, 0, NG>(cur + (ty + M) * LW + 4 * tq, S, uc, acc, p.w);
+        // z differences: output zp - m and output zp
+        cfor<1, M + 1>([&](auto mc) {
+            constexpr int m = decltype(mc)::value;
+            constexpr int qs_ = ((PH - m) % M + M) % M, as = ((PH - m) % Q + Q) % Q;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const float dl = uc[i] - q[qs_][i];
+                acc[as][i] = fmaf(p.w.wc[m], dl, acc[as][i]);
+                acc[PH][i] = fmaf(-p.w.wc[m], dl, acc[PH][i]);
+            }
+        });
+        // output o = zp - M is complete
+        constexpr int QO = PH % M, AO = (PH + M) % Q;
+        const int o = zp - M;
+        if (o >= zs && o < ze) {
+            const int dzb = nb > 0 ? band_depth(o, p.nz, nb) : 0;
+            const float rz = dzb * p.sp.inv_nb;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const bool inband = xyband[i] || dzb != 0;
+                const float e = inband ? p.sp.escale * fmaf(rz, rz, exy[i]) : 0.f;
+                const float d = delta_update(dd[i], vv[i], acc[AO][i], inband, e, src_i == i && o == src_z, qs);
+                pd[i] = d;
+                pu[i] = q[QO][i] + d;
+            }
+            pst_d = plane_rsrc_at(adn, pbytes);
+            pst_u = plane_rsrc_at(aun, pbytes);
+            pending = true;
+        }
+        adn += pstep;
+        aun += pstep;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) q[QO][i] = uc[i];
+    };
+    for (int z = z_begin; z < z_end; z += Q) run_phases<0, Q>(body, z, z_end);
+    flush();
 }
 
 template <int SHAPE, int M, int RY>
@@ -1156,21 +1294,34 @@ static bool cross_rows_adj(const AdjArgs& a, int rows, hipStream_t s) {
     }
     return false;
 }
-template <int M, int RY>
+// The ball kernel tiles 64 x 4W points (W waves; rows = 1: W = 4, rows = 2:
+// W = 8) and takes its own tile grid.
+template <int M, int W>
 static void run_ball(const StepArgs& a, hipStream_t s) {
-    hipLaunchKernelGGL((k_fwd3d_ball<M, RY>), dim3(a.ntiles), dim3(kBlock3), 0, s, a);
+    StepArgs b = a;
+    constexpr int TY = BallGeo<M, W>::TY;
+    b.tiles_x = (a.nx + 63) / 64;
+    b.tiles_y = (a.ny + TY - 1) / TY;
+    b.ntiles = b.tiles_x * b.tiles_y * ((a.nz + a.zchunk - 1) / a.zchunk);
+    auto al16 = [](const void* q) { return ((uintptr_t)q & 15) == 0; };
+    const bool vec = a.nx % 4 == 0 && a.ldv_y % 4 == 0 && a.ldv_z % 4 == 0 && al16(a.ucur) && al16(a.dcur) &&
+                     al16(a.dnext) && al16(a.unext) && al16(a.v);
+    if (vec)
+        hipLaunchKernelGGL((k_fwd3d_ball<M, W, 1>), dim3(b.ntiles), dim3(64 * W), 0, s, b);
+    else
+        hipLaunchKernelGGL((k_fwd3d_ball<M, W, 0>), dim3(b.ntiles), dim3(64 * W), 0, s, b);
 }
 template <int M>
 static bool ball_rows(const StepArgs& a, int rows, hipStream_t s) {
     if constexpr (M <= 4) {
         switch (rows) {
-            case 1: run_ball<M, 1>(a, s); return true;
-            case 2: run_ball<M, 2>(a, s); return true;
+            case 1: run_ball<M, 4>(a, s); return true;
+            case 2: run_ball<M, 8>(a, s); return true;
         }
         return false;
     } else {
         if (rows != 1) return false;
-        run_ball<M, 1>(a, s);
+        run_ball<M, 4>(a, s);
         return true;
     }
 }

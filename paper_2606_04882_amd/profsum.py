@@ -24,10 +24,23 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 
 
+def _code_only(text: bytes) -> bytes:
+    """Source text without // comments and blank lines, so that a record
+    survives edits of comments but not of code."""
+    out = []
+    for line in text.decode("utf-8", "replace").splitlines():
+        if '"' not in line and "//" in line:
+            line = line[:line.index("//")]
+        line = line.rstrip()
+        if line:
+            out.append(line)
+    return "\n".join(out).encode()
+
+
 def kernel_sources_sha(kernel: str) -> str:
-    """sha256 (16 hex digits) over what a kernel is built from: its .hip file
-    (k_fwd2d<...> -> k_fwd2d.hip, k_fwd3d_cross<...> -> k_fwd3d.hip), every
-    header of csrc/ and the build script with its flags."""
+    """sha256 (16 hex digits) over what a kernel is built from, comments
+    aside: its .hip file (k_fwd2d<...> -> k_fwd2d.hip, k_fwd3d_cross<...> ->
+    k_fwd3d.hip), every header of csrc/ and the build script with its flags."""
     base = kernel.split("<")[0].split("::")[-1].replace("void ", "").strip()
     hip = os.path.join(CSRC, base + ".hip")
     while not os.path.exists(hip) and "_" in base:
@@ -40,7 +53,7 @@ def kernel_sources_sha(kernel: str) -> str:
     h = hashlib.sha256()
     for f in files:
         with open(f, "rb") as fh:
-            h.update(fh.read())
+            h.update(_code_only(fh.read()))
     return h.hexdigest()[:16]
 
 

@@ -138,13 +138,18 @@ def test_3d_adjoint_gradient(F, shape, M):
     assert rel_l2(grad.cpu().numpy(), gref) <= 1e-3
 
 
-@pytest.mark.parametrize("M,rows,zchunk", [(4, 1, 8), (6, 1, 8), (3, 1, 24), (2, 2, 8), (5, 1, 40)])
-def test_3d_ball_z_chunks(F, M, rows, zchunk):
-    """The L1-ball (3D rhombus) kernel warms up 2 (M - 1) planes below each z
-    chunk, reaching into the chunk below (or off the grid): chunks shorter
-    than the warm-up, ragged last chunks and a source on a chunk boundary
-    against the oracle, 1e-5 (traces and final state)."""
-    nz, ny, nx, h, nt, nb = 45, 19, 70, 10.0, 50, 5
+@pytest.mark.parametrize("nx", [70, 64])
+@pytest.mark.parametrize("M,rows,zchunk", [(4, 1, 8), (6, 1, 8), (3, 1, 24), (2, 2, 8), (5, 1, 40), (1, 1, 16),
+                                          (4, 2, 512)])
+def test_3d_ball_z_chunks(F, M, rows, zchunk, nx):
+    """The L1-ball (3D rhombus) kernel runs M planes before and after each z
+    chunk, reaching into the neighbouring chunks (or off the grid): chunks
+    shorter than that, ragged last chunks, one chunk for the whole column and
+    a source on a chunk boundary against the oracle, 1e-5 (traces and final
+    state).  nx = 64 takes the 16-byte load/store path, nx = 70 the 4-byte
+    one."""
+    nz, ny, h, nt, nb = 45, 19, 10.0, 50, 5
+    zc = min(zchunk, nz - 3)
     vel = layered((nz, ny, nx), seed=40 + M)
     vmax = float(vel.max())
     dt = 0.35 * 0.5 * h / vmax
@@ -153,8 +158,8 @@ def test_3d_ball_z_chunks(F, M, rows, zchunk):
     F.fd_set_tile(sid, rows, zchunk)
     eta = synth.sponge_eta_max(vmax, nb, h)
     wav = synth.ricker(nt, dt, 30.0)
-    src = (33, 9, zchunk)              # first plane of the second chunk
-    rec = [[x, y, z] for x in range(1, nx - 1, 6) for y in (2, 10) for z in (zchunk - 1, zchunk, 30)]
+    src = (33, 9, zc)                  # first plane of the second chunk
+    rec = [[x, y, z] for x in range(1, nx - 1, 6) for y in (2, 10) for z in (zc - 1, zc, 30)]
     gpu = run3(F, vel, h, dt, nt, nb, eta, sid, src, wav, rec, final=True)
     ref = oracle_traces(3, "rhombus", M, wo, vel, h, dt, nt, nb, eta, src, wav, rec)
     check_traces(gpu["traces"], ref["traces"])

@@ -820,7 +820,9 @@ __global__ __launch_bounds__(kBlock3) void k_fwd3d_gen(StepArgs p) {
 // D_ab(z') is formed once and added with its weights into the partial sums
 // of the outputs z' - (M-a-b) .. z' + (M-a-b), and the z differences
 // u(z') - u(z'-m), m = 1..M, go to outputs z' - m and z'; output z' - M is
-// then complete and updated.  A thread owns four consecutive points of a row
+// then complete and updated.  Transfers whose offset fails the range check
+// (cells off the grid, planes off the grid) write zeros into LDS, as the
+// stencil reads them.  A thread owns four consecutive points of a row
 // (16 threads per 64-point row), so a row window of its points' in-plane
 // neighbours is 1 + MP/2 aligned 16-byte LDS reads, and per point it keeps
 // 2M partial sums and M queued values of u.  The z loop is unrolled by the

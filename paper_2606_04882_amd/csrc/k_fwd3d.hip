@@ -502,16 +502,153 @@ __global__ __launch_bounds__(kBlock3) void k_fwd3d_cross_wide(StepArgs p) {
     }
 }
 
-// Adjoint step and gradient term (cross), pipelined like k_fwd3d_cross: the
+// Adjoint step and gradient term (cross), laid out like k_fwd3d_cross: the
 // operands of plane z+1 (queue fronts of psi^{k+1} and u^k, psi^{k+2}, v,
 // the gradient and both halos) are fetched while plane z is computed; both
-// xy planes alternate between two LDS buffers (one barrier per plane).
-// psi^{k+2}, v and the gradient are touched once per step and streamed
-// non-temporally; psi^{k+1} and u^k stay cacheable for the neighbouring
-// blocks' halo reads.  psi^k may overwrite psi^{k+2} in place: every point is
-// read (fetch of its plane) before the same thread writes it.
+// xy planes alternate between two LDS buffers (one barrier per plane); the
+// z loop is unrolled by the queue period 2M + 1 and every field goes through
+// range-checked per-plane buffer descriptors (a field the call does not use
+// gets size 0: its loads return 0 and cost no traffic).  psi^{k+2}, v and
+// the gradient are touched once per step and streamed non-temporally;
+// psi^{k+1} and u^k stay cacheable for the neighbouring blocks' halo reads.
+// psi^k may overwrite psi^{k+2} in place: every point is read (fetch of its
+// plane) before the same thread writes it; likewise the gradient.
 template <int M, int RY>
-__global__ __launch_bounds__(kBlock3) void k_adj3d_cross(AdjArgs p) {
+__global__ __launch_bounds__(kBlock3) __attribute__((amdgpu_waves_per_eu((RY == 1 || (RY == 2 && M <= 5)) ? 4 : 2))) void k_adj3d_cross(AdjArgs p) {
+    using G = Geo3<M, RY>;
+    constexpr int P = 2 * M + 1;
+    __shared__ float tp[2][G::PLANE];
+    __shared__ float tu[2][G::PLANE];
+    const Pos3 b = block_pos<RY>(p.ntiles, p.tiles_x, p.tiles_y, p.zchunk, p.nz);
+    const bool xok = b.gx < p.nx;
+    const long long plane = (long long)p.nx * p.ny;
+    const bool wg = p.with_grad, wu = p.with_update;
+    const unsigned pbytes = 4u * (unsigned)plane, vbytes = 4u * (unsigned)p.ldv_z;
+    const unsigned ubytes = wg ? pbytes : 0u, gbytes = wg ? vbytes : 0u, ppbytes = wu ? pbytes : 0u;
+    const int z0 = b.zs;
+    float qp[RY][P], qu[RY][P];   // psi^{k+1}(z'), u^k(z') at (z' - z0) mod P
+    unsigned coff[RY], voff[RY];
+    int dyb[RY];
+    const int nb = p.sp.nb;
+    const int dxb = nb > 0 ? band_depth(b.gx, p.nx, nb) : 0;
+#pragma unroll
+    for (int j = 0; j < RY; ++j) {
+        const int gy = b.y0 + b.ty * RY + j;
+        const bool ok = xok && gy < p.ny;
+        coff[j] = ok ? 4u * (unsigned)(gy * p.nx + b.gx) : kOffGrid;
+        voff[j] = ok ? 4u * (unsigned)(gy * (int)p.ldv_y + b.gx) : kOffGrid;
+        dyb[j] = (nb > 0 && ok) ? band_depth(gy, p.ny, nb) : 0;
+    }
+#pragma unroll
+    for (int k = -M; k < M; ++k) {
+        const int z = z0 + k;
+        const bool in = (unsigned)z < (unsigned)p.nz;
+        const Rsrc rp = plane_rsrc(p.pcur + (in ? z : 0) * plane, in ? pbytes : 0u);
+        const Rsrc ru = plane_rsrc(p.ufwd + (in ? z : 0) * plane, in ? ubytes : 0u);
+#pragma unroll
+        for (int j = 0; j < RY; ++j) {
+            qp[j][(k + P) % P] = bload(rp, coff[j]);
+            qu[j][(k + P) % P] = bload(ru, coff[j]);
+        }
+    }
+    PlaneHalo<M, RY> hp, hu;
+    hp.init(p.nx, p.ny, b.x0, b.y0);
+    hu.init(p.nx, p.ny, b.x0, b.y0);
+    float fp[RY], fu[RY], pp[RY], vv[RY], gg[RY];
+    // running byte addresses: queue fronts (z + M), halo planes (z), psi^{k+2},
+    // v and the gradient of the next fetch; psi^k and the gradient of the next
+    // update
+    const unsigned long long pstep = 4ull * (unsigned long long)plane, vstep = 4ull * (unsigned long long)p.ldv_z;
+    unsigned long long apf = (unsigned long long)p.pcur + (unsigned long long)(long long)(z0 + M) * pstep;
+    unsigned long long auf = (unsigned long long)p.ufwd + (unsigned long long)(long long)(z0 + M) * pstep;
+    unsigned long long aph = (unsigned long long)p.pcur + (unsigned long long)(long long)z0 * pstep;
+    unsigned long long auh = (unsigned long long)p.ufwd + (unsigned long long)(long long)z0 * pstep;
+    unsigned long long app = (unsigned long long)p.pprev + (unsigned long long)(long long)z0 * pstep;
+    unsigned long long av = (unsigned long long)p.v + (unsigned long long)(long long)z0 * vstep;
+    unsigned long long ag = (unsigned long long)p.grad + (unsigned long long)(long long)z0 * vstep;
+    unsigned long long apn = (unsigned long long)p.pnext + (unsigned long long)(long long)z0 * pstep;
+    unsigned long long agw = ag;
+    auto fetch = [&](int z) {   // operands of iteration z (z < ze <= nz)
+        const bool fin = z + M < p.nz;
+        const Rsrc rpf = plane_rsrc_at(apf, fin ? pbytes : 0u), ruf = plane_rsrc_at(auf, fin ? ubytes : 0u);
+        const Rsrc rph = plane_rsrc_at(aph, pbytes), ruh = plane_rsrc_at(auh, ubytes);
+        const Rsrc rpp = plane_rsrc_at(app, ppbytes), rv = plane_rsrc_at(av, vbytes), rg = plane_rsrc_at(ag, gbytes);
+        apf += pstep;
+        auf += pstep;
+        aph += pstep;
+        auh += pstep;
+        app += pstep;
+        av += vstep;
+        ag += vstep;
+#pragma unroll
+        for (int j = 0; j < RY; ++j) {
+            fp[j] = bload(rpf, coff[j]);
+            fu[j] = bload(ruf, coff[j]);
+            pp[j] = bload<kNonTemporal>(rpp, coff[j]);
+            vv[j] = bload<kNonTemporal>(rv, voff[j]);
+            gg[j] = bload<kNonTemporal>(rg, voff[j]);
+        }
+        hp.fetch(rph);
+        if (wg) hu.fetch(ruh);
+    };
+    fetch(z0);
+    int buf = 0;
+    auto body = [&](auto ph, int z) {
+        constexpr int PH = decltype(ph)::value;
+        float* tpb = tp[buf];
+        float* tub = tu[buf];
+        float ppc[RY], vvc[RY], ggc[RY];
+#pragma unroll
+        for (int j = 0; j < RY; ++j) {
+            qp[j][(PH + M) % P] = fp[j];
+            qu[j][(PH + M) % P] = fu[j];
+            ppc[j] = pp[j];
+            vvc[j] = vv[j];
+            ggc[j] = gg[j];
+            tpb[(b.ty * RY + j + M) * G::LW + b.tx + M] = qp[j][PH];
+            tub[(b.ty * RY + j + M) * G::LW + b.tx + M] = qu[j][PH];
+        }
+        hp.store(tpb);
+        if (wg) hu.store(tub);
+        if (z + 1 < b.ze) fetch(z + 1);
+        __syncthreads();
+        const int dzb = nb > 0 ? band_depth(z, p.nz, nb) : 0;
+        const Rsrc rg = plane_rsrc_at(agw, gbytes), rn = plane_rsrc_at(apn, wu ? pbytes : 0u);
+        agw += vstep;
+        apn += pstep;
+#pragma unroll
+        for (int j = 0; j < RY; ++j) {
+            const int row = b.ty * RY + j + M;
+            const float pc = qp[j][PH];
+            if (wg) {
+                const float Lu = cross_sum_q<M, RY, PH, P>(tub, qu[j], row, b.tx + M, p.w);
+                bstore_nt(fmaf(grad_factor(p.gparam, p.gscale, vvc[j]) * pc, Lu, ggc[j]), rg, voff[j]);
+            }
+            if (wu) {
+                const float Lp = cross_sum_q<M, RY, PH, P>(tpb, qp[j], row, b.tx + M, p.w);
+                const bool inband = (dxb | dyb[j] | dzb) != 0;
+                float r;
+                if (!inband) {
+                    r = fmaf(vvc[j], Lp, 2.f * pc - ppc[j]);
+                } else {
+                    const float rx = dxb * p.sp.inv_nb, ry = dyb[j] * p.sp.inv_nb, rz = dzb * p.sp.inv_nb;
+                    const float e = p.sp.escale * fmaf(rx, rx, fmaf(ry, ry, rz * rz));
+                    r = fmaf(-(1.f - e), ppc[j], 2.f * pc);
+                    r = fmaf(vvc[j], Lp, r);
+                    r = r / (1.f + e);
+                }
+                bstore_nt(r, rn, coff[j]);
+            }
+        }
+        buf ^= 1;
+    };
+    for (int z = z0; z < b.ze; z += P) run_phases<0, P>(body, z, b.ze);
+}
+
+// The same step with 64-bit addressing, for windows whose planes exceed the
+// 2^31-byte range of a buffer descriptor.
+template <int M, int RY>
+__global__ __launch_bounds__(kBlock3) void k_adj3d_cross_wide(AdjArgs p) {
     using G = Geo3<M, RY>;
     constexpr int NQ = 2 * M + 1;
     __shared__ float tp[2][G::PLANE];
@@ -1267,7 +1404,10 @@ static void run_cross(const StepArgs& a, hipStream_t s) {
 }
 template <int M, int RY>
 static void run_cross_adj(const AdjArgs& a, hipStream_t s) {
-    hipLaunchKernelGGL((k_adj3d_cross<M, RY>), dim3(a.ntiles), dim3(kBlock3), 0, s, a);
+    if ((long long)a.nx * a.ny < (1LL << 29) && a.ldv_z < (1LL << 29))
+        hipLaunchKernelGGL((k_adj3d_cross<M, RY>), dim3(a.ntiles), dim3(kBlock3), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_adj3d_cross_wide<M, RY>), dim3(a.ntiles), dim3(kBlock3), 0, s, a);
 }
 template <int SHAPE, int M, int RY>
 static void run_gen(const StepArgs& a, hipStream_t s) {

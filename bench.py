@@ -358,6 +358,8 @@ def large2d_bench(torch, F, autotune, configs, design, dev, args, reps=5):
     w, _, vel, grid, variants = setup_2d(torch, F, autotune, configs, design, dev, args)
     npts = int(np.prod(w.shape))
     shots = [v["shot"] for v in variants]
+    if not args.no_tune:
+        autotune.tune_batched(grid, vel, shots, [v["name"] for v in variants])
     ws_all = torch.empty(F.fd_workspace_bytes(grid, shots), dtype=torch.uint8, device=dev)
     F.fd_forward(grid, vel, shots, ws=ws_all)
     torch.cuda.synchronize()
@@ -367,7 +369,7 @@ def large2d_bench(torch, F, autotune, configs, design, dev, args, reps=5):
         F.fd_forward(grid, vel, [v["shot"]], ws=v["ws"])
         t = _event_time(torch, lambda: F.fd_forward(grid, vel, [v["shot"]], ws=v["ws"]), reps=2)
         alone.append({"stencil": v["name"], "gupd_s": round(npts * w.nt / (t * 1e-3) / 1e9, 1),
-                      "rows": v["rows"]})
+                      "rows": v["rows"], "batched_rows": F.fd_get_batch_tile(v["sid"])})
     return {"grid": list(w.shape), "nt": w.nt, "batched_ms": round(ms, 3),
             "batched_gupd_s": round(npts * w.nt * len(variants) / (ms * 1e-3) / 1e9, 1),
             "sequential_ms": round(sum(npts * w.nt / (a["gupd_s"] * 1e9) * 1e3 for a in alone), 3),

@@ -342,12 +342,26 @@ int fd_revolve_plan(int nt, int nsnap, int* ops, long long max_ops, long long* n
  * fd_set_tile overrides the built-in choice (as found by the autotuner);
  * rows must be one of 1, 2, 4, 8 and zchunk a multiple of 8 in [8, 4096].
  * The setting applies to single-shot kernels (and to shots run one after the
- * other with FD_NO_BATCH); batched 2D calls use fixed tiles, 8 rows for the
- * forward steps of dense (non-cross) stencils and 4 rows otherwise.  The
- * results do not depend on the tile configuration.
+ * other with FD_NO_BATCH); batched 2D calls take their forward tiles from
+ * fd_set_batch_tile and run their adjoint steps at 4 rows.  The results do
+ * not depend on the tile configuration.
  */
 int fd_set_tile(int stencil_id, int rows, int zchunk);
 int fd_get_tile(int stencil_id, int* rows, int* zchunk);
+
+/*
+ * Tile of a 2D stencil's variant group in the forward steps of batched
+ * calls (nshots > 1): rows per thread, 4 (64 x 16 tiles) or 8 (64 x 32, not
+ * for crosses), or 0 for the built-in choice (8 for dense shapes, 4 for
+ * crosses).  The groups of a batched call run concurrently, so the best tile
+ * differs from the single-shot one; the autotuner times whole batched calls
+ * to choose it.  Results do not depend on the setting.  fd_get_batch_tile
+ * returns the rows in effect.
+ * Errors: FD_EINVAL (unknown stencil, rows not 0, 4 or 8), FD_EUNSUPPORTED
+ * (3D stencil; rows = 8 for a cross).
+ */
+int fd_set_batch_tile(int stencil_id, int rows);
+int fd_get_batch_tile(int stencil_id, int* rows);
 
 /*
  * Time steps per kernel launch of the forward (kept for callers of the

@@ -4,7 +4,8 @@ For a stencil on a given grid, times a short forward run for every compiled
 configuration (2D: rows per thread 2, 4, 8, and for crosses also the
 z-marching kernel with chunks of 16-48 rows; 3D: rows 1, 2, 4 (crosses) or
 1, 2 times z-chunk 32 .. 1024) and installs the fastest with
-fd_set_tile.  Results are
+fd_set_tile.  For batched calls, tune_batched times the whole call to choose
+each dense stencil's batched tile (fd_set_batch_tile).  Results are
 cached in a JSON file keyed by device, dimension, stencil and grid size, so a
 tuned configuration is reused by later runs; configurations tuned on MI355X
 for the standard workloads ship with the package (tuned_mi355x.json) and are
@@ -133,6 +134,69 @@ def tune(stencil_id: int, ndim: int, shape: str, M: int, grid: F.Grid, vel: torc
     rows, zc, ts = (int(x) for x in win.split("x"))
     _install(stencil_id, ndim, rows, zc, ts)
     rec = {"rows": rows, "zchunk": zc, "tsteps": ts, "ms": times}
+    if use_cache:
+        db = _load()
+        db[key] = rec
+        _store(db)
+    return dict(rec, cached=False)
+
+
+def tune_batched(grid: F.Grid, vel: torch.Tensor, shots: Sequence[F.Shot], names: Sequence[str],
+                 nt: int = 40, reps: int = 2, use_cache: bool = True) -> Dict:
+    """Choose the batched forward tile (fd_set_batch_tile) of every dense
+    stencil of a batched call by timing the whole call: its variant groups run
+    concurrently, so a group's best tile depends on the others.  One pass over
+    the dense stencils (those that accept 8 rows), each tried at 4 and 8 rows
+    with the others at their current choice; names[i] labels shot i's
+    stencil.  Results are cached under the device, the grid and the sorted
+    stencil names; returns {"rows": {name: rows}, "ms": {trial: time}}."""
+    label = {}
+    for s, n in zip(shots, names):
+        label[s.stencil_id] = n
+    key = f"v5|{device_tag()}|batched|{'x'.join(str(int(n)) for n in grid.shape)}|{','.join(sorted(names))}"
+    db = {}
+    if use_cache:
+        db = _load(PACKAGED)
+        db.update(_load())
+    if key in db:
+        e = db[key]
+        for sid, n in label.items():
+            if n in e["rows"]:
+                F.fd_set_batch_tile(sid, e["rows"][n])
+        return dict(e, cached=True)
+    g = F.Grid(shape=grid.shape, h=grid.h, dt=grid.dt, nt=nt, nb=grid.nb, eta_max=grid.eta_max,
+               vmax=grid.vmax)
+
+    def timed() -> float:
+        F.fd_forward(g, vel, list(shots))     # capture / warm-up
+        torch.cuda.synchronize()
+        best = float("inf")
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            F.fd_forward(g, vel, list(shots))
+            e1.record()
+            torch.cuda.synchronize()
+            best = min(best, e0.elapsed_time(e1))
+        return best
+
+    times = {"start": timed()}
+    current = times["start"]
+    for sid, n in sorted(label.items(), key=lambda kv: kv[1]):
+        try:
+            F.fd_set_batch_tile(sid, 8)
+        except F.FdError:
+            continue                              # crosses: one batched tile
+        rows_now = F.fd_get_batch_tile(sid)
+        alt = 4 if rows_now == 8 else 8
+        F.fd_set_batch_tile(sid, alt)
+        t = timed()
+        times[f"{n}:{alt}"] = t
+        if t < current:
+            current = t
+        else:
+            F.fd_set_batch_tile(sid, 8 if alt == 4 else 4)
+    rec = {"rows": {n: F.fd_get_batch_tile(sid) for sid, n in label.items()}, "ms": times}
     if use_cache:
         db = _load()
         db[key] = rec

@@ -220,7 +220,14 @@ struct Stencil {
     double cfl;
     int rows, zchunk;
     int tsteps;   // single-shot forward: time steps per launch (1 or 2)
+    int brows;    // batched 2D forward: rows per thread (0: 8 for dense shapes, 4 for crosses)
 };
+
+// rows per thread of a stencil's group in the forward steps of a batched call
+int batch_forward_rows(const Stencil& st) {
+    if (st.brows) return st.brows;
+    return st.shape != SH_CROSS ? 8 : 4;
+}
 
 std::mutex g_mu;
 std::vector<Stencil> g_stencils;
@@ -1336,13 +1343,12 @@ void build_batch_blob(CallCtx& c, int mode) {
             CallCtx::Group g;
             g.shape = s.st.shape;
             g.M = s.st.M;
-            // forward steps of dense (non-cross) groups run on 64 x 32 tiles,
-            // whatever the stencil's single-shot tuning: with the groups
-            // running concurrently, the taller tiles' smaller halo share wins
-            // (8-stencil 1001^2 step 64.8 -> 60.4 ms; crosses are faster at
-            // 4 rows); the adjoint's job list (shared with its recompute)
-            // stays at 4
-            g.rows = (mode == MODE_FORWARD && s.st.shape != SH_CROSS) ? 8 : batch_rows();
+            // forward steps: the stencil's batched tile (fd_set_batch_tile;
+            // by default 64 x 32 for dense shapes, 64 x 16 for crosses: with
+            // the groups running concurrently the dense groups' taller tiles
+            // win, 8-stencil 1001^2 step 64.8 -> 60.4 ms); the adjoint's job
+            // list (shared with its recompute) stays at 4 rows
+            g.rows = mode == MODE_FORWARD ? batch_forward_rows(s.st) : batch_rows();
             g.d0 = k;
             g.dn = 0;
             g.job0 = (long long)jobs.size();
@@ -1510,7 +1516,7 @@ int run_call(CallCtx& c, int mode, hipStream_t user) {
     for (const ShotCtx& s : c.shots) {
         key_push(key, s.s, sizeof(fd_shot));
         key.push_back(((uint64_t)s.st.rows << 32) | (uint32_t)s.st.zchunk);
-        key.push_back((uint64_t)s.st.tsteps);
+        key.push_back(((uint64_t)s.st.tsteps << 32) | (uint32_t)s.st.brows);
     }
     std::lock_guard<std::mutex> lk(g_graphs.mu);
     GraphCache::Entry* entry = nullptr;
@@ -1863,6 +1869,7 @@ int fd_weights_set_n(int ndim, int shape, int M, int N, const double* w, int nw,
     st.rows = default_rows(ndim, ks, M);
     st.zchunk = ndim == 3 ? 512 : 64;
     st.tsteps = 1;
+    st.brows = 0;
     std::lock_guard<std::mutex> lk(g_mu);
     for (size_t i = 0; i < g_stencils.size(); ++i) {
         const Stencil& e = g_stencils[i];
@@ -1924,6 +1931,25 @@ int fd_get_tile(int stencil_id, int* rows, int* zchunk) {
     if (!get_stencil(stencil_id, &st)) return fail(FD_EINVAL, "unknown stencil id");
     if (rows) *rows = st.rows;
     if (zchunk) *zchunk = st.zchunk;
+    return FD_OK;
+}
+
+int fd_set_batch_tile(int stencil_id, int rows) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (stencil_id < 0 || stencil_id >= (int)g_stencils.size()) return fail(FD_EINVAL, "unknown stencil id");
+    if (rows != 0 && rows != 4 && rows != 8) return fail(FD_EINVAL, "batched rows must be 0, 4 or 8");
+    Stencil& s = g_stencils[stencil_id];
+    if (s.ndim != 2) return fail(FD_EUNSUPPORTED, "batched calls are 2D only");
+    if (rows == 8 && s.shape == SH_CROSS) return fail(FD_EUNSUPPORTED, "no batched cross kernel for rows = 8");
+    s.brows = rows;
+    return FD_OK;
+}
+
+int fd_get_batch_tile(int stencil_id, int* rows) {
+    Stencil st;
+    if (!get_stencil(stencil_id, &st)) return fail(FD_EINVAL, "unknown stencil id");
+    if (st.ndim != 2) return fail(FD_EUNSUPPORTED, "batched calls are 2D only");
+    if (rows) *rows = batch_forward_rows(st);
     return FD_OK;
 }
 

@@ -8,7 +8,8 @@ raises immediately - there is no CPU fallback.
 
 Names follow the C entry points: fd_orbits, fd_weights_set, fd_cfl_limit,
 fd_forward, fd_adjoint_gradient, fd_workspace_bytes, fd_set_tile,
-fd_get_tile, fd_set_time_block, fd_get_time_block, fd_last_error
+fd_get_tile, fd_set_batch_tile, fd_get_batch_tile, fd_set_time_block,
+fd_get_time_block, fd_last_error
 (fd_orbits and fd_weights_set take the inner size N of the cross-rhombus and
 cross-square shapes as a keyword and call fd_orbits_n / fd_weights_set_n).
 """
@@ -84,6 +85,8 @@ def _load() -> ctypes.CDLL:
     lib.fd_cfl_limit.argtypes = [ctypes.c_int, P(ctypes.c_double)]
     lib.fd_set_tile.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int]
     lib.fd_get_tile.argtypes = [ctypes.c_int, P(ctypes.c_int), P(ctypes.c_int)]
+    lib.fd_set_batch_tile.argtypes = [ctypes.c_int, ctypes.c_int]
+    lib.fd_get_batch_tile.argtypes = [ctypes.c_int, P(ctypes.c_int)]
     lib.fd_set_time_block.argtypes = [ctypes.c_int, ctypes.c_int]
     lib.fd_get_time_block.argtypes = [ctypes.c_int, P(ctypes.c_int)]
     lib.fd_workspace_bytes.restype = ctypes.c_size_t
@@ -157,6 +160,16 @@ def fd_get_tile(stencil_id: int) -> Tuple[int, int]:
     r, z = ctypes.c_int(), ctypes.c_int()
     _check(_lib.fd_get_tile(stencil_id, ctypes.byref(r), ctypes.byref(z)))
     return r.value, z.value
+
+
+def fd_set_batch_tile(stencil_id: int, rows: int):
+    _check(_lib.fd_set_batch_tile(stencil_id, rows))
+
+
+def fd_get_batch_tile(stencil_id: int) -> int:
+    r = ctypes.c_int()
+    _check(_lib.fd_get_batch_tile(stencil_id, ctypes.byref(r)))
+    return r.value
 
 
 def fd_set_time_block(stencil_id: int, steps: int):

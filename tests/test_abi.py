@@ -32,7 +32,8 @@ def declared():
 def test_header_declares_the_entry_points():
     names = declared()
     for n in ["fd_orbits", "fd_weights_set", "fd_cfl_limit", "fd_forward", "fd_adjoint_gradient",
-              "fd_workspace_bytes", "fd_set_tile", "fd_get_tile", "fd_set_time_block",
+              "fd_workspace_bytes", "fd_set_tile", "fd_get_tile", "fd_set_batch_tile", "fd_get_batch_tile",
+              "fd_set_time_block",
               "fd_get_time_block", "fd_last_error"]:
         assert n in names
 
@@ -106,6 +107,27 @@ def test_tile_controls_reject_unknown_configurations(F):
     with pytest.raises(F.FdError) as e:
         F.fd_set_tile(sid, 3)
     assert e.value.code == F.FD_EINVAL
+
+
+def test_batch_tile_controls(F):
+    """Batched forward tiles: built-in 8 rows for dense shapes and 4 for
+    crosses, settable to 4 or 8 (dense) or back to automatic; crosses have no
+    8-row batched kernel and 3D stencils no batched path."""
+    dense = F.fd_weights_set(2, "square", 3, oracle_weights(2, "specls", "square", 3, 0.3))
+    cross = F.fd_weights_set(2, "cross", 3, oracle_weights(2, "taylor", "cross", 3))
+    assert F.fd_get_batch_tile(dense) == 8 and F.fd_get_batch_tile(cross) == 4
+    F.fd_set_batch_tile(dense, 4)
+    assert F.fd_get_batch_tile(dense) == 4
+    F.fd_set_batch_tile(dense, 0)
+    assert F.fd_get_batch_tile(dense) == 8
+    for sid, rows, code in [(dense, 2, F.FD_EINVAL), (cross, 8, F.FD_EUNSUPPORTED), (10 ** 6, 4, F.FD_EINVAL)]:
+        with pytest.raises(F.FdError) as e:
+            F.fd_set_batch_tile(sid, rows)
+        assert e.value.code == code
+    vol = F.fd_weights_set(3, "cross", 2, oracle_weights(3, "taylor", "cross", 2))
+    with pytest.raises(F.FdError) as e:
+        F.fd_set_batch_tile(vol, 4)
+    assert e.value.code == F.FD_EUNSUPPORTED
 
 
 def _ws_bytes(F, shape, mode, K, sid, wav):

@@ -209,10 +209,11 @@ def test_large_variant_group_equals_shot_after_shot(F, nshots):
 
 def test_batched_dense_groups_at_eight_rows(F):
     """The forward steps of dense-stencil groups run batched on 64 x 32 tiles
-    whatever the stencils' own tile setting: traces bitwise equal to the shots
-    one after another with the dense stencils at 4 and at 8 rows per thread;
-    the adjoint of such a batch (whose groups keep 4 rows) equal to the
-    per-shot adjoint."""
+    by default, whatever the stencils' own tile setting: traces bitwise equal
+    to the shots one after another with the dense stencils at 4 and at 8 rows
+    per thread, and to the batch with the dense groups' batched tile set to 4
+    rows (fd_set_batch_tile); the adjoint of such a batch (whose groups keep 4
+    rows) equal to the per-shot adjoint."""
     nt = 120
     w = configs.ragged(nshots=12, nt=nt)
     model = configs.ragged_model(w)
@@ -235,6 +236,17 @@ def test_batched_dense_groups_at_eight_rows(F):
         torch.cuda.synchronize()
         for a, s in zip(batched, shots):
             assert torch.equal(a, s.traces), rows
+    for sid in dense:
+        assert F.fd_get_batch_tile(sid) == 8
+        F.fd_set_batch_tile(sid, 4)
+    for s in shots:
+        s.traces.zero_()
+    F.fd_forward(grid, vel, shots)
+    torch.cuda.synchronize()
+    for a, s in zip(batched, shots):
+        assert torch.equal(a, s.traces), "batched tile 4"
+    for sid in dense:
+        F.fd_set_batch_tile(sid, 0)
     rng = np.random.default_rng(3)
     for s in shots:
         s.trace_adj = torch.tensor(rng.standard_normal(tuple(s.traces.shape)).astype(np.float32), device=DEV)

@@ -279,3 +279,37 @@ def test_marching_cross_kernel(M, zchunk, shape):
     assert np.array_equal(tr1, tr4) and np.array_equal(u1, u4) and np.array_equal(g1, g4)
     ref = oracle_traces(2, "cross", M, wo, vel, h, dt, nt, nb, eta, src, wav, rec)
     assert rel_l2(tr1, ref["traces"]) <= 1e-5
+
+
+def test_marching_kernel_at_the_study_reference_size():
+    """The z-marching cross kernel as the refined-reference study runs it:
+    the 6401^2 homogeneous reference grid (h / 16, dt / 16, 640-cell sponge),
+    SpatTE (Taylor) cross M=8, chunks of 16 rows, 60 steps from the central
+    source; the final state against the oracle on the 961^2 box that holds
+    the field's support (placed by full-grid coordinates), exactly zero
+    outside it, to 1e-5."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2606_04882_amd import fdwave as F
+    from oracle import stepper as S
+    from tests.fdcase import oracle_weights, q32, rel_l2, rounded_stencil, v32
+    w = configs.study_homogeneous(refine=16)
+    nt, M = 60, 8
+    vel = configs.study_model(w)
+    wo = oracle_weights(2, "taylor", "cross", M)
+    sid = F.fd_weights_set(2, "cross", M, wo)
+    F.fd_set_tile(sid, 1, 16)
+    wav = synth.ricker(nt, w.dt, w.f0)
+    out = gpu_run(F, vel, w.h, w.dt, nt, w.nb, w.eta_max, sid, w.src, wav, None, vmax=w.c_max, final=True)
+    sx, sz = w.src
+    r = nt * M
+    box = (slice(sz - r, sz + r + 1), slice(sx - r, sx + r + 1))
+    crop = np.ascontiguousarray(vel[box])
+    ref = S.forward(rounded_stencil(2, "cross", M, wo), v32(crop, w.dt, w.h), w.dt, nt, w.nb, w.eta_max,
+                    (sx - box[1].start, sz - box[0].start), q32(wav, w.dt, w.h, 2), None,
+                    crop=((box[1].start, box[0].start), (w.shape[1], w.shape[0])))
+    cur = out["cur"]
+    assert rel_l2(cur[box], ref["cur"]) <= 1e-5
+    outside = cur.copy()
+    outside[box] = 0.0
+    assert not np.any(outside)

@@ -1198,8 +1198,15 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(M <= 2 ?
                 bload_lds<UNIT>(r, buf + ((threadIdx.x & ~63) + NTH * k) * UNIT, doff[k]);
         }
     };
-    float dd[4], vv[4];
-    auto fetch_dv = [&]() {   // d, v of output zdv, then advance
+    // AHEAD (M = 4, 5, where eight more registers leave the occupancy as it
+    // is): d, v of an output are fetched one plane ahead, and the next plane's
+    // LDS load is issued once this plane's LDS reads are done.  The compiler
+    // makes every LDS read wait for LDS-flag loads still in flight, so a load
+    // issued before the reads is waited for at once; issued after them, it
+    // and the d, v loads have the rest of the plane's work to land.
+    constexpr bool AHEAD = M == 4 || M == 5;
+    float dv[AHEAD ? 2 : 1][2][4];   // [slot][d, v][point]
+    auto fetch_dv = [&](float (&dd)[4], float (&vv)[4]) {   // d, v of output zdv, then advance
         const bool in = zdv >= zs && zdv < ze;
         const Rsrc rd = plane_rsrc_at(ad, in ? pbytes : 0u);
         const Rsrc rv = plane_rsrc_at(av, in ? vbytes : 0u);
@@ -1260,6 +1267,7 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(M <= 2 ?
         pending = false;
     };
     load_plane_lds(lds);
+    if constexpr (AHEAD) fetch_dv(dv[0][0], dv[0][1]);   // output z_begin - M
     auto body = [&](auto ph, int zp) {
         constexpr int PH = decltype(ph)::value;
         float* cur = lds + (PH & 1) * PLANE;
@@ -1268,11 +1276,22 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(M <= 2 ?
         // thread is done with the other buffer
         __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
         __syncthreads();
-        if (zp + 1 < z_end) load_plane_lds(lds + ((PH & 1) ^ 1) * PLANE);
-        fetch_dv();   // d, v of output zp - M, used at the end of this iteration
+        float* nxt = lds + ((PH & 1) ^ 1) * PLANE;
+        constexpr int DV = AHEAD ? PH & 1 : 0;   // slot of output zp - M
+        if constexpr (AHEAD) {
+            fetch_dv(dv[DV ^ 1][0], dv[DV ^ 1][1]);   // output zp + 1 - M
+        } else {
+            if (zp + 1 < z_end) load_plane_lds(nxt);
+            fetch_dv(dv[0][0], dv[0][1]);   // output zp - M
+        }
         flush();
         float S[NG][4], uc[4];
         ball_rows_from<M, MP, LW, Q, PH, 0, NG>(cur + (ty + M) * LW + 4 * tq, S, uc, acc, p.w);
+        if constexpr (AHEAD) {
+            if (zp + 1 < z_end) load_plane_lds(nxt);
+        }
+        const float (&dd)[4] = dv[DV][0];
+        const float (&vv)[4] = dv[DV][1];
         // z differences: output zp - m and output zp
         cfor<1, M + 1>([&](auto mc) {
             constexpr int m = decltype(mc)::value;

@@ -1018,33 +1018,48 @@ __device__ __forceinline__ void bload_lds(Rsrc r, float* buf, unsigned off) {
     else __builtin_amdgcn_raw_ptr_buffer_load_lds(r, dst, 4, off, 0, 0, 0);
 }
 
-// In-plane sums of row dy (|dy| = R) into the group sums S of the thread's
-// four points; `row` is the thread's first LDS column of that row.  The first
-// contribution to group (a, b) comes from row -b (rows are taken in the order
-// 0, -1, +1, -2, +2, ...) and is assigned.
-template <int M, int MP, int R, int DY, int NG>
-__device__ __forceinline__ void ball_row(const float* row, float (&S)[NG][4], float (&uc)[4]) {
+// In-plane sums of rows -R and +R (row 0 alone for R = 0) into the group
+// sums S of the thread's four points; rm and rp are the thread's first LDS
+// columns of the two rows.  For R >= 1 the two rows are added column by
+// column first (over the columns the rows use), then the column sums are
+// paired at x distances 1 .. M - R.  The first contribution to group (a, b),
+// a >= b, comes from R = b and is assigned.
+template <int M, int MP, int R, int NG>
+__device__ __forceinline__ void ball_row_pair(const float* rm, const float* rp, float (&S)[NG][4],
+                                              float (&uc)[4]) {
     constexpr int lo = MP - (M - R), hi = MP + 3 + (M - R);
     constexpr int k0 = lo / 4, k1 = hi / 4;
     float win[4 * (k1 + 1)];
     cfor<k0, k1 + 1>([&](auto kc) {
         constexpr int k = decltype(kc)::value;
-        const float4 v = reinterpret_cast<const float4*>(__builtin_assume_aligned(row, 16))[k];
-        win[4 * k] = v.x;
-        win[4 * k + 1] = v.y;
-        win[4 * k + 2] = v.z;
-        win[4 * k + 3] = v.w;
+        const float4 a = reinterpret_cast<const float4*>(__builtin_assume_aligned(rm, 16))[k];
+        if constexpr (R == 0) {
+            win[4 * k] = a.x;
+            win[4 * k + 1] = a.y;
+            win[4 * k + 2] = a.z;
+            win[4 * k + 3] = a.w;
+        } else {
+            const float4 b = reinterpret_cast<const float4*>(__builtin_assume_aligned(rp, 16))[k];
+            win[4 * k] = a.x + b.x;
+            win[4 * k + 1] = a.y + b.y;
+            win[4 * k + 2] = a.z + b.z;
+            win[4 * k + 3] = a.w + b.w;
+            // each 16-byte piece summed before the next pair of reads
+#pragma unroll
+            for (int j = 4 * k; j < 4 * k + 4; ++j)
+                if (j >= lo && j <= hi) __asm__ volatile("" : "+v"(win[j])::"memory");
+        }
     });
     cfor<0, 4>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
         if constexpr (R == 0) uc[i] = win[MP + i];
-        if constexpr (R > 0) S[ball_gidx(R, 0)][i] += win[MP + i];
+        else S[ball_gidx(R, 0)][i] += win[MP + i];
         cfor<1, M - R + 1>([&](auto kc) {
             constexpr int k = decltype(kc)::value;
             constexpr int a = k > R ? k : R, b = k > R ? R : k;
             constexpr int g = ball_gidx(a, b);
             const float pr = win[MP + i - k] + win[MP + i + k];
-            if constexpr (DY == -b) S[g][i] = pr;
+            if constexpr (b == R) S[g][i] = pr;
             else S[g][i] += pr;
         });
     });
@@ -1088,12 +1103,10 @@ __device__ __forceinline__ void ball_rows_from(const float* base, float (&S)[NG]
                 for (int i = 0; i < 4; ++i) __asm__ volatile("" : "+v"(S[g][i])::"memory");
         };
         if constexpr (R == 0) {
-            ball_row<M, MP, 0, 0, NG>(base, S, uc);
+            ball_row_pair<M, MP, 0, NG>(base, base, S, uc);
             fence();
         } else {
-            ball_row<M, MP, R, -R, NG>(base - R * LW, S, uc);
-            fence();
-            ball_row<M, MP, R, R, NG>(base + R * LW, S, uc);
+            ball_row_pair<M, MP, R, NG>(base - R * LW, base + R * LW, S, uc);
             fence();
             cfor<0, (R < M - R ? R : M - R) + 1>([&](auto bc) {
                 ball_scatter<M, Q, PH, R, decltype(bc)::value, NG>(acc, S, uc, W);
@@ -1203,7 +1216,10 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(M <= 2 ?
     // LDS load is issued once this plane's LDS reads are done.  The compiler
     // makes every LDS read wait for LDS-flag loads still in flight, so a load
     // issued before the reads is waited for at once; issued after them, it
-    // and the d, v loads have the rest of the plane's work to land.
+    // and the d, v loads have the rest of the plane's work to land.  The
+    // update is then stored at once, on every plane (range-checked to nothing
+    // outside the chunk), so that the wait before the next barrier can leave
+    // exactly those stores in flight.
     constexpr bool AHEAD = M == 4 || M == 5;
     float dv[AHEAD ? 2 : 1][2][4];   // [slot][d, v][point]
     auto fetch_dv = [&](float (&dd)[4], float (&vv)[4]) {   // d, v of output zdv, then advance
@@ -1242,7 +1258,8 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(M <= 2 ?
     for (int k = 0; k < Q; ++k)
 #pragma unroll
         for (int i = 0; i < 4; ++i) acc[k][i] = 0.f;
-    // the finished update of the previous plane, stored after the next barrier
+    // the finished update of a plane: stored at once (AHEAD), else after the
+    // next barrier
     float pd[4], pu[4];
     bool pending = false;
     Rsrc pst_d = plane_rsrc_at(0, 0u), pst_u = plane_rsrc_at(0, 0u);
@@ -1274,7 +1291,13 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(M <= 2 ?
         // this wave's loads into LDS (and every other memory operation it has
         // in flight) complete, then the barrier: plane zp is in cur, and every
         // thread is done with the other buffer
-        __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
+        if constexpr (AHEAD) {
+            // the stores of the previous plane, issued last, may stay in flight
+            constexpr int NS = VEC ? 2 : 8;
+            __builtin_amdgcn_s_waitcnt(0x0F70 | NS);   // vmcnt(NS)
+        } else {
+            __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
+        }
         __syncthreads();
         float* nxt = lds + ((PH & 1) ^ 1) * PLANE;
         constexpr int DV = AHEAD ? PH & 1 : 0;   // slot of output zp - M
@@ -1284,7 +1307,7 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(M <= 2 ?
             if (zp + 1 < z_end) load_plane_lds(nxt);
             fetch_dv(dv[0][0], dv[0][1]);   // output zp - M
         }
-        flush();
+        if constexpr (!AHEAD) flush();
         float S[NG][4], uc[4];
         ball_rows_from<M, MP, LW, Q, PH, 0, NG>(cur + (ty + M) * LW + 4 * tq, S, uc, acc, p.w);
         if constexpr (AHEAD) {
@@ -1306,7 +1329,8 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(M <= 2 ?
         // output o = zp - M is complete
         constexpr int QO = PH % M, AO = (PH + M) % Q;
         const int o = zp - M;
-        if (o >= zs && o < ze) {
+        const bool oin = o >= zs && o < ze;
+        if (AHEAD || oin) {
             const int dzb = nb > 0 ? band_depth(o, p.nz, nb) : 0;
             const float rz = dzb * p.sp.inv_nb;
 #pragma unroll
@@ -1317,10 +1341,11 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(M <= 2 ?
                 pd[i] = d;
                 pu[i] = q[QO][i] + d;
             }
-            pst_d = plane_rsrc_at(adn, pbytes);
-            pst_u = plane_rsrc_at(aun, pbytes);
+            pst_d = plane_rsrc_at(adn, oin ? pbytes : 0u);
+            pst_u = plane_rsrc_at(aun, oin ? pbytes : 0u);
             pending = true;
         }
+        if constexpr (AHEAD) flush();   // every plane, in or out of the chunk: a fixed count
         adn += pstep;
         aun += pstep;
 #pragma unroll

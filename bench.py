@@ -79,7 +79,8 @@ def parse():
     ap.add_argument("--no-extras", action="store_true", help="skip the earlier lines (2D, ragged)")
     ap.add_argument("--all", action="store_true", help="also the 3D FWI gradient and study lines")
     ap.add_argument("--no-tune", action="store_true", help="skip the tile autotuner")
-    ap.add_argument("--only", choices=["vol3d", "2d", "ragged", "fwi", "fwi3d", "study", "copy"], default=None,
+    ap.add_argument("--only", choices=["vol3d", "2d", "ragged", "fwi", "fwi3d", "study", "copy", "cpu"],
+                    default=None,
                     help="run one workload alone (for profiling); no value line")
     ap.add_argument("--stencil", default=None,
                     help="--only 2d / vol3d: run this stencil alone (e.g. specls-square-M8)")
@@ -131,6 +132,9 @@ def main():
             res = fwi3d_bench(torch, F, design, configs, dev, args.nt)
         elif args.only == "ragged":
             res = ragged_bench(torch, F, design, configs, dev, args.ragged_nt)
+        elif args.only == "cpu":      # the oracle with every host thread, then with one
+            res = {"all_threads": cpu_baseline_3d(configs, args.n3d, args.cpu_seconds),
+                   "one_thread": cpu_baseline_3d(configs, args.n3d, args.cpu_seconds, threads=1)}
         else:
             res = fwi_bench(torch, F, design, configs, dev)
         emit({"only": args.only, "result": res})
@@ -585,20 +589,35 @@ def _cpu_model() -> str:
     return "unknown"
 
 
-def cpu_baseline_3d(configs, n3d, budget_s):
+def cpu_baseline_3d(configs, n3d, budget_s, threads=0):
     """The FP64 oracle (plain C, OpenMP over the slowest axis) on this host:
     each of the three stencils advanced a few steps on the full 512^3 model
     with every host thread.  A one-step call is timed first; when the
     stencil's share of budget_s (a third) leaves room, a call of as many
     steps as fit in the rest (at most 19) is timed instead.  The rate
     counts every second of the timed call (its set-up included), so it
-    does not overstate the oracle."""
-    from fractions import Fraction
+    does not overstate the oracle.  threads > 0: that many OpenMP threads
+    instead of every host thread."""
     from oracle import stepper as S
-    from oracle import weights as W
     S.build(force=False)
     gomp = _gomp()
     cores = int(gomp.omp_get_max_threads()) if gomp else int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    if threads > 0:
+        if gomp is None:
+            raise RuntimeError("libgomp not found: cannot set the oracle's thread count")
+        gomp.omp_set_num_threads(threads)
+        restore, cores = cores, threads
+    try:
+        return _cpu_sample(configs, n3d, budget_s, cores)
+    finally:
+        if threads > 0:
+            gomp.omp_set_num_threads(restore)
+
+
+def _cpu_sample(configs, n3d, budget_s, cores):
+    from fractions import Fraction
+    from oracle import stepper as S
+    from oracle import weights as W
     w = configs.volume_3d(n=n3d, nt=20)
     v = S.v_from_c(configs.volume_3d_model(w).astype(np.float64), w.dt, w.h)
     q = S.source_term(w.wavelet(), w.dt, w.h, 3)

@@ -166,6 +166,31 @@ def test_3d_ball_z_chunks(F, M, rows, zchunk, nx):
     assert rel_l2(gpu["cur"], ref["cur"]) <= 1e-5
 
 
+@pytest.mark.parametrize("dims", [(1, 1, 1), (3, 5, 7), (9, 2, 4), (2, 9, 64), (70, 1, 3)])
+@pytest.mark.parametrize("scheme,shape,M,rows", [("taylor", "cross", 8, 2), ("taylor", "cross", 4, 1),
+                                                 ("dispte", "rhombus", 4, 1), ("dispte", "rhombus", 6, 1)])
+def test_3d_degenerate_windows(F, dims, scheme, shape, M, rows):
+    """3D windows smaller than the stencil radius in one, two or all three
+    axes (every neighbour may fall off the grid, zeros beyond the window),
+    z-chunks of 8 planes: cross kernel and L1-ball kernel (nx = 4 and 64
+    take its 16-byte path) against the oracle, traces and final field."""
+    nz, ny, nx = dims
+    h, nt = 10.0, 40
+    vel = np.full(dims, 2000.0, np.float32)
+    dt = 0.25 * h / 2000.0
+    wo = oracle_weights(3, scheme, shape, M, 2000.0 * dt / h)
+    sid = F.fd_weights_set(3, shape, M, wo)
+    F.fd_set_tile(sid, rows, 8)
+    wav = synth.ricker(nt, dt, 30.0)
+    rec = np.array([[nx - 1, ny - 1, nz - 1], [0, 0, 0], [nx // 2, ny // 2, nz // 2]])
+    src = (nx // 2, ny // 2, nz // 2)
+    print(f"[case] 3D window {dims}, {scheme} {shape} M={M} rows={rows}", flush=True)
+    gpu = run3(F, vel, h, dt, nt, 0, 0.0, sid, src, wav, rec, final=True)
+    ref = oracle_traces(3, shape, M, wo, vel, h, dt, nt, 0, 0.0, src, wav, rec)
+    check_traces(gpu["traces"], ref["traces"])
+    assert rel_l2(gpu["cur"], ref["cur"]) <= 1e-5
+
+
 def test_3d_time_block_is_one_step(F):
     sid = F.fd_weights_set(3, "cross", 4, oracle_weights(3, "taylor", "cross", 4))
     assert F.fd_get_time_block(sid) == 1

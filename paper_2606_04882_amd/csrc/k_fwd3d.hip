@@ -961,8 +961,10 @@ __global__ __launch_bounds__(kBlock3) void k_fwd3d_gen(StepArgs p) {
 // (cells off the grid, planes off the grid) write zeros into LDS, as the
 // stencil reads them.  A thread owns four consecutive points of a row
 // (16 threads per 64-point row), so a row window of its points' in-plane
-// neighbours is 1 + MP/2 aligned 16-byte LDS reads, and per point it keeps
-// 2M partial sums and M queued values of u.  The z loop is unrolled by the
+// neighbours is 1 + MP/2 aligned 16-byte LDS reads (rows -R and +R are
+// added column by column before their x pairs are formed, the column sums
+// shared by the four points), and per point it keeps 2M partial sums and
+// M queued values of u.  The z loop is unrolled by the
 // period 2M, so partial sums, queue entries and the LDS buffer are
 // compile-time slots.  Each z chunk runs M planes before and after its own.
 __host__ __device__ constexpr int ball_ngroups(int M) {

@@ -79,7 +79,7 @@ def parse():
     ap.add_argument("--no-extras", action="store_true", help="skip the earlier lines (2D, ragged)")
     ap.add_argument("--all", action="store_true", help="also the 3D FWI gradient and study lines")
     ap.add_argument("--no-tune", action="store_true", help="skip the tile autotuner")
-    ap.add_argument("--only", choices=["vol3d", "2d", "ragged", "fwi", "fwi3d", "study", "copy", "cpu"],
+    ap.add_argument("--only", choices=["vol3d", "2d", "ragged", "fwi", "fwi3d", "study", "copy", "stream", "cpu"],
                     default=None,
                     help="run one workload alone (for profiling); no value line")
     ap.add_argument("--stencil", default=None,
@@ -122,6 +122,8 @@ def main():
             torch.cuda.synchronize()
             ms = _event_time(torch, lambda: b.copy_(a), reps=5)
             res = {"copy_bytes": 4 * n, "ms": ms, "gbs_read_plus_write": 8 * n / (ms * 1e-3) / 1e9}
+        elif args.only == "stream":
+            res = stream_reference(torch, dev, args.n3d)
         elif args.only == "vol3d":
             res = vol3d_only(torch, F, design, configs, dev, args)
         elif args.only == "2d":
@@ -321,6 +323,28 @@ def _event_time(torch, fn, reps=1):
     e1.record(s)
     torch.cuda.synchronize()
     return e0.elapsed_time(e1) / reps
+
+
+def stream_reference(torch, dev, n3d):
+    """Reference streaming rates on this GPU from PyTorch's own elementwise
+    kernels over 512^3-point FP32 fields (no stencil, no halo): a copy
+    (1 read, 1 write), an add (2 reads, 1 write) and an addcmul (3 reads,
+    1 write), each as bytes moved per second, for comparison with the
+    stencil kernels' 3 reads and 2 writes per update."""
+    n = n3d ** 3
+    a, b, c = (torch.rand(n, device=dev) for _ in range(3))
+    out = torch.empty(n, device=dev)
+    cases = {"copy_1r1w": (lambda: out.copy_(a), 2),
+             "add_2r1w": (lambda: torch.add(a, b, out=out), 3),
+             "addcmul_3r1w": (lambda: torch.addcmul(a, b, c, out=out), 4)}
+    res = {"points": n}
+    for name, (fn, nfields) in cases.items():
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        ms = _event_time(torch, fn, reps=20)
+        res[name] = {"us": round(ms * 1e3, 2), "gbs": round(nfields * 4 * n / (ms * 1e-3) / 1e9, 1)}
+    return res
 
 
 # ---------------------------------------------------------------------------
